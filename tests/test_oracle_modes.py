@@ -1,0 +1,152 @@
+"""Oracle pins against analytic eigenfrequencies and the spectrum extractor.
+
+* annulus (2-D polar) and hollow cylinder (3-D) normal modes: the scheme must
+  converge at second order (Sec. IV.A convergence study) to the continuum
+  frequencies c k, with k from the Bessel cross-product equations of the
+  Laplacian on an annulus.  Bounce-back walls are zero-flux walls, so the
+  radial condition is dP/dr = 0 (zeros built from J'_m, Y'_m); fixed walls
+  give P = 0.  m = 0 modes pin the sqrt(g) factor of the Christoffel force,
+  m >= 1 and z-dependent modes pin the sign of the gradient force.
+* the frequency extractor recovers known sinusoids;
+* the zeros the paper prints for the pipe's wall condition (golden file).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq, minimize_scalar
+from scipy.special import jv, jvp, yv, yvp
+
+import oracle
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def first_root(fun, lo=0.5, hi=40.0, step=0.01):
+    x = lo
+    f0 = fun(x)
+    while x < hi:
+        x2 = x + step
+        f1 = fun(x2)
+        if f0 == 0.0 or f0 * f1 < 0:
+            return brentq(fun, x, x2, xtol=1e-14)
+        x, f0 = x2, f1
+    raise RuntimeError("no root")
+
+
+def annulus_k(m, a, b, outer):
+    if outer == "bounceback":
+        fun = lambda k: jvp(m, k * a) * yvp(m, k * b) - jvp(m, k * b) * yvp(m, k * a)
+    else:
+        fun = lambda k: jvp(m, k * a) * yv(m, k * b) - jv(m, k * b) * yvp(m, k * a)
+    return first_root(fun)
+
+
+def radial_profile(m, k, a, r):
+    return jv(m, k * r) * yvp(m, k * a) - yv(m, k * r) * jvp(m, k * a)
+
+
+def measure_omega(trace, guess):
+    """Least-squares frequency of traces assumed to hold one oscillation plus
+    the stationary and period-2 components of the scheme."""
+    t = np.arange(trace.shape[0])
+
+    def resid(om):
+        B = np.stack([np.ones_like(t, dtype=float), (-1.0) ** t, np.cos(om * t), np.sin(om * t)], axis=1)
+        coef, *_ = np.linalg.lstsq(B, trace, rcond=None)
+        return float(((trace - B @ coef) ** 2).sum())
+
+    res = minimize_scalar(resid, bounds=(0.9 * guess, 1.1 * guess), method="bounded",
+                          options={"xatol": 1e-13 * guess})
+    return res.x
+
+
+def bound(o):
+    tot = np.zeros(o.N)
+    for a in range(o.dim):
+        m = o.Mhat[a]
+        tot += np.where(m <= 1.0, 4.0, (1.0 + m) ** 2 / np.maximum(m, 1e-300))
+    return 2.0 / math.sqrt(tot.max())
+
+
+def annulus_error(nr, m, outer, a=0.3, b=1.0, periods=8):
+    geom = dict(kind="polar2d", dim=2, n=(nr, 3 * nr), qmin=(a, 0.0), qmax=(b, 2 * math.pi),
+                bc_lo=("bounceback", "periodic"), bc_hi=(outer, "periodic"), h_ref=(b - a) / nr, c=0.3,
+                damp=1.0, params=())
+    c = 0.8 * bound(oracle.Oracle(geom))
+    geom["c"] = c
+    o = oracle.Oracle(geom)
+    k = annulus_k(m, a, b, outer)
+    r, th = W.node_grid(geom)
+    P0 = radial_profile(m, k, a, r) * np.cos(m * th)
+    f = o.init(P0)
+    om_c = k * c * geom["h_ref"]
+    T = int(periods * 2 * math.pi / om_c)
+    probes = [i + nr * j for i in (1, nr // 3, nr // 2) for j in (0, 1)]
+    _, trace = o.run(f, T, probes)
+    om = measure_omega(trace, om_c)
+    return om / om_c - 1.0
+
+
+@pytest.mark.parametrize("m,outer", [(0, "bounceback"), (1, "bounceback"), (2, "bounceback"), (1, "fixed")])
+def test_annulus_modes_converge_second_order(m, outer):
+    e1 = annulus_error(16, m, outer)
+    e2 = annulus_error(32, m, outer)
+    e3 = annulus_error(64, m, outer)
+    assert abs(e3) < 2e-3, (e1, e2, e3)
+    r1, r2 = e1 / e2, e2 / e3
+    assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, (e1, e2, e3)
+
+
+def cylinder_error(nr, m=1, nz_mode=1, a=0.3, b=1.0, L=1.0, periods=6):
+    n = (nr, 3 * nr, int(round(nr * 10 / 12)))
+    geom = dict(kind="cylinder", dim=3, n=n, qmin=(a, 0.0, 0.0), qmax=(b, 2 * math.pi, L),
+                bc_lo=("bounceback", "periodic", "bounceback"), bc_hi=("bounceback", "periodic", "bounceback"),
+                h_ref=(b - a) / nr, c=0.3, damp=1.0, params=())
+    c = 0.8 * bound(oracle.Oracle(geom))
+    geom["c"] = c
+    o = oracle.Oracle(geom)
+    assert abs(o.Mhat[2]).max() > 0.3  # h_z != h_r: the z gradient force is active
+    kr = annulus_k(m, a, b, "bounceback")
+    k = math.hypot(kr, nz_mode * math.pi / L)
+    r, th, z = W.node_grid(geom)
+    P0 = radial_profile(m, kr, a, r) * np.cos(m * th) * np.cos(nz_mode * math.pi * z / L)
+    f = o.init(P0)
+    om_c = k * c * geom["h_ref"]
+    T = int(periods * 2 * math.pi / om_c)
+    probes = [i + n[0] * (j + n[1] * kz) for i in (1, nr // 2) for j in (0, 1) for kz in (0, n[2] // 3)]
+    _, trace = o.run(f, T, probes)
+    return measure_omega(trace, om_c) / om_c - 1.0
+
+
+def test_hollow_cylinder_mode_with_axial_variation():
+    e1 = cylinder_error(12)
+    e2 = cylinder_error(24)
+    assert abs(e2) < 1e-2 and 3.0 < e1 / e2 < 5.5, (e1, e2)
+
+
+def test_extractor_recovers_sinusoids():
+    rng = np.random.default_rng(11)
+    for T in (700, 4000, 20000):
+        fs = np.array([0.013, 0.041, 0.097, 0.151])
+        t = np.arange(T)
+        x = sum(a * np.cos(2 * math.pi * f * t + rng.uniform(0, 6)) for f, a in zip(fs, (1.0, 0.5, 0.8, 0.3)))
+        x = np.stack([x + 0.2, 0.5 * x - 1.0], axis=1)
+        est, pw = oracle.modes(x, 4)
+        nfft = oracle.modes.__globals__["nfft_for"](T)
+        assert np.abs(est - fs).max() * nfft < 2e-3
+        assert np.all(np.diff(est) > 0)
+    # fewer peaks than requested are NaN-padded
+    est, _ = oracle.modes(np.cos(0.3 * np.arange(1000))[:, None], 3)
+    assert abs(est[0] - 0.3 / (2 * math.pi)) < 1e-4 and np.isnan(est[1:]).all()
+
+
+def test_paper_robin_zero_table():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_pipe_robin_zeros.txt")) if not l.startswith("#")]
+    printed = [float(v) for _, v in rows]
+    fun = lambda x: jv(0, x) - x * jv(1, x)  # (m+1) J_m - x J_{m+1}, m = 0
+    zeros = [brentq(fun, lo, lo + 1.5) for lo in (0.5, 3.5, 6.5)]
+    assert abs(zeros[0] - printed[0]) < 5e-4 and abs(zeros[1] - printed[1]) < 5e-4
+    assert abs(zeros[2] - 7.1558) < 1e-3 and abs(zeros[2] - printed[2]) > 1e-2

@@ -1,0 +1,231 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the
+benchmark.
+
+This module only describes inputs: a geometry description (a plain dict that
+both the HIP library binding and the CPU oracle translate into their own
+structs), the initial pressure field P0, probe positions and step counts.  It
+contains none of the method's arithmetic (no metric, no coefficients, no
+collision or streaming).  Node positions follow the placement used by the
+method: a periodic axis has nodes at qmin + i h, a walled axis at
+qmin + (i + 1/2) h with h = (qmax - qmin) / n.
+
+The paper uses no datasets; the shapes below stand in for its cylinder, horn
+and torus experiments (Sec. IV) at the sizes of the benchmark configurations.
+
+Lattice wave speeds ``c`` are fixed numbers chosen below the stability bound
+of each full-size grid (0.9 of it, rounded down so that c^2 is a multiple of
+2^-16, which makes c^2 exact in float32 as well as float64).  Coarser grids of
+the same geometry (``scale`` > 1) have a larger bound, so the same c is safe.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+SEED_BASE = 170501801
+
+# c^2 values (multiples of 2^-16) per configuration; see module docstring.
+C2 = {
+    0: 17545,  # polar disk 64 x 64: bound 0.5749
+    1: 12440,  # cylinder 128 x 128 x 256: bound 0.4841
+    2: 12465,  # horn 128 x 128 x 512: bound 0.4846
+    3: 946,    # torus 96 x 256 x 512: bound 0.1335
+}
+
+
+def _c(idx: int) -> float:
+    v = C2[idx]
+    if v is None:
+        raise RuntimeError("wave speed for configuration %d not set" % idx)
+    return math.sqrt(v / 65536.0)
+
+
+# ---------------------------------------------------------------------------
+# geometry helpers (input side only)
+# ---------------------------------------------------------------------------
+
+def shape_of(geom: dict):
+    return tuple(int(v) for v in geom["n"][: geom["dim"]])
+
+
+def num_nodes(geom: dict) -> int:
+    return int(np.prod(shape_of(geom)))
+
+
+def axis_coords(geom: dict, a: int) -> np.ndarray:
+    n = int(geom["n"][a])
+    lo, hi = float(geom["qmin"][a]), float(geom["qmax"][a])
+    h = (hi - lo) / n
+    i = np.arange(n, dtype=np.float64)
+    if geom["bc_lo"][a] == "periodic":
+        return lo + i * h
+    return lo + (i + 0.5) * h
+
+
+def node_grid(geom: dict):
+    """Generalised coordinates of every node, each as an array of the grid
+    shape in memory order (axis 0 fastest), flattened."""
+    d = geom["dim"]
+    axes = [axis_coords(geom, a) for a in range(d)]
+    mesh = np.meshgrid(*axes[::-1], indexing="ij")  # slowest axis first
+    return [m.reshape(-1) for m in mesh[::-1]]
+
+
+def embed(geom: dict, q):
+    """Euclidean position of points given in generalised coordinates."""
+    kind = geom["kind"]
+    if kind == "box":
+        return np.stack(q, axis=-1)
+    if kind == "polar2d":
+        r, t = q
+        return np.stack([r * np.cos(t), r * np.sin(t)], axis=-1)
+    if kind == "cylinder":
+        r, t, z = q
+        return np.stack([r * np.cos(t), r * np.sin(t), z], axis=-1)
+    if kind == "horn":
+        a, b, k = geom["params"][:3]
+        r, t, z = q
+        s = a + b * np.exp(k * z)
+        return np.stack([r * s * np.cos(t), r * s * np.sin(t), z], axis=-1)
+    if kind == "bessel_horn":
+        lam, zmax = geom["params"][:2]
+        r, t, z = q
+        s = (zmax - z) ** (-lam)
+        return np.stack([r * s * np.cos(t), r * s * np.sin(t), z], axis=-1)
+    if kind == "torus":
+        R = geom["params"][0]
+        p, t, f = q
+        u = R + p * np.cos(f)
+        return np.stack([u * np.cos(t), u * np.sin(t), p * np.sin(f)], axis=-1)
+    raise ValueError(kind)
+
+
+def gaussian_pulses(geom: dict, centers: np.ndarray, amps, sigma: float) -> np.ndarray:
+    """P0 = sum_j amp_j exp(-|X - X_j|^2 / (2 sigma^2)), Euclidean distance."""
+    X = embed(geom, node_grid(geom))
+    P0 = np.zeros(X.shape[0])
+    for c, a in zip(np.atleast_2d(centers), np.atleast_1d(amps)):
+        d2 = ((X - c[None, :]) ** 2).sum(axis=1)
+        P0 += a * np.exp(-d2 / (2.0 * sigma * sigma))
+    return P0
+
+
+def node_position(geom: dict, node: int) -> np.ndarray:
+    shape = shape_of(geom)
+    idx = []
+    rem = int(node)
+    for a in range(geom["dim"]):
+        idx.append(rem % shape[a])
+        rem //= shape[a]
+    q = [np.array([axis_coords(geom, a)[idx[a]]]) for a in range(geom["dim"])]
+    return embed(geom, q)[0]
+
+
+def smoothed_noise(geom: dict, rng: np.random.Generator, sigma_cells: float) -> np.ndarray:
+    """Uniform[-1, 1] per node, smoothed by a separable Gaussian of width
+    sigma_cells (truncated at 4 sigma): periodic axes wrap, walled axes
+    reflect."""
+    from scipy.ndimage import gaussian_filter1d
+
+    shape = shape_of(geom)
+    u = rng.uniform(-1.0, 1.0, size=shape[::-1])  # slowest axis first
+    for a in range(geom["dim"]):
+        arr_axis = geom["dim"] - 1 - a
+        mode = "wrap" if geom["bc_lo"][a] == "periodic" else "reflect"
+        u = gaussian_filter1d(u, sigma_cells, axis=arr_axis, mode=mode, truncate=4.0)
+    return np.ascontiguousarray(u).reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# configurations
+# ---------------------------------------------------------------------------
+
+def _scaled(n, scale):
+    return tuple(max(1, int(v) // int(scale)) for v in n)
+
+
+def polar_disk(scale: int = 1, c: float | None = None) -> dict:
+    """2-D polar (r, theta) disk, r in [0.05, 1], fixed (P = 0) outer wall,
+    bounce-back inner wall, theta periodic; 64 x 64 nodes."""
+    n = _scaled((64, 64), scale)
+    return dict(kind="polar2d", dim=2, n=n, qmin=(0.05, 0.0), qmax=(1.0, TWO_PI),
+                bc_lo=("bounceback", "periodic"), bc_hi=("fixed", "periodic"), h_ref=0.95 / n[0],
+                c=_c(0) if c is None else c, damp=1.0, params=())
+
+
+def closed_cylinder(scale: int = 1, c: float | None = None) -> dict:
+    """3-D closed cylinder (r, theta, z), R = 1, L = 2, inner radius 0.05,
+    bounce-back on r = 0.05, r = 1, z = 0, z = 2; 128 x 128 x 256 nodes."""
+    n = _scaled((128, 128, 256), scale)
+    return dict(kind="cylinder", dim=3, n=n, qmin=(0.05, 0.0, 0.0),
+                qmax=(1.0, TWO_PI, 2.0), bc_lo=("bounceback", "periodic", "bounceback"),
+                bc_hi=("bounceback", "periodic", "bounceback"), h_ref=0.95 / n[0],
+                c=_c(1) if c is None else c, damp=1.0, params=())
+
+
+def trumpet_horn(scale: int = 1, c: float | None = None, a=0.1, b=0.02, k=3.0, n=(128, 128, 512)) -> dict:
+    """Exponential horn R(z) = a + b exp(k z), z in [0, 1], scaled radius
+    r in [0.05, 1]; closed mouthpiece (z = 0, bounce-back), open bell (z = 1,
+    free), bounce-back wall at r = 1 and r = 0.05.
+
+    One lattice unit is the physical length of a radial link at the
+    mouthpiece wall, R(0) h_r / sqrt(1 + R'(0)^2): the radial links are then
+    nowhere shorter than a lattice unit, which keeps the scheme's radial
+    gradient-force coefficient non-positive."""
+    n = _scaled(n, scale)
+    hr = 0.95 / n[0]
+    h_ref = (a + b) * hr / math.sqrt(1.0 + (b * k) ** 2)
+    return dict(kind="horn", dim=3, n=n, qmin=(0.05, 0.0, 0.0), qmax=(1.0, TWO_PI, 1.0),
+                bc_lo=("bounceback", "periodic", "bounceback"), bc_hi=("bounceback", "periodic", "free"),
+                h_ref=h_ref, c=_c(2) if c is None else c, damp=1.0, params=(a, b, k))
+
+
+def torus(scale: int = 1, c: float | None = None) -> dict:
+    """Torus (rho, theta major, phi minor), minor radius 1, major radius 3,
+    rho in [0.05, 1] with bounce-back walls, theta and phi periodic;
+    96 x 256 x 512 nodes."""
+    n = _scaled((96, 256, 512), scale)
+    return dict(kind="torus", dim=3, n=n, qmin=(0.05, 0.0, 0.0),
+                qmax=(1.0, TWO_PI, TWO_PI), bc_lo=("bounceback", "periodic", "periodic"),
+                bc_hi=("bounceback", "periodic", "periodic"), h_ref=0.95 / n[0],
+                c=_c(3) if c is None else c, damp=1.0, params=(3.0,))
+
+
+GEOMETRIES = {0: polar_disk, 1: closed_cylinder, 2: trumpet_horn, 3: torus}
+STEPS = {0: 2000, 1: 20000, 2: 50000, 3: 40000}
+N_PROBES = {0: 1, 1: 16, 2: 32, 3: 64}
+NAMES = {0: "polar_disk_d2q5_64x64", 1: "cylinder_d3q7_128x128x256", 2: "horn_d3q7_128x128x512",
+         3: "torus_d3q7_96x256x512"}
+
+
+def workload(idx: int, scale: int = 1, c: float | None = None) -> dict:
+    """Geometry, initial pressure P0 (float64, N), probe node indices and the
+    configured step count for configuration idx."""
+    geom = GEOMETRIES[idx](scale=scale, c=c)
+    rng = np.random.default_rng(SEED_BASE + idx)
+    N = num_nodes(geom)
+    if idx == 0:
+        centre = node_position(geom, int(rng.integers(0, N)))
+        P0 = gaussian_pulses(geom, centre[None, :], [1.0], 0.1)
+        probes = rng.integers(0, N, size=N_PROBES[idx])
+    elif idx == 1:
+        nodes = rng.integers(0, N, size=8)
+        amps = rng.uniform(-1.0, 1.0, size=8)
+        centres = np.stack([node_position(geom, int(v)) for v in nodes])
+        P0 = gaussian_pulses(geom, centres, amps, 0.1)
+        probes = rng.integers(0, N, size=N_PROBES[idx])
+    elif idx == 2:
+        P0 = gaussian_pulses(geom, np.array([[0.0, 0.0, 0.1]]), [1.0], 0.05)
+        n0, n1, n2 = shape_of(geom)
+        m = N_PROBES[idx]
+        zs = ((np.arange(m) + 0.5) * n2 / m).astype(np.int64)
+        probes = zs * (n0 * n1)  # i0 = 0 (innermost ring), i1 = 0
+    elif idx == 3:
+        P0 = smoothed_noise(geom, rng, 2.0)
+        probes = rng.integers(0, N, size=N_PROBES[idx])
+    else:
+        raise ValueError(idx)
+    return dict(index=idx, name=NAMES[idx], geom=geom, P0=P0, probes=np.asarray(probes, dtype=np.int64),
+                steps=STEPS[idx], scale=scale)
