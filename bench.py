@@ -1,0 +1,126 @@
+"""Benchmark: fused collide-and-stream step of the curvilinear wave LBM on
+one MI355X, on the 3-D closed cylinder (D3Q7, 128 x 128 x 256 nodes, FP32
+populations, 16 probes recorded every step).
+
+Prints one JSON line.  value = whole-job MLUPS (node updates per second / 1e6)
+with the state resident in HBM; roofline = algorithmic bytes per launch
+(56 B per node: 7 float populations read and written) over the measured
+average launch duration, against 8 TB/s; cpu_baseline = the FP64 oracle on
+the host for a bounded number of steps of the same grid.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM peak; shape-spectra/sec batched+surrogate vs plain LBM"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_cylinder_128x128x256.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("step.hip", "lbw_internal.h"):
+        with open(os.path.join(ROOT, "paper_1705_01801_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current step kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, steps):
+    import numpy as np
+
+    import oracle
+    o = oracle.Oracle(w["geom"])
+    f = o.init(w["P0"])
+    t0 = time.perf_counter()
+    o.run(f, steps, w["probes"])
+    dt = time.perf_counter() - t0
+    return {"value": o.N * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "%d steps of the full %s grid (FP64, single thread, %.1f s; host has %d cores)"
+                      % (steps, w["name"], dt, os.cpu_count() or 0)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=15)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1705_01801_amd as lbw
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.workload(1)
+    geom = w["geom"]
+    N = W.num_nodes(geom)
+    g = lbw.Geometry(geom)
+    sim = lbw.Simulation(g, w["P0"], w["probes"], t_max=args.warmup + args.steps)
+    log("bench: %s, %d nodes, warmup %d, steps %d" % (w["name"], N, args.warmup, args.steps))
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sim.probe(0, min(sim.t, sim.t_max))  # raises on a non-finite trace
+    ms_per_step = ms / args.steps
+    mlups = N * args.steps / (ms / 1e3) / 1e6
+    bytes_per_launch = 56.0 * N
+    achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
+    traffic = read_traffic()
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["name"], "nodes": N, "lattice": "D3Q7", "probes": int(len(w["probes"])),
+                   "c": geom["c"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: oracle baseline, %d steps" % args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * lbw: curvilinear wave lattice-Boltzmann on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the lattice-Boltzmann model for the scalar wave equation in
+ * curvilinear coordinates of Velasco, Munoz and Mendoza (arXiv 1705.01801):
+ * a D3Q7 (or D2Q5) lattice that is uniform in the generalised coordinates,
+ * BGK relaxation with tau = 1/2, the corrected equilibrium of Sec. III
+ * (f_0 = w_0 sqrt(g) P, f_l = w_l sqrt(g) [P + xi_l.J'/c_s^2]) and the
+ * Christoffel and metric-gradient forcing carried in the corrected momentum
+ * J' (Sec. III, corrected-momentum equation).  Walls follow Sec. IV.A
+ * (bounce-back with damping, free) plus a fixed P = 0 wall.
+ *
+ * Conventions for every entry point:
+ *  - returns LBW_OK (0) or a negative LBW_E* code; lbw_last_error() gives a
+ *    message for the calling thread's last failure.  Arguments are validated
+ *    on the host before any device work is queued; on error nothing is
+ *    queued and no output is written.
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary host memory.  The library owns only the opaque
+ *    geometry/state objects and the small tables and scratch inside them.
+ *  - stream arguments are hipStream_t passed as void* (NULL = the null
+ *    stream).  All device work is queued on that stream; only lbw_probe,
+ *    lbw_modes, lbw_geometry_export and lbw_stability_bound wait for it.
+ *  - populations are stored structure-of-arrays, f[l * N + n] with node
+ *    n = i0 + n0 * (i1 + n1 * i2) and l in the order
+ *    0: rest, 1: +e0, 2: -e0, 3: +e1, 4: -e1, 5: +e2, 6: -e2 (Q = 2*dim + 1).
+ */
+#ifndef LBW_H
+#define LBW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBW_OK 0
+#define LBW_EINVAL (-1)    /* invalid argument */
+#define LBW_ENOMEM (-2)    /* device allocation failed */
+#define LBW_EDEVICE (-3)   /* HIP runtime error */
+#define LBW_EUNSTABLE (-4) /* non-finite value found in a probe trace */
+#define LBW_ESTATE (-5)    /* call not valid in the object's current state */
+
+/* Coordinate systems (Sec. IV).  Axis order (q0, q1, q2):
+ *  LBW_BOX         Cartesian (x, y, z); 2-D or 3-D
+ *  LBW_POLAR2D     (r, theta), 2-D restriction of the cylinder
+ *  LBW_CYLINDER    (r, theta, z), Sec. IV.A
+ *  LBW_HORN        (r, theta, z), x = r s(z) cos(theta), y = r s(z) sin(theta),
+ *                  s(z) = a + b exp(k z); params = {a, b, k}
+ *  LBW_TORUS       (rho, theta major, phi minor), Sec. IV.C; params = {R}
+ *  LBW_BESSEL_HORN as LBW_HORN with s(z) = (Zmax - z)^(-lambda), the Bessel
+ *                  horn of Sec. IV.B; params = {lambda, Zmax}
+ */
+enum { LBW_BOX = 0, LBW_POLAR2D = 1, LBW_CYLINDER = 2, LBW_HORN = 3, LBW_TORUS = 4, LBW_BESSEL_HORN = 5 };
+
+/* Wall codes per face.  Walls sit half a link outside the end nodes.
+ *  PERIODIC    both faces of the axis must be periodic
+ *  BOUNCEBACK  half-way bounce-back, reflected population scaled by the
+ *              damping factor D (Sec. IV.A, pipe boundary conditions)
+ *  FREE        the incoming population copies the boundary node's own
+ *              post-collision population ("copying the values of the
+ *              neighbouring cell", Sec. IV.A)
+ *  FIXED       half-way anti-bounce-back, pressure P = 0 on the wall */
+enum { LBW_BC_PERIODIC = 0, LBW_BC_BOUNCEBACK = 1, LBW_BC_FREE = 2, LBW_BC_FIXED = 3 };
+
+typedef struct {
+    int32_t kind;      /* LBW_BOX ... LBW_BESSEL_HORN */
+    int32_t dim;       /* 2 -> D2Q5, 3 -> D3Q7 */
+    int32_t n[3];      /* nodes per axis (n[2] ignored for dim 2) */
+    int32_t bc_lo[3];  /* wall code of the low face of each axis */
+    int32_t bc_hi[3];  /* wall code of the high face of each axis */
+    int32_t reserved;  /* must be 0 */
+    double qmin[3];    /* coordinate range; periodic axis nodes at qmin + i h, */
+    double qmax[3];    /* walled axis nodes at qmin + (i + 1/2) h, h = (qmax - qmin) / n */
+    double h_ref;      /* physical length of one lattice unit (> 0) */
+    double c;          /* lattice wave speed c = c_phys dt / h_ref (c_s = c) */
+    double damping;    /* bounce-back damping factor D in [0, 1] */
+    double params[4];  /* kind-specific, see above */
+} lbw_geometry_desc;
+
+typedef struct lbw_geometry* lbw_geometry_t;
+typedef struct lbw_state* lbw_state_t;
+
+/* Builds the per-geometry coefficient tables on the device (Sec. III and IV:
+ * sqrt(g), g^{ij} and the contracted Christoffel symbols
+ * Gamma^i = Gamma^i_jk g^jk, evaluated in FP64 from closed forms and
+ * converted to lattice units: Mhat^{ij} = h_ref^2 g^{ij}/(h_i h_j) - delta^{ij},
+ * Gamh^i = h_ref^2 Gamma^i / h_i).  The coefficients of every supported kind
+ * depend on (i0, i2) only, so tables are n0 x n2.  Queued on stream; the
+ * geometry may be used by later calls on the same stream at once.
+ * Errors: LBW_EINVAL for an invalid descriptor (bad kind/dim pairing, n < 1,
+ * qmax <= qmin, h_ref <= 0, c <= 0 or not finite, damping outside [0, 1],
+ * unpaired periodic faces, radius <= 0, torus rho >= R, horn s(z) <= 0,
+ * more than 2^31 - 1 nodes); LBW_ENOMEM; LBW_EDEVICE. */
+int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_t* out);
+
+/* Releases a geometry (waits for its stream first).  NULL is accepted. */
+int lbw_free_geometry(lbw_geometry_t g);
+
+/* Exported views, for checking the device tables (synchronises):
+ *  LBW_EXPORT_TABLE_F64  8 planes of n0*n2 doubles, entry e = i0 + n0*i2:
+ *                        Mhat00, Mhat11, Mhat22, Mhat02, Gamh0, Gamh1, Gamh2, sqrtg
+ *  LBW_EXPORT_MASK_U8    N bytes; bit (l-1) set when the link n -> n + xi_l
+ *                        crosses a wall
+ *  LBW_EXPORT_PULL_I32   Q*N int32; entry l*N + n is the node population l
+ *                        arrives from at n (periodic wrap applied), or
+ *                        -(1 + wall code) when it arrives through a wall
+ * bytes must equal the exported size exactly (LBW_EINVAL otherwise). */
+enum { LBW_EXPORT_TABLE_F64 = 0, LBW_EXPORT_MASK_U8 = 1, LBW_EXPORT_PULL_I32 = 2 };
+int lbw_geometry_export(lbw_geometry_t g, int what, void* host_dst, size_t bytes);
+
+/* Frozen-coefficient stability bound of the tau = 1/2 step on this geometry:
+ * c_max = 2 / sqrt(max_nodes sum_d B_d), B_d = 4 if m_d <= 1 else
+ * (1 + m_d)^2 / m_d, m_d = Mhat^dd (+ |Mhat^02| on axes 0 and 2).
+ * Synchronises.  Errors: LBW_EINVAL for NULL arguments. */
+int lbw_stability_bound(lbw_geometry_t g, double* c_max);
+
+/* Creates a simulation state on caller-owned device buffers.
+ *  p0        device, N doubles: initial pressure P; populations start at the
+ *            corrected equilibrium at rest, f_l = w_l sqrt(g) P0 with
+ *            w_0 = 1 - dim c^2, w_l = c^2 / 2 (rounded once to float)
+ *  f_a, f_b  device, Q*N floats each, distinct; ping-pong population
+ *            buffers, f_a holds the state after init
+ *  probes    host, n_probes node indices in [0, N) (copied)
+ *  trace     device, t_max * n_probes doubles: row t receives the pressure
+ *            P = sum_l f_l / sqrt(g) at every probe before step t
+ *  t_max     capacity of trace in rows (>= 0); steps beyond it run but
+ *            record nothing
+ * The state keeps the buffer pointers; the caller keeps them alive until
+ * lbw_free_state.  Errors: LBW_EINVAL (NULL pointers, f_a == f_b,
+ * probe out of range, n_probes < 0, n_probes > 0 with trace == NULL),
+ * LBW_ENOMEM, LBW_EDEVICE. */
+int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const int64_t* probes, int n_probes,
+             double* trace, int64_t t_max, void* stream, lbw_state_t* out);
+
+/* Queues n time steps (BGK, tau = 1/2, fused collide-and-push-stream with
+ * walls; Sec. II evolution equation with the Sec. III equilibrium and
+ * forcing) and the probe recording; returns without waiting.
+ * Errors: LBW_EINVAL for n < 0, LBW_EDEVICE on a launch failure. */
+int lbw_step_n(lbw_state_t s, int64_t n);
+
+/* Copies trace rows [t0, t1) (t1 <= recorded rows) to host memory,
+ * n_probes doubles per row.  Synchronises.  Returns LBW_EUNSTABLE (after
+ * copying) when a copied value is not finite. */
+int lbw_probe(lbw_state_t s, double* host_dst, int64_t t0, int64_t t1);
+
+/* Resonant frequencies of the recorded probe traces, computed on the device
+ * in FP64: per probe subtract the mean, apply the symmetric Hann window
+ * 1/2 - 1/2 cos(2 pi t/(T-1)), zero-pad to 4 x the next power of two of T,
+ * FFT, sum |X_k|^2 over probes; peaks are bins k in [2, nfft/2 - 1] with
+ * P[k-1] < P[k] >= P[k+1] and P[k] > 1e-3 max_{k>=2} P, refined by a parabola
+ * through ln P; the k lowest, ascending, in cycles per step (NaN-padded).
+ * power_out may be NULL.  Synchronises.  Errors: LBW_EINVAL (k < 1, fewer
+ * than 8 recorded rows, no probes), LBW_EUNSTABLE (non-finite trace). */
+int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out);
+
+/* Current step count and the device buffer holding the current populations. */
+int lbw_state_info(lbw_state_t s, int64_t* t, float** f_current);
+
+/* Pressure P = sum_l f_l / sqrt(g) of the current state into a device buffer
+ * of N doubles (queued on the state's stream). */
+int lbw_pressure(lbw_state_t s, double* p_out);
+
+/* Releases a state (waits for its stream first); caller buffers are left
+ * untouched.  NULL is accepted. */
+int lbw_free_state(lbw_state_t s);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* lbw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBW_H */

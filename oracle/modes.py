@@ -11,7 +11,8 @@ information is the peak set of the probe signal's power spectrum.  Rule:
   3. sum the power over probes;
   4. peaks: bins k in [2, nfft/2 - 1] with P[k-1] < P[k] >= P[k+1] and
      P[k] > rel_threshold * max_{k >= 2} P;
-  5. refine each by a parabola through ln P at k-1, k, k+1:
+  5. refine each by a parabola through ln P at k-1, k, k+1 (no refinement,
+     delta = 0, when P[k-1] or P[k+1] is zero):
      delta = (ln P[k-1] - ln P[k+1]) / (2 (ln P[k-1] - 2 ln P[k] + ln P[k+1])),
      frequency (k + delta) / nfft cycles per step,
      power exp(ln P[k] - (ln P[k-1] - ln P[k+1]) delta / 4);
@@ -56,9 +57,13 @@ def modes(trace: np.ndarray, k: int, rel_threshold: float = 1e-3):
         if found == k:
             break
         if P[b - 1] < P[b] and P[b] >= P[b + 1] and P[b] > rel_threshold * pmax:
-            lm, l0, lp = np.log(P[b - 1]), np.log(P[b]), np.log(P[b + 1])
-            den = lm - 2.0 * l0 + lp
-            delta = 0.5 * (lm - lp) / den if den != 0.0 else 0.0
+            l0 = np.log(P[b])
+            if P[b - 1] > 0.0 and P[b + 1] > 0.0:
+                lm, lp = np.log(P[b - 1]), np.log(P[b + 1])
+                den = lm - 2.0 * l0 + lp
+                delta = 0.5 * (lm - lp) / den if den != 0.0 else 0.0
+            else:
+                lm = lp = delta = 0.0
             freq[found] = (b + delta) / nfft
             powr[found] = np.exp(l0 - 0.25 * (lm - lp) * delta)
             found += 1

@@ -1,0 +1,234 @@
+"""Python binding of liblbw: the curvilinear wave lattice-Boltzmann step of
+Velasco, Munoz and Mendoza (arXiv 1705.01801) on MI355X.
+
+Argument marshalling only: every step of the method runs in the HIP library
+(``liblbw.so``, built by ``paper_1705_01801_amd.build``).  PyTorch provides
+device memory and the stream.  Importing works without a GPU; creating a
+geometry needs the built library and a device, and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbw.so")
+
+KINDS = {"box": 0, "polar2d": 1, "cylinder": 2, "horn": 3, "torus": 4, "bessel_horn": 5}
+BCS = {"periodic": 0, "bounceback": 1, "free": 2, "fixed": 3}
+EXPORT_TABLE_F64, EXPORT_MASK_U8, EXPORT_PULL_I32 = 0, 1, 2
+TABLE_PLANES = ("Mhat00", "Mhat11", "Mhat22", "Mhat02", "Gamh0", "Gamh1", "Gamh2", "sqrtg")
+
+# every symbol include/lbw.h declares
+SYMBOLS = ("lbw_make_geometry", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound", "lbw_init",
+           "lbw_step_n", "lbw_probe", "lbw_modes", "lbw_state_info", "lbw_pressure", "lbw_free_state",
+           "lbw_last_error")
+
+
+class GeometryDesc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("dim", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("bc_lo", ctypes.c_int32 * 3),
+        ("bc_hi", ctypes.c_int32 * 3),
+        ("reserved", ctypes.c_int32),
+        ("qmin", ctypes.c_double * 3),
+        ("qmax", ctypes.c_double * 3),
+        ("h_ref", ctypes.c_double),
+        ("c", ctypes.c_double),
+        ("damping", ctypes.c_double),
+        ("params", ctypes.c_double * 4),
+    ]
+
+
+class LbwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("lbw error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("liblbw.so is not built (run paper_1705_01801_amd/build.py); "
+                               "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.lbw_make_geometry.argtypes = [ctypes.POINTER(GeometryDesc), vp, ctypes.POINTER(vp)]
+        L.lbw_free_geometry.argtypes = [vp]
+        L.lbw_geometry_export.argtypes = [vp, i32, vp, ctypes.c_size_t]
+        L.lbw_stability_bound.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.lbw_init.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), i32, vp, i64, vp, ctypes.POINTER(vp)]
+        L.lbw_step_n.argtypes = [vp, i64]
+        L.lbw_probe.argtypes = [vp, vp, i64, i64]
+        L.lbw_modes.argtypes = [vp, i32, vp, vp]
+        L.lbw_state_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(vp)]
+        L.lbw_pressure.argtypes = [vp, vp]
+        L.lbw_free_state.argtypes = [vp]
+        L.lbw_last_error.restype = ctypes.c_char_p
+        for name in SYMBOLS:
+            getattr(L, name).restype = ctypes.c_int if name != "lbw_last_error" else ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(rc: int):
+    if rc != 0:
+        raise LbwError(rc, lib().lbw_last_error().decode())
+
+
+def to_desc(geom: dict) -> GeometryDesc:
+    """Geometry description (plain dict, see ``workloads``) -> C struct."""
+    d = GeometryDesc()
+    d.kind = KINDS[geom["kind"]]
+    d.dim = int(geom["dim"])
+    dim = d.dim
+    for a in range(3):
+        if a < dim:
+            d.n[a] = int(geom["n"][a])
+            d.qmin[a] = float(geom["qmin"][a])
+            d.qmax[a] = float(geom["qmax"][a])
+            d.bc_lo[a] = BCS[geom["bc_lo"][a]]
+            d.bc_hi[a] = BCS[geom["bc_hi"][a]]
+        else:
+            d.n[a], d.qmin[a], d.qmax[a] = 1, 0.0, 1.0
+    d.reserved = 0
+    d.h_ref = float(geom["h_ref"])
+    d.c = float(geom["c"])
+    d.damping = float(geom.get("damp", 1.0))
+    par = list(geom.get("params", ())) + [0.0] * 4
+    for i in range(4):
+        d.params[i] = float(par[i])
+    return d
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Geometry:
+    """Device coefficient tables of one coordinate system and grid."""
+
+    def __init__(self, geom: dict, stream=None):
+        self.geom = dict(geom)
+        self.dim = int(geom["dim"])
+        self.Q = 2 * self.dim + 1
+        self.shape = tuple(int(v) for v in geom["n"][: self.dim])
+        self.N = int(np.prod(self.shape))
+        self.E = self.shape[0] * (self.shape[2] if self.dim == 3 else 1)
+        self._desc = to_desc(geom)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        check(lib().lbw_make_geometry(ctypes.byref(self._desc), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def table(self) -> np.ndarray:
+        out = np.zeros((8, self.E))
+        check(lib().lbw_geometry_export(self.handle, EXPORT_TABLE_F64, out.ctypes.data, out.nbytes))
+        return out
+
+    def maps(self):
+        mask = np.zeros(self.N, np.uint8)
+        pull = np.zeros((self.Q, self.N), np.int32)
+        check(lib().lbw_geometry_export(self.handle, EXPORT_MASK_U8, mask.ctypes.data, mask.nbytes))
+        check(lib().lbw_geometry_export(self.handle, EXPORT_PULL_I32, pull.ctypes.data, pull.nbytes))
+        return mask, pull
+
+    def stability_bound(self) -> float:
+        v = ctypes.c_double()
+        check(lib().lbw_stability_bound(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lbw_free_geometry(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Simulation:
+    """A wave field on a geometry: caller-owned populations (two float32
+    buffers, Q x N), an FP64 probe trace, and the step/probe/modes calls."""
+
+    def __init__(self, geometry: Geometry, P0, probes=(), t_max: int = 0, stream=None):
+        import torch
+        self.geometry = geometry
+        dev = torch.device("cuda", torch.cuda.current_device())
+        P0 = torch.as_tensor(P0, dtype=torch.float64).reshape(-1).to(dev).contiguous()
+        if P0.numel() != geometry.N:
+            raise ValueError("P0 has %d values, geometry has %d nodes" % (P0.numel(), geometry.N))
+        self._P0 = P0
+        self.f = [torch.empty((geometry.Q, geometry.N), dtype=torch.float32, device=dev) for _ in range(2)]
+        probes = np.ascontiguousarray(np.asarray(probes, dtype=np.int64).reshape(-1))
+        self.n_probes = int(probes.size)
+        self.t_max = int(t_max) if self.n_probes else 0
+        self.trace = torch.zeros((max(self.t_max, 1), max(self.n_probes, 1)), dtype=torch.float64, device=dev)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        pp = probes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if self.n_probes else None
+        check(lib().lbw_init(geometry.handle, P0.data_ptr(), self.f[0].data_ptr(), self.f[1].data_ptr(), pp,
+                             self.n_probes, self.trace.data_ptr() if self.n_probes else None, self.t_max,
+                             _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def step(self, n: int = 1):
+        check(lib().lbw_step_n(self.handle, int(n)))
+
+    @property
+    def t(self) -> int:
+        t = ctypes.c_int64()
+        check(lib().lbw_state_info(self.handle, ctypes.byref(t), None))
+        return t.value
+
+    def populations(self):
+        """The torch tensor (Q x N, float32) holding the current state."""
+        p = ctypes.c_void_p()
+        check(lib().lbw_state_info(self.handle, None, ctypes.byref(p)))
+        return self.f[0] if p.value == self.f[0].data_ptr() else self.f[1]
+
+    def probe(self, t0: int = 0, t1: int | None = None) -> np.ndarray:
+        rows = min(self.t, self.t_max)
+        t1 = rows if t1 is None else t1
+        out = np.zeros((max(t1 - t0, 0), self.n_probes))
+        if out.size == 0:
+            return out
+        check(lib().lbw_probe(self.handle, out.ctypes.data, int(t0), int(t1)))
+        return out
+
+    def modes(self, k: int):
+        freq = np.zeros(k)
+        power = np.zeros(k)
+        check(lib().lbw_modes(self.handle, int(k), freq.ctypes.data, power.ctypes.data))
+        return freq, power
+
+    def pressure(self):
+        import torch
+        out = torch.empty(self.geometry.N, dtype=torch.float64, device=self.f[0].device)
+        check(lib().lbw_pressure(self.handle, out.data_ptr()))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lbw_free_state(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,361 @@
+// C-ABI entry points declared in include/lbw.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbw_internal.h"
+
+using lbw::GeomDev;
+
+struct lbw_geometry {
+    lbw_geometry_desc d;
+    int Q = 0;
+    int64_t N = 0;
+    int64_t E = 0;  // table entries n0 * n2
+    double* tab64 = nullptr;
+    float* tab32 = nullptr;
+    hipStream_t stream = nullptr;
+    GeomDev dev{};
+};
+
+struct lbw_state {
+    lbw_geometry* g = nullptr;
+    float* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t t = 0;
+    int64_t t_max = 0;
+    int n_probes = 0;
+    double* trace = nullptr;
+    int64_t* d_probes = nullptr;
+    int64_t* d_tcount = nullptr;
+    hipStream_t stream = nullptr;
+    double* mode_work = nullptr;
+    size_t mode_work_bytes = 0;
+    double* mode_out = nullptr;  // device, 2 * mode_k
+    int mode_k = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) return fail(LBW_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(LBW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                 \
+    do {                                    \
+        hipError_t e_ = (expr);             \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate(const lbw_geometry_desc* d) {
+    if (!d) return fail(LBW_EINVAL, "descriptor is NULL");
+    if (d->kind < LBW_BOX || d->kind > LBW_BESSEL_HORN) return fail(LBW_EINVAL, "unknown kind %d", d->kind);
+    if (d->dim != 2 && d->dim != 3) return fail(LBW_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
+    if (d->kind == LBW_POLAR2D && d->dim != 2) return fail(LBW_EINVAL, "polar2d needs dim 2");
+    if (d->kind != LBW_POLAR2D && d->kind != LBW_BOX && d->dim != 3) return fail(LBW_EINVAL, "kind needs dim 3");
+    if (d->reserved != 0) return fail(LBW_EINVAL, "reserved field must be 0");
+    int64_t N = 1;
+    for (int a = 0; a < d->dim; ++a) {
+        if (d->n[a] < 1) return fail(LBW_EINVAL, "n[%d] = %d < 1", a, d->n[a]);
+        if (!finite(d->qmin[a]) || !finite(d->qmax[a]) || !(d->qmax[a] > d->qmin[a]))
+            return fail(LBW_EINVAL, "axis %d: need qmin < qmax", a);
+        for (int side = 0; side < 2; ++side) {
+            int code = side ? d->bc_hi[a] : d->bc_lo[a];
+            if (code < LBW_BC_PERIODIC || code > LBW_BC_FIXED) return fail(LBW_EINVAL, "axis %d: bad wall code", a);
+        }
+        if ((d->bc_lo[a] == LBW_BC_PERIODIC) != (d->bc_hi[a] == LBW_BC_PERIODIC))
+            return fail(LBW_EINVAL, "axis %d: periodic faces must be paired", a);
+        N *= d->n[a];
+    }
+    if (N > 2147483647LL) return fail(LBW_EINVAL, "too many nodes (%lld)", (long long)N);
+    if (!finite(d->h_ref) || !(d->h_ref > 0.0)) return fail(LBW_EINVAL, "h_ref must be > 0");
+    if (!finite(d->c) || !(d->c > 0.0)) return fail(LBW_EINVAL, "c must be > 0");
+    if (!finite(d->damping) || d->damping < 0.0 || d->damping > 1.0) return fail(LBW_EINVAL, "damping outside [0,1]");
+    switch (d->kind) {
+    case LBW_POLAR2D:
+    case LBW_CYLINDER:
+        if (!(d->qmin[0] > 0.0)) return fail(LBW_EINVAL, "radius must stay > 0");
+        break;
+    case LBW_HORN: {
+        if (!(d->qmin[0] > 0.0)) return fail(LBW_EINVAL, "radius must stay > 0");
+        const double a = d->params[0], b = d->params[1], k = d->params[2];
+        for (int end = 0; end < 2; ++end) {
+            const double z = end ? d->qmax[2] : d->qmin[2];
+            const double s = a + b * std::exp(k * z);
+            if (!finite(s) || !(s > 0.0)) return fail(LBW_EINVAL, "horn radius must stay > 0");
+        }
+        if (!(a > 0.0) && !(b > 0.0)) return fail(LBW_EINVAL, "horn radius must stay > 0");
+        break;
+    }
+    case LBW_BESSEL_HORN:
+        if (!(d->qmin[0] > 0.0)) return fail(LBW_EINVAL, "radius must stay > 0");
+        if (!(d->params[1] > d->qmax[2])) return fail(LBW_EINVAL, "Bessel horn needs Zmax > z range");
+        break;
+    case LBW_TORUS:
+        if (!(d->qmin[0] > 0.0)) return fail(LBW_EINVAL, "rho must stay > 0");
+        if (!(d->params[0] > d->qmax[0])) return fail(LBW_EINVAL, "torus needs R > rho_max");
+        break;
+    default:
+        break;
+    }
+    return LBW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbw_last_error(void) { return g_err.c_str(); }
+
+int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_t* out) {
+    if (!out) return fail(LBW_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(desc);
+    if (rc) return rc;
+    lbw_geometry* g = new lbw_geometry();
+    g->d = *desc;
+    if (g->d.dim == 2) {
+        g->d.n[2] = 1;
+        g->d.bc_lo[2] = g->d.bc_hi[2] = LBW_BC_PERIODIC;
+        g->d.qmin[2] = 0.0;
+        g->d.qmax[2] = 1.0;
+    }
+    const lbw_geometry_desc& d = g->d;
+    g->Q = 2 * d.dim + 1;
+    g->N = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    g->E = (int64_t)d.n[0] * d.n[2];
+    g->stream = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&g->tab64, sizeof(double) * lbw::kTabF64 * g->E);
+    if (e == hipSuccess) e = hipMalloc(&g->tab32, sizeof(float) * lbw::kTabF32 * g->E);
+    if (e == hipSuccess) e = lbw::launch_geometry_tables(d, g->tab64, g->tab32, g->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(g->tab64);
+        (void)hipFree(g->tab32);
+        delete g;
+        return hip_fail(e, "lbw_make_geometry");
+    }
+    GeomDev& v = g->dev;
+    v.dim = d.dim;
+    v.n0 = d.n[0];
+    v.n1 = d.n[1];
+    v.n2 = d.n[2];
+    v.N = g->N;
+    for (int a = 0; a < 3; ++a) {
+        v.bc_lo[a] = d.bc_lo[a];
+        v.bc_hi[a] = d.bc_hi[a];
+    }
+    const double c2 = d.c * d.c;
+    v.c2 = (float)c2;
+    v.two_w0 = (float)(2.0 * (1.0 - d.dim * c2));
+    v.damp = (float)d.damping;
+    v.c2_64 = c2;
+    v.tab = g->tab32;
+    v.sqrtg = g->tab64 + 7 * g->E;
+    *out = g;
+    return LBW_OK;
+}
+
+int lbw_free_geometry(lbw_geometry_t g) {
+    if (!g) return LBW_OK;
+    (void)hipStreamSynchronize(g->stream);
+    (void)hipFree(g->tab64);
+    (void)hipFree(g->tab32);
+    delete g;
+    return LBW_OK;
+}
+
+int lbw_geometry_export(lbw_geometry_t g, int what, void* host_dst, size_t bytes) {
+    if (!g || !host_dst) return fail(LBW_EINVAL, "NULL argument");
+    size_t need = 0;
+    switch (what) {
+    case LBW_EXPORT_TABLE_F64: need = sizeof(double) * lbw::kTabF64 * g->E; break;
+    case LBW_EXPORT_MASK_U8: need = (size_t)g->N; break;
+    case LBW_EXPORT_PULL_I32: need = sizeof(int32_t) * g->Q * g->N; break;
+    default: return fail(LBW_EINVAL, "unknown export %d", what);
+    }
+    if (bytes != need) return fail(LBW_EINVAL, "export %d needs %zu bytes, got %zu", what, need, bytes);
+    if (what == LBW_EXPORT_TABLE_F64) {
+        HIP_TRY(hipMemcpyAsync(host_dst, g->tab64, need, hipMemcpyDeviceToHost, g->stream), "export table");
+        HIP_TRY(hipStreamSynchronize(g->stream), "export table");
+        return LBW_OK;
+    }
+    uint8_t* mask = nullptr;
+    int32_t* pull = nullptr;
+    HIP_TRY(hipMalloc(&mask, g->N), "export maps");
+    hipError_t e = hipMalloc(&pull, sizeof(int32_t) * g->Q * g->N);
+    if (e == hipSuccess) e = lbw::launch_index_maps(g->dev, mask, pull, g->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_dst, what == LBW_EXPORT_MASK_U8 ? (void*)mask : (void*)pull, need,
+                           hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    (void)hipFree(mask);
+    (void)hipFree(pull);
+    if (e != hipSuccess) return hip_fail(e, "export maps");
+    return LBW_OK;
+}
+
+int lbw_stability_bound(lbw_geometry_t g, double* c_max) {
+    if (!g || !c_max) return fail(LBW_EINVAL, "NULL argument");
+    std::vector<double> t((size_t)lbw::kTabF64 * g->E);
+    HIP_TRY(hipMemcpyAsync(t.data(), g->tab64, sizeof(double) * t.size(), hipMemcpyDeviceToHost, g->stream),
+            "stability bound");
+    HIP_TRY(hipStreamSynchronize(g->stream), "stability bound");
+    const int64_t E = g->E;
+    double worst = 0.0;
+    for (int64_t e = 0; e < E; ++e) {
+        double tot = 0.0;
+        for (int a = 0; a < g->d.dim; ++a) {
+            double m = t[a * E + e];
+            if (g->d.dim == 3 && a != 1) m += std::fabs(t[3 * E + e]);
+            tot += m <= 1.0 ? 4.0 : (1.0 + m) * (1.0 + m) / m;
+        }
+        worst = std::fmax(worst, tot);
+    }
+    *c_max = 2.0 / std::sqrt(worst);
+    return LBW_OK;
+}
+
+int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const int64_t* probes, int n_probes,
+             double* trace, int64_t t_max, void* stream, lbw_state_t* out) {
+    if (!out) return fail(LBW_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g || !p0 || !f_a || !f_b) return fail(LBW_EINVAL, "NULL argument");
+    if (f_a == f_b) return fail(LBW_EINVAL, "f_a and f_b must be distinct");
+    if (n_probes < 0 || t_max < 0) return fail(LBW_EINVAL, "negative n_probes or t_max");
+    if (n_probes > 0 && (!probes || (!trace && t_max > 0))) return fail(LBW_EINVAL, "probes need a trace buffer");
+    for (int p = 0; p < n_probes; ++p)
+        if (probes[p] < 0 || probes[p] >= g->N) return fail(LBW_EINVAL, "probe %d out of range", p);
+    lbw_state* s = new lbw_state();
+    s->g = g;
+    s->f[0] = f_a;
+    s->f[1] = f_b;
+    s->t_max = n_probes > 0 ? t_max : 0;
+    s->n_probes = n_probes;
+    s->trace = trace;
+    s->stream = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&s->d_tcount, sizeof(int64_t));
+    if (e == hipSuccess && n_probes > 0) e = hipMalloc(&s->d_probes, sizeof(int64_t) * n_probes);
+    if (e == hipSuccess && n_probes > 0)
+        e = hipMemcpyAsync(s->d_probes, probes, sizeof(int64_t) * n_probes, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_tcount, 0, sizeof(int64_t), s->stream);
+    if (e == hipSuccess && s->stream != g->stream) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = lbw::launch_init(g->dev, p0, f_a, s->stream);
+    if (e == hipSuccess && n_probes > 0) e = hipStreamSynchronize(s->stream);  // host probe list may go away
+    if (e != hipSuccess) {
+        (void)hipFree(s->d_tcount);
+        (void)hipFree(s->d_probes);
+        delete s;
+        return hip_fail(e, "lbw_init");
+    }
+    *out = s;
+    return LBW_OK;
+}
+
+int lbw_step_n(lbw_state_t s, int64_t n) {
+    if (!s) return fail(LBW_EINVAL, "state is NULL");
+    if (n < 0) return fail(LBW_EINVAL, "negative step count");
+    lbw::ProbeArgs pr{s->d_probes, s->n_probes, s->trace, s->t_max, s->d_tcount};
+    for (int64_t i = 0; i < n; ++i) {
+        HIP_TRY(lbw::launch_step(s->g->dev, pr, s->f[s->cur], s->f[1 - s->cur], s->stream), "lbw_step_n");
+        s->cur ^= 1;
+        s->t += 1;
+    }
+    return LBW_OK;
+}
+
+int lbw_probe(lbw_state_t s, double* host_dst, int64_t t0, int64_t t1) {
+    if (!s || !host_dst) return fail(LBW_EINVAL, "NULL argument");
+    const int64_t rows = s->t < s->t_max ? s->t : s->t_max;
+    if (t0 < 0 || t1 < t0 || t1 > rows) return fail(LBW_EINVAL, "rows [%lld, %lld) outside [0, %lld)",
+                                                    (long long)t0, (long long)t1, (long long)rows);
+    const size_t cnt = (size_t)(t1 - t0) * s->n_probes;
+    if (cnt) {
+        HIP_TRY(hipMemcpyAsync(host_dst, s->trace + t0 * s->n_probes, cnt * sizeof(double), hipMemcpyDeviceToHost,
+                               s->stream),
+                "lbw_probe");
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream), "lbw_probe");
+    for (size_t i = 0; i < cnt; ++i)
+        if (!std::isfinite(host_dst[i])) return fail(LBW_EUNSTABLE, "non-finite probe value at row %lld",
+                                                     (long long)(t0 + i / s->n_probes));
+    return LBW_OK;
+}
+
+int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out) {
+    if (!s || !freq_out) return fail(LBW_EINVAL, "NULL argument");
+    if (k < 1) return fail(LBW_EINVAL, "k must be >= 1");
+    if (s->n_probes < 1) return fail(LBW_EINVAL, "state has no probes");
+    const int64_t T = s->t < s->t_max ? s->t : s->t_max;
+    if (T < 8) return fail(LBW_EINVAL, "need at least 8 recorded rows (have %lld)", (long long)T);
+    const size_t need = lbw::modes_work_bytes(T, s->n_probes);
+    if (need > s->mode_work_bytes) {
+        (void)hipFree(s->mode_work);
+        s->mode_work = nullptr;
+        s->mode_work_bytes = 0;
+        HIP_TRY(hipMalloc(&s->mode_work, need), "lbw_modes");
+        s->mode_work_bytes = need;
+    }
+    if (k > s->mode_k) {
+        (void)hipFree(s->mode_out);
+        s->mode_out = nullptr;
+        s->mode_k = 0;
+        HIP_TRY(hipMalloc(&s->mode_out, sizeof(double) * 2 * k), "lbw_modes");
+        s->mode_k = k;
+    }
+    HIP_TRY(lbw::launch_modes(s->trace, T, s->n_probes, k, s->mode_work, s->mode_work_bytes, s->mode_out,
+                              s->mode_out + k, s->stream),
+            "lbw_modes");
+    std::vector<double> host(2 * (size_t)k);
+    HIP_TRY(hipMemcpyAsync(host.data(), s->mode_out, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, s->stream),
+            "lbw_modes");
+    HIP_TRY(hipStreamSynchronize(s->stream), "lbw_modes");
+    for (int i = 0; i < k; ++i) {
+        freq_out[i] = host[i];
+        if (power_out) power_out[i] = host[k + i];
+    }
+    return LBW_OK;
+}
+
+int lbw_state_info(lbw_state_t s, int64_t* t, float** f_current) {
+    if (!s) return fail(LBW_EINVAL, "state is NULL");
+    if (t) *t = s->t;
+    if (f_current) *f_current = s->f[s->cur];
+    return LBW_OK;
+}
+
+int lbw_pressure(lbw_state_t s, double* p_out) {
+    if (!s || !p_out) return fail(LBW_EINVAL, "NULL argument");
+    HIP_TRY(lbw::launch_pressure(s->g->dev, s->f[s->cur], p_out, s->stream), "lbw_pressure");
+    return LBW_OK;
+}
+
+int lbw_free_state(lbw_state_t s) {
+    if (!s) return LBW_OK;
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(s->d_tcount);
+    (void)hipFree(s->d_probes);
+    (void)hipFree(s->mode_work);
+    (void)hipFree(s->mode_out);
+    delete s;
+    return LBW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,249 @@
+"""GPU parity: the HIP library against the FP64 oracle on identical seeded
+inputs, through the C-ABI binding.
+
+Bars (written here, derived in the design notes): coefficient tables within
+1e-12 relative; index maps bit-exact; one step within 2e-6 of max|f|
+(float32 rounding of a handful of operations); relative L2 error of the
+populations and of the pressure field <= 1e-5 after 1000 steps; mode
+frequencies within 1e-5 relative.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1705_01801_amd as lbw
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(geom, P0, steps, probes=(), t_max=None):
+    g = lbw.Geometry(geom)
+    sim = lbw.Simulation(g, P0, probes, t_max=steps if t_max is None else t_max)
+    sim.step(steps)
+    f = sim.populations().double().cpu().numpy()
+    tr = sim.probe() if len(probes) else None
+    return g, sim, f, tr
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def table_from_oracle(o, geom):
+    """Oracle per-node values at the table entries (i0, i1 = 0, i2)."""
+    n0 = o.shape[0]
+    n1 = o.shape[1]
+    n2 = o.shape[2] if o.dim == 3 else 1
+    nodes = np.array([i0 + n0 * n1 * i2 for i2 in range(n2) for i0 in range(n0)])
+    M = o.Mhat[:, nodes]
+    G = o.Gamh[:, nodes]
+    return np.stack([M[0], M[1], M[2], M[4], G[0], G[1], G[2], o.sqrtg[nodes]])
+
+
+SMALL = {
+    "polar": dict(W.polar_disk(), n=(12, 20)),
+    "cylinder": dict(W.closed_cylinder(scale=8)),
+    "horn": W.trumpet_horn(scale=8),
+    "torus": W.torus(scale=8),
+    "bessel_horn": dict(kind="bessel_horn", dim=3, n=(9, 8, 20), qmin=(2.0, 0.0, 0.0), qmax=(150.0, 2 * math.pi, 700.0),
+                        bc_lo=("free", "periodic", "bounceback"), bc_hi=("bounceback", "periodic", "free"),
+                        h_ref=1.0, c=0.2, damp=0.65, params=(0.2, 750.0)),
+    "box3": dict(kind="box", dim=3, n=(7, 9, 11), qmin=(0, 0, 0), qmax=(7.0, 7.2, 14.3),
+                 bc_lo=("bounceback", "fixed", "free"), bc_hi=("fixed", "fixed", "bounceback"), h_ref=1.0, c=0.3,
+                 damp=0.8, params=()),
+    "box2": dict(kind="box", dim=2, n=(13, 5), qmin=(0, 0), qmax=(13.0, 4.0), bc_lo=("periodic", "free"),
+                 bc_hi=("periodic", "bounceback"), h_ref=1.0, c=0.4, damp=1.0, params=()),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_tables_match_oracle(name):
+    geom = SMALL[name]
+    say("tables", name, geom["n"])
+    o = oracle.Oracle(geom)
+    ref = table_from_oracle(o, geom)
+    tab = lbw.Geometry(geom).table()
+    scale = np.maximum(np.abs(ref).max(axis=1, keepdims=True), 1.0)
+    assert np.abs(tab - ref).max() / 1.0 <= 1e-12 * scale.max(), np.abs(tab - ref).max(axis=1)
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_index_maps_bit_exact(name):
+    geom = SMALL[name]
+    say("maps", name)
+    mask, pull = oracle.Oracle(geom).maps()
+    gm, gp = lbw.Geometry(geom).maps()
+    assert np.array_equal(gm, mask) and np.array_equal(gp, pull)
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2, 3])
+def test_index_maps_full_size(idx):
+    geom = W.GEOMETRIES[idx]()
+    say("maps full size", idx, geom["n"])
+    mask, pull = oracle.Oracle(geom).maps()
+    gm, gp = lbw.Geometry(geom).maps()
+    assert np.array_equal(gm, mask) and np.array_equal(gp, pull)
+
+
+def test_stability_bound_matches_oracle_formula():
+    for name, geom in SMALL.items():
+        o = oracle.Oracle(geom)
+        tot = np.zeros(o.N)
+        for a in range(o.dim):
+            m = o.Mhat[a] + (np.abs(o.Mhat[4]) if o.dim == 3 and a in (0, 2) else 0.0)
+            tot += np.where(m <= 1.0, 4.0, (1.0 + m) ** 2 / np.maximum(m, 1e-300))
+        ref = 2.0 / math.sqrt(tot.max())
+        assert abs(lbw.Geometry(geom).stability_bound() / ref - 1.0) < 1e-12, name
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_short_run_all_walls(name):
+    geom = SMALL[name]
+    rng = np.random.default_rng(7)
+    N = W.num_nodes(geom)
+    P0 = rng.uniform(-1, 1, N)
+    probes = rng.integers(0, N, 5)
+    say("short run", name)
+    o = oracle.Oracle(geom)
+    f = o.init(P0)
+    f1 = gpu_run(geom, P0, 1)[2]
+    o.step(f, 1)
+    assert np.abs(f1 - f).max() <= 2e-6 * np.abs(f).max()
+    f, tr = o.run(o.init(P0), 200, probes)
+    _, _, fg, trg = gpu_run(geom, P0, 200, probes)
+    assert rel_l2(fg, f) <= 1e-5
+    assert np.abs(trg - tr).max() <= 1e-5 * np.abs(tr).max()
+
+
+def test_edge_shapes():
+    """Single-node and two-node axes, a node count that is not a multiple of
+    the block size, and every wall code on one grid."""
+    cases = [
+        dict(kind="box", dim=3, n=(1, 5, 3), qmin=(0, 0, 0), qmax=(1.0, 5.0, 3.0),
+             bc_lo=("bounceback", "periodic", "fixed"), bc_hi=("free", "periodic", "bounceback"), h_ref=1.0,
+             c=0.3, damp=0.9, params=()),
+        dict(kind="box", dim=3, n=(2, 1, 1), qmin=(0, 0, 0), qmax=(2.0, 1.0, 1.0),
+             bc_lo=("periodic", "periodic", "periodic"), bc_hi=("periodic", "periodic", "periodic"), h_ref=1.0,
+             c=0.5, damp=1.0, params=()),
+        dict(kind="cylinder", dim=3, n=(17, 3, 5), qmin=(0.3, 0.0, 0.0), qmax=(1.0, 2 * math.pi, 1.0),
+             bc_lo=("free", "periodic", "fixed"), bc_hi=("fixed", "periodic", "free"), h_ref=0.7 / 17, c=0.3,
+             damp=1.0, params=()),
+        dict(kind="polar2d", dim=2, n=(3, 1), qmin=(0.5, 0.0), qmax=(1.0, 2 * math.pi),
+             bc_lo=("bounceback", "periodic"), bc_hi=("fixed", "periodic"), h_ref=1.0 / 6, c=0.4, damp=1.0,
+             params=()),
+    ]
+    for geom in cases:
+        say("edge", geom["kind"], geom["n"])
+        N = W.num_nodes(geom)
+        P0 = np.random.default_rng(3).uniform(-1, 1, N)
+        o = oracle.Oracle(geom)
+        f, tr = o.run(o.init(P0), 100, [0, N - 1])
+        _, _, fg, trg = gpu_run(geom, P0, 100, [0, N - 1])
+        assert rel_l2(fg, f) <= 1e-5, geom
+        assert np.abs(trg - tr).max() <= 1e-5 * max(np.abs(tr).max(), 1e-30)
+        mask, pull = o.maps()
+        gm, gp = lbw.Geometry(geom).maps()
+        assert np.array_equal(gm, mask) and np.array_equal(gp, pull)
+
+
+@pytest.mark.parametrize("idx,scale", [(0, 1), (1, 4), (2, 4), (3, 4)])
+def test_thousand_steps(idx, scale):
+    """Relative L2 error of the populations and of the pressure field after
+    1000 steps (configuration 0 at full size, 1-3 on grids 4x coarser per
+    axis), plus the probe traces."""
+    w = W.workload(idx, scale=scale)
+    geom, P0, probes = w["geom"], w["P0"], w["probes"]
+    say("1000 steps", w["name"], geom["n"])
+    o = oracle.Oracle(geom)
+    f, tr = o.run(o.init(P0), 1000, probes)
+    _, sim, fg, trg = gpu_run(geom, P0, 1000, probes)
+    assert rel_l2(fg, f) <= 1e-5
+    Pg = sim.pressure().cpu().numpy()
+    assert rel_l2(Pg, o.pressure(f)) <= 1e-5
+    assert np.abs(trg - tr).max() <= 1e-5 * np.abs(tr).max()
+
+
+def test_polar_disk_modes_full_run():
+    """Configuration 0 end to end: 2000 steps, probe trace, device FFT mode
+    extraction versus the oracle's trace and extractor."""
+    w = W.workload(0)
+    geom, P0, probes = w["geom"], w["P0"], w["probes"]
+    say("modes", w["name"])
+    o = oracle.Oracle(geom)
+    f, tr = o.run(o.init(P0), w["steps"], probes)
+    g, sim, fg, trg = gpu_run(geom, P0, w["steps"], probes)
+    assert rel_l2(fg, f) <= 1e-5 * 2  # 2000 steps
+    k = 10
+    fo, po = oracle.modes(tr, k)
+    fgpu, pgpu = sim.modes(k)
+    ok = ~np.isnan(fo)
+    assert ok.sum() >= 3
+    assert np.array_equal(ok, ~np.isnan(fgpu))
+    assert np.abs(fgpu[ok] / fo[ok] - 1.0).max() <= 1e-5
+    # the extractor alone, on the same (GPU) trace: FP64 FFT agreement
+    fo2, po2 = oracle.modes(trg, k)
+    assert np.abs(fgpu[ok] / fo2[ok] - 1.0).max() <= 1e-10
+    assert np.abs(pgpu[ok] / po2[ok] - 1.0).max() <= 1e-8
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3])
+def test_full_size_one_step(idx):
+    """Full-size grids in the benchmark's launch configuration: after 20 GPU
+    steps, one oracle step on the GPU state must match the GPU's next step."""
+    w = W.workload(idx)
+    geom, P0 = w["geom"], w["P0"]
+    say("full size one step", w["name"], geom["n"])
+    g = lbw.Geometry(geom)
+    sim = lbw.Simulation(g, P0, w["probes"], t_max=64)
+    sim.step(20)
+    f = sim.populations().double().cpu().numpy()
+    sim.step(1)
+    fg = sim.populations().double().cpu().numpy()
+    o = oracle.Oracle(geom)
+    o.step(f, 1)
+    err = np.abs(fg - f)
+    assert err.max() <= 2e-6 * np.abs(f).max(), err.max()
+    assert rel_l2(fg, f) <= 1e-6
+
+
+def test_full_size_invariant_and_determinism():
+    """Closed cylinder at full size: sum sqrt(g) P stays put (float32
+    rounding only) and two runs are bit-identical."""
+    w = W.workload(1)
+    geom, P0 = w["geom"], w["P0"]
+    say("invariant", w["name"])
+    runs = []
+    for _ in range(2):
+        g = lbw.Geometry(geom)
+        sim = lbw.Simulation(g, P0, w["probes"], t_max=300)
+        I0 = float(sim.populations().double().sum())
+        scale = float(sim.populations().double().abs().sum())
+        sim.step(300)
+        f = sim.populations()
+        I1 = float(f.double().sum())
+        assert abs(I1 - I0) <= 1e-5 * scale
+        runs.append((f.cpu().numpy().copy(), sim.probe()))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_errors_on_device_calls():
+    geom = SMALL["box3"]
+    g = lbw.Geometry(geom)
+    with pytest.raises(lbw.LbwError):
+        lbw.Simulation(g, np.zeros(g.N), probes=[g.N], t_max=4)
+    sim = lbw.Simulation(g, np.zeros(g.N), probes=[0], t_max=4)
+    with pytest.raises(lbw.LbwError):
+        sim.modes(3)  # fewer than 8 rows
+    sim.step(10)  # beyond t_max: runs, records 4 rows
+    assert sim.t == 10 and sim.probe().shape == (4, 1)
+    with pytest.raises(lbw.LbwError):
+        sim.probe(0, 5)
