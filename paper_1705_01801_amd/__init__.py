@@ -53,14 +53,34 @@ class LbwError(RuntimeError):
 _lib = None
 
 
+def _hip_runtimes():
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(line.split()[-1])
+    except OSError:
+        pass
+    return paths
+
+
 def lib():
-    """The loaded HIP library; raises if it has not been built."""
+    """The loaded HIP library; raises if it has not been built.
+
+    torch is imported first so that the library's libamdhip64.so.7
+    dependency resolves to the HIP runtime torch already loaded: streams and
+    device pointers handed over by torch are only valid in that runtime."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("liblbw.so is not built (run paper_1705_01801_amd/build.py); "
                                "there is no fallback path")
+        import torch  # noqa: F401  (loads torch's HIP runtime)
         L = ctypes.CDLL(LIB_PATH)
+        runtimes = _hip_runtimes()
+        if len(runtimes) > 1:
+            raise RuntimeError("two HIP runtimes loaded in one process: %s" % sorted(runtimes))
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         L.lbw_make_geometry.argtypes = [ctypes.POINTER(GeometryDesc), vp, ctypes.POINTER(vp)]
         L.lbw_free_geometry.argtypes = [vp]
