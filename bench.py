@@ -107,6 +107,20 @@ def main():
     bytes_per_launch = 56.0 * N
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
     traffic = read_traffic()
+    # practical ceiling: a device-to-device copy moving the same bytes
+    src = torch.empty(7 * N, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(50):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = bytes_per_launch / (c0.elapsed_time(c1) / 50 / 1e3) / 1e9
+    del src, dst
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
@@ -115,6 +129,8 @@ def main():
                    "c": geom["c"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "copy_ceiling": {"achieved": round(copy_gbs, 1), "unit": "GB/s",
+                         "note": "device copy of the same 56 B/node, torch copy_"},
     }
     if not args.no_cpu_baseline:
         log("bench: oracle baseline, %d steps" % args.cpu_steps)

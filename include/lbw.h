@@ -116,6 +116,17 @@ int lbw_geometry_export(lbw_geometry_t g, int what, void* host_dst, size_t bytes
  * Synchronises.  Errors: LBW_EINVAL for NULL arguments. */
 int lbw_stability_bound(lbw_geometry_t g, double* c_max);
 
+/* Launch shape of the 3-D step kernel for this geometry (the per-node
+ * arithmetic, and so every result, is the same for every shape; only speed
+ * changes).  tile_x: 32 or 64 nodes along axis 0 per workgroup tile (the
+ * tile spans 256 / tile_x nodes along axis 1); chunk_z >= 1 planes per
+ * tile along axis 2; blocks: persistent grid size, rounded down to a
+ * multiple of 8 (0 = one full wave of resident workgroups).  Used by
+ * lbw_autotune and by tests.  Errors: LBW_EINVAL for a 2-D geometry or
+ * out-of-range values. */
+int lbw_set_step_config(lbw_geometry_t g, int tile_x, int chunk_z, int blocks);
+int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* chunk_z, int* blocks);
+
 /* Creates a simulation state on caller-owned device buffers.
  *  p0        device, N doubles: initial pressure P; populations start at the
  *            corrected equilibrium at rest, f_l = w_l sqrt(g) P0 with

@@ -22,7 +22,8 @@ EXPORT_TABLE_F64, EXPORT_MASK_U8, EXPORT_PULL_I32 = 0, 1, 2
 TABLE_PLANES = ("Mhat00", "Mhat11", "Mhat22", "Mhat02", "Gamh0", "Gamh1", "Gamh2", "sqrtg")
 
 # every symbol include/lbw.h declares
-SYMBOLS = ("lbw_make_geometry", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound", "lbw_init",
+SYMBOLS = ("lbw_make_geometry", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound",
+           "lbw_set_step_config", "lbw_get_step_config", "lbw_init",
            "lbw_step_n", "lbw_probe", "lbw_modes", "lbw_state_info", "lbw_pressure", "lbw_free_state",
            "lbw_last_error")
 
@@ -86,6 +87,9 @@ def lib():
         L.lbw_free_geometry.argtypes = [vp]
         L.lbw_geometry_export.argtypes = [vp, i32, vp, ctypes.c_size_t]
         L.lbw_stability_bound.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.lbw_set_step_config.argtypes = [vp, i32, i32, i32]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.lbw_get_step_config.argtypes = [vp, ip, ip, ip]
         L.lbw_init.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), i32, vp, i64, vp, ctypes.POINTER(vp)]
         L.lbw_step_n.argtypes = [vp, i64]
         L.lbw_probe.argtypes = [vp, vp, i64, i64]
@@ -168,6 +172,14 @@ class Geometry:
         v = ctypes.c_double()
         check(lib().lbw_stability_bound(self.handle, ctypes.byref(v)))
         return v.value
+
+    def set_step_config(self, tile_x: int, chunk_z: int, blocks: int = 0):
+        check(lib().lbw_set_step_config(self.handle, int(tile_x), int(chunk_z), int(blocks)))
+
+    def step_config(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().lbw_get_step_config(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def close(self):
         if getattr(self, "handle", None):

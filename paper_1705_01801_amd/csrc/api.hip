@@ -19,6 +19,7 @@ struct lbw_geometry {
     float* tab32 = nullptr;
     hipStream_t stream = nullptr;
     GeomDev dev{};
+    lbw::MarchPlan plan{};  // launch shape of the 3-D step
 };
 
 struct lbw_state {
@@ -169,6 +170,19 @@ int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_
     v.c2_64 = c2;
     v.tab = g->tab32;
     v.sqrtg = g->tab64 + 7 * g->E;
+    if (d.dim == 3) {
+        int dev = 0, cus = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) {
+            (void)hipFree(g->tab64);
+            (void)hipFree(g->tab32);
+            delete g;
+            return hip_fail(e, "lbw_make_geometry");
+        }
+        const int tx = lbw::march_tx_for(v.n0);
+        g->plan = lbw::make_march_plan(v, tx, 16, cus * lbw::march_blocks_per_cu(tx));
+    }
     *out = g;
     return LBW_OK;
 }
@@ -233,6 +247,30 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max) {
     return LBW_OK;
 }
 
+int lbw_set_step_config(lbw_geometry_t g, int tile_x, int chunk_z, int blocks) {
+    if (!g) return fail(LBW_EINVAL, "geometry is NULL");
+    if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
+    if (tile_x != 32 && tile_x != 64) return fail(LBW_EINVAL, "tile_x must be 32 or 64");
+    if (chunk_z < 1 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 1 and blocks >= 0");
+    if (blocks == 0) {
+        int dev = 0, cus = 0;
+        HIP_TRY(hipGetDevice(&dev), "lbw_set_step_config");
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "lbw_set_step_config");
+        blocks = cus * lbw::march_blocks_per_cu(tile_x);
+    }
+    g->plan = lbw::make_march_plan(g->dev, tile_x, chunk_z, blocks);
+    return LBW_OK;
+}
+
+int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* chunk_z, int* blocks) {
+    if (!g) return fail(LBW_EINVAL, "geometry is NULL");
+    if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
+    if (tile_x) *tile_x = g->plan.tx;
+    if (chunk_z) *chunk_z = g->plan.lz;
+    if (blocks) *blocks = g->plan.blocks;
+    return LBW_OK;
+}
+
 int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const int64_t* probes, int n_probes,
              double* trace, int64_t t_max, void* stream, lbw_state_t* out) {
     if (!out) return fail(LBW_EINVAL, "out is NULL");
@@ -274,7 +312,11 @@ int lbw_step_n(lbw_state_t s, int64_t n) {
     if (n < 0) return fail(LBW_EINVAL, "negative step count");
     lbw::ProbeArgs pr{s->d_probes, s->n_probes, s->trace, s->t_max, s->d_tcount};
     for (int64_t i = 0; i < n; ++i) {
-        HIP_TRY(lbw::launch_step(s->g->dev, pr, s->f[s->cur], s->f[1 - s->cur], s->stream), "lbw_step_n");
+        if (s->g->dev.dim == 3)
+            HIP_TRY(lbw::launch_step_march(s->g->dev, pr, s->g->plan, s->f[s->cur], s->f[1 - s->cur], s->stream),
+                    "lbw_step_n");
+        else
+            HIP_TRY(lbw::launch_step(s->g->dev, pr, s->f[s->cur], s->f[1 - s->cur], s->stream), "lbw_step_n");
         s->cur ^= 1;
         s->t += 1;
     }

@@ -62,6 +62,20 @@ struct ProbeArgs {
 };
 hipError_t launch_step(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* fout, hipStream_t st);
 
+// Launch shape of the z-marching D3Q7 kernel.
+struct MarchPlan {
+    int tx, ty;          // tile extent along axes 0 and 1 (tx * ty = 256)
+    int lz;              // planes per chunk along axis 2
+    int ntx, nty, nchunks;
+    int64_t tiles;       // ntx * nty * nchunks
+    int blocks;          // persistent grid size (multiple of 8)
+};
+MarchPlan make_march_plan(const GeomDev& g, int tx, int lz, int blocks);
+int march_tx_for(int n0);
+int march_blocks_per_cu(int tx);
+hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
+                             float* fout, hipStream_t st);
+
 // Spectrum: fills freq/power (device, k each) from trace rows [0, T).
 hipError_t launch_modes(const double* trace, int64_t T, int n_probes, int k, double* work, size_t work_bytes,
                         double* freq, double* power, hipStream_t st);

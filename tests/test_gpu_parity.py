@@ -247,3 +247,32 @@ def test_errors_on_device_calls():
     assert sim.t == 10 and sim.probe().shape == (4, 1)
     with pytest.raises(lbw.LbwError):
         sim.probe(0, 5)
+
+
+def test_launch_shapes_bit_identical():
+    """Tile widths, chunk lengths and grid sizes change only the data
+    movement, never a result: all shapes give bit-identical states, and they
+    match the oracle.  The grid has several x tiles on a periodic axis 0,
+    partial tiles in x and y, and chunk boundaries on a periodic axis 2."""
+    geom = dict(kind="box", dim=3, n=(70, 11, 37), qmin=(0, 0, 0), qmax=(70.0, 8.8, 48.1),
+                bc_lo=("periodic", "fixed", "periodic"), bc_hi=("periodic", "free", "periodic"), h_ref=1.0, c=0.35,
+                damp=1.0, params=())
+    N = W.num_nodes(geom)
+    P0 = np.random.default_rng(12).uniform(-1, 1, N)
+    probes = [0, 5, N - 1]
+    o = oracle.Oracle(geom)
+    f, tr = o.run(o.init(P0), 60, probes)
+    ref = None
+    for tx, lz, blocks in [(64, 16, 0), (32, 1, 8), (32, 5, 16), (64, 37, 24), (64, 64, 8), (32, 7, 0)]:
+        say("launch shape", tx, lz, blocks)
+        g = lbw.Geometry(geom)
+        g.set_step_config(tx, lz, blocks)
+        sim = lbw.Simulation(g, P0, probes, t_max=60)
+        sim.step(60)
+        fg = sim.populations().cpu().numpy()
+        if ref is None:
+            ref = fg.copy()
+            assert rel_l2(fg.astype(np.float64), f) <= 1e-5
+            assert np.abs(sim.probe() - tr).max() <= 1e-5 * np.abs(tr).max()
+        else:
+            assert np.array_equal(fg, ref), (tx, lz, blocks)
