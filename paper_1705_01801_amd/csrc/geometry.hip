@@ -108,9 +108,9 @@ __global__ void geometry_tables_kernel(lbw_geometry_desc d, double* __restrict__
     const double c2 = d.c * d.c;
     float* t = tab32 + (size_t)e * kTabF32;
     t[0] = (float)(c2 * M00);
-    t[1] = (float)(c2 * M11);
+    t[1] = (float)(c2 * M02);
     t[2] = (float)(c2 * M22);
-    t[3] = (float)(c2 * M02);
+    t[3] = (float)(c2 * M11);
     t[4] = (float)(0.5 * c2 * g0);
     t[5] = (float)(0.5 * c2 * g2);
     t[6] = 0.0f;

@@ -9,9 +9,10 @@
 
 namespace lbw {
 
-// Per-entry float table used by the step kernels, 8 floats per (i0, i2)
-// entry: c^2 Mhat00, c^2 Mhat11, c^2 Mhat22, c^2 Mhat02,
-// c^2 Gamh0 / 2, c^2 Gamh2 / 2, 0, 0.
+// Per-entry float table used by the step kernels, 8 floats (32 bytes) per
+// (i0, i2) entry: c^2 Mhat00, c^2 Mhat02, c^2 Mhat22, c^2 Mhat11,
+// c^2 Gamh0 / 2, c^2 Gamh2 / 2, 0, 0.  The pairs an axis-0 neighbour needs
+// (00, 02) and an axis-2 neighbour needs (02, 22) are adjacent.
 constexpr int kTabF32 = 8;
 // FP64 table planes (exported): Mhat00, Mhat11, Mhat22, Mhat02, Gamh0,
 // Gamh1, Gamh2, sqrtg.

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void step_simple_kernel(GeomDev g, ProbeArg
     for (int l = 1; l < Q; ++l) S += f[l];
 
     const float* te = g.tab + (size_t)(i0 + n0 * i2) * kTabF32;
-    const float cM00 = te[0], cM11 = te[1], cM22 = te[2], cM02 = te[3], hG0 = te[4], hG2 = te[5];
+    const float cM00 = te[0], cM02 = te[1], cM22 = te[2], cM11 = te[3], hG0 = te[4], hG2 = te[5];
 
     // axis 0 neighbours: A^{00} and A^{20}
     float A00[2], A20[2];
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void step_simple_kernel(GeomDev g, ProbeArg
             const float Sn = node_sum<Q>(fin, N, n + (j - i0));
             const float* tn = g.tab + (size_t)(j + n0 * i2) * kTabF32;
             A00[side] = tn[0] * Sn;
-            A20[side] = tn[3] * Sn;
+            A20[side] = tn[1] * Sn;
         } else {
             const float sg = wall == LBW_BC_FIXED ? -1.0f : 1.0f;
             A00[side] = sg * cM00 * S;
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void step_simple_kernel(GeomDev g, ProbeArg
                 const float Sn = node_sum<Q>(fin, N, n + (int64_t)(j - i2) * plane);
                 const float* tn = g.tab + (size_t)(i0 + n0 * j) * kTabF32;
                 A22[side] = tn[2] * Sn;
-                A02[side] = tn[3] * Sn;
+                A02[side] = tn[1] * Sn;
             } else {
                 const float sg = wall == LBW_BC_FIXED ? -1.0f : 1.0f;
                 A22[side] = sg * cM22 * S;

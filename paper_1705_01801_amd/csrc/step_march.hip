@@ -1,4 +1,4 @@
-// D3Q7 step kernel for MI355X: z-marching column tiles with an LDS halo.
+// D3Q7 step kernel for MI355X: z-marching column tiles with LDS staging.
 //
 // Same arithmetic as the per-node description in step.hip (BGK tau = 1/2,
 // corrected equilibrium, Christoffel and metric-gradient forcing, push
@@ -6,15 +6,20 @@
 //  - a workgroup of 256 threads owns a TX x TY tile of (axis 0, axis 1)
 //    columns and walks a chunk of LZ planes along axis 2;
 //  - each thread keeps its own column's populations and S = sum_l f_l of
-//    planes z-1, z, z+1 in registers, so axis-2 neighbours cost nothing;
-//  - S of the tile plus a one-node ring is staged in LDS (double-buffered
-//    by plane parity) for the axis-0 and axis-1 neighbours; ring nodes are
+//    planes z-1, z, z+1 in registers, so axis-2 neighbours cost no loads;
+//  - S of the tile plus a one-node ring is staged in LDS (two plane slots)
+//    for the axis-0 and axis-1 neighbours; the ring's populations are
 //    loaded by the first 2 TX + 2 TY threads;
-//  - the next plane's populations and coefficient entry are loaded before
-//    the current plane is computed, so their latency hides behind it;
+//  - the coefficient row of a plane (entries x0-1 .. x0+TX, 32 bytes each)
+//    is staged in LDS (three plane slots: z, z+1 and the one being filled),
+//    so a node reads its own and its axis-0 neighbours' coefficients there;
+//  - populations, ring and coefficient row of plane z+2 (z+1 for the ring)
+//    are loaded before plane z is computed and stored after it, so their
+//    latency hides behind the computation;
 //  - a persistent grid walks the tiles; each XCD (blocks b with the same
 //    b mod 8) gets one contiguous range of tiles, so ring and chunk-boundary
 //    planes shared by neighbouring tiles are re-read from the same L2.
+// Node offsets are 32-bit (the library keeps Q * N below 2^31).
 #include "lbw_internal.h"
 
 namespace lbw {
@@ -23,7 +28,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;
 
-__device__ inline void load7(const float* __restrict__ f, int64_t N, int64_t n, float v[7]) {
+__device__ inline void load7(const float* __restrict__ f, uint32_t N, uint32_t n, float v[7]) {
 #pragma unroll
     for (int l = 0; l < 7; ++l) v[l] = f[l * N + n];
 }
@@ -49,34 +54,42 @@ __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* 
     if (threadIdx.x == 0) *(volatile int64_t*)pr.tcount = t + 1;
 }
 
+// value beyond a wall: mirrored, odd for fixed walls
+__device__ inline float ghost(int wall, float v) { return wall == LBW_BC_FIXED ? -v : v; }
+
+__device__ inline float bounce(int wall, float damp, float out_l, float own_lb) {
+    return wall == LBW_BC_BOUNCEBACK ? damp * out_l : (wall == LBW_BC_FREE ? own_lb : -out_l);
+}
+
 template <int TX>
 __global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
     constexpr int TY = kThreads / TX;
     constexpr int W = TX + 2;
-    __shared__ float lds[2][(TY + 2) * W];
+    __shared__ float sS[2][(TY + 2) * W];
+    __shared__ float4 sE[3][W][2];
 
     if (blockIdx.x == 0) probe_block(g, pr, fin);
 
     const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
-    const int64_t N = g.N;
-    const int64_t plane = (int64_t)n0 * n1;
+    const uint32_t N = (uint32_t)g.N;
+    const uint32_t plane = (uint32_t)n0 * (uint32_t)n1;
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     const float c2 = g.c2, two_w0 = g.two_w0, damp = g.damp;
+    const float4* __restrict__ tab4 = reinterpret_cast<const float4*>(g.tab);
 
-    // tiles of this block: XCD-contiguous ranges
     const int xcd = blockIdx.x % kXcds;
     const int slot = blockIdx.x / kXcds;
     const int per_xcd_blocks = gridDim.x / kXcds;
-    const int64_t t_begin = (int64_t)plan.tiles * xcd / kXcds;
-    const int64_t t_end = (int64_t)plan.tiles * (xcd + 1) / kXcds;
+    const int t_begin = (int)(plan.tiles * xcd / kXcds);
+    const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
 
-    for (int64_t tile = t_begin + slot; tile < t_end; tile += per_xcd_blocks) {
-        const int tx = (int)(tile % plan.ntx);
-        const int64_t r1 = tile / plan.ntx;
-        const int ty = (int)(r1 % plan.nty);
-        const int chunk = (int)(r1 / plan.nty);
+    for (int tile = t_begin + slot; tile < t_end; tile += per_xcd_blocks) {
+        const int tx = tile % plan.ntx;
+        const int r1 = tile / plan.ntx;
+        const int ty = r1 % plan.nty;
+        const int chunk = r1 / plan.nty;
         const int x0 = tx * TX, y0 = ty * TY;
         const int z0 = chunk * plan.lz;
         const int z1 = min(z0 + plan.lz, n2);
@@ -84,159 +97,163 @@ __global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeAr
         const int hgt = min(TY, n1 - y0);
         const int x = x0 + lx, y = y0 + ly;
         const bool active = lx < wdt && ly < hgt;
-        const int64_t col = (int64_t)x + (int64_t)n0 * y;  // node index at plane 0
+        const uint32_t col = (uint32_t)x + (uint32_t)n0 * (uint32_t)y;
 
-        // wall / wrap information of this thread's links in x and y
         int wx_p = 0, wx_m = 0, wy_p = 0, wy_m = 0;
         const int jx_p = link_coord(x, +1, n0, g.bc_lo[0], g.bc_hi[0], &wx_p);
         const int jx_m = link_coord(x, -1, n0, g.bc_lo[0], g.bc_hi[0], &wx_m);
         const int jy_p = link_coord(y, +1, n1, g.bc_lo[1], g.bc_hi[1], &wy_p);
         const int jy_m = link_coord(y, -1, n1, g.bc_lo[1], g.bc_hi[1], &wy_m);
 
-        // ring node handled by this thread (if any): position in the LDS
-        // window and its (wrapped) global coordinates
+        // ring node of this thread: LDS position and wrapped column, or -1
         int ring_lds = -1;
-        int64_t ring_col = 0;
+        uint32_t ring_col = 0;
         {
             const int r = threadIdx.x;
-            int rx = 0, ry = 0, sx = 0, sy = 0;  // sx, sy: LDS window coords (1-based interior)
+            int rx = 0, ry = 0, sx = 0, sy = 0;
             bool have = false;
-            if (r < wdt) {  // below
+            if (r < wdt) {
                 rx = x0 + r; ry = y0 - 1; sx = r + 1; sy = 0; have = true;
-            } else if (r >= TX && r < TX + wdt) {  // above
+            } else if (r >= TX && r < TX + wdt) {
                 rx = x0 + (r - TX); ry = y0 + hgt; sx = r - TX + 1; sy = hgt + 1; have = true;
-            } else if (r >= 2 * TX && r < 2 * TX + hgt) {  // left
+            } else if (r >= 2 * TX && r < 2 * TX + hgt) {
                 rx = x0 - 1; ry = y0 + (r - 2 * TX); sx = 0; sy = r - 2 * TX + 1; have = true;
-            } else if (r >= 2 * TX + TY && r < 2 * TX + TY + hgt) {  // right
+            } else if (r >= 2 * TX + TY && r < 2 * TX + TY + hgt) {
                 rx = x0 + wdt; ry = y0 + (r - 2 * TX - TY); sx = wdt + 1; sy = r - 2 * TX - TY + 1; have = true;
             }
             if (have) {
                 int w = 0;
-                const int gx = rx < 0 || rx >= n0 ? link_coord(rx < 0 ? 0 : n0 - 1, rx < 0 ? -1 : 1, n0, g.bc_lo[0],
-                                                               g.bc_hi[0], &w)
-                                                  : rx;
-                const int gy = ry < 0 || ry >= n1 ? link_coord(ry < 0 ? 0 : n1 - 1, ry < 0 ? -1 : 1, n1, g.bc_lo[1],
-                                                               g.bc_hi[1], &w)
-                                                  : ry;
+                const int gx = rx < 0 || rx >= n0
+                                   ? link_coord(rx < 0 ? 0 : n0 - 1, rx < 0 ? -1 : 1, n0, g.bc_lo[0], g.bc_hi[0], &w)
+                                   : rx;
+                const int gy = ry < 0 || ry >= n1
+                                   ? link_coord(ry < 0 ? 0 : n1 - 1, ry < 0 ? -1 : 1, n1, g.bc_lo[1], g.bc_hi[1], &w)
+                                   : ry;
                 if (gx >= 0 && gy >= 0) {
                     ring_lds = sy * W + sx;
-                    ring_col = (int64_t)gx + (int64_t)n0 * gy;
+                    ring_col = (uint32_t)gx + (uint32_t)n0 * (uint32_t)gy;
                 }
             }
         }
         const int my_lds = (ly + 1) * W + (lx + 1);
 
-        // wrapped plane index (or -1 beyond a wall)
-        auto zlink = [&](int z, int s, int* wall) { return link_coord(z, s, n2, g.bc_lo[2], g.bc_hi[2], wall); };
-        auto entry = [&](int xx, int zz) { return g.tab + (size_t)(xx + n0 * zz) * kTabF32; };
+        // coefficient-row loader: thread t < wdt + 2 stages entry x0 - 1 + t
+        int erow_x = -1;
+        if ((int)threadIdx.x < wdt + 2) {
+            const int ex = x0 - 1 + (int)threadIdx.x;
+            int w = 0;
+            erow_x = ex < 0 || ex >= n0
+                         ? link_coord(ex < 0 ? 0 : n0 - 1, ex < 0 ? -1 : 1, n0, g.bc_lo[0], g.bc_hi[0], &w)
+                         : ex;
+        }
 
-        // ---- prologue ----
-        int wz_dummy = 0;
-        const int zm0 = zlink(z0, -1, &wz_dummy);
+        int wz = 0;
+        const int zm0 = link_coord(z0, -1, n2, g.bc_lo[2], g.bc_hi[2], &wz);
+        const int zp0 = link_coord(z0, +1, n2, g.bc_lo[2], g.bc_hi[2], &wz);
+
+        // ---- prologue: planes z0-1 (S only), z0, z0+1 ----
         float fc[7], fnx[7], tmp[7];
         float Sm = 0.f, Sc = 0.f, Sp = 0.f;
-        float em22 = 0.f, em02 = 0.f;
-        float ec[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, ep[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float2 em = make_float2(0.f, 0.f);  // (c^2 Mhat02, c^2 Mhat22) at z-1
         if (active) {
             if (zm0 >= 0) {
-                load7(fin, N, col + zm0 * plane, tmp);
+                load7(fin, N, col + (uint32_t)zm0 * plane, tmp);
                 Sm = sum7(tmp);
-                const float* e = entry(x, zm0);
-                em22 = e[2];
-                em02 = e[3];
+                const float4 e = tab4[2 * (x + n0 * zm0)];
+                em = make_float2(e.y, e.z);
             }
-            load7(fin, N, col + z0 * plane, fc);
+            load7(fin, N, col + (uint32_t)z0 * plane, fc);
             Sc = sum7(fc);
-            const float* e = entry(x, z0);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) ec[i] = e[i];
+            if (zp0 >= 0) {
+                load7(fin, N, col + (uint32_t)zp0 * plane, fnx);
+                Sp = sum7(fnx);
+            }
         }
-        int wdum = 0;
-        const int zp0 = zlink(z0, +1, &wdum);
-        if (active && zp0 >= 0) {
-            load7(fin, N, col + zp0 * plane, fnx);
-            Sp = sum7(fnx);
-            const float* e = entry(x, zp0);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) ep[i] = e[i];
+        if (erow_x >= 0) {
+            const int e0 = 2 * (erow_x + n0 * z0);
+            sE[0][threadIdx.x][0] = tab4[e0];
+            sE[0][threadIdx.x][1] = tab4[e0 + 1];
+            if (zp0 >= 0) {
+                const int e1 = 2 * (erow_x + n0 * zp0);
+                sE[1][threadIdx.x][0] = tab4[e1];
+                sE[1][threadIdx.x][1] = tab4[e1 + 1];
+            }
         }
         if (ring_lds >= 0) {
-            load7(fin, N, ring_col + z0 * plane, tmp);
-            lds[z0 & 1][ring_lds] = sum7(tmp);
+            load7(fin, N, ring_col + (uint32_t)z0 * plane, tmp);
+            sS[0][ring_lds] = sum7(tmp);
         }
-        if (active) lds[z0 & 1][my_lds] = Sc;
+        if (active) sS[0][my_lds] = Sc;
 
+        int es = 0;  // coefficient-row slot of plane z (z+1 in es+1 mod 3)
         for (int z = z0; z < z1; ++z) {
-            const int b = z & 1;
+            const int sb = (z - z0) & 1;
+            const int es1 = es == 2 ? 0 : es + 1;
+            const int es2 = es1 == 2 ? 0 : es1 + 1;
             int wz_p = 0, wz_m = 0;
-            const int jz_p = zlink(z, +1, &wz_p);
-            const int jz_m = zlink(z, -1, &wz_m);
-            // prefetch: own column at z+2 (needed while z+1 < z1), ring at z+1
-            float fnn[7], hr[7];
-            float en[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const int jz_p = link_coord(z, +1, n2, g.bc_lo[2], g.bc_hi[2], &wz_p);
+            const int jz_m = link_coord(z, -1, n2, g.bc_lo[2], g.bc_hi[2], &wz_m);
+            const bool more = z + 1 < z1;
             int wq = 0;
-            const int zq = jz_p >= 0 && z + 1 < z1 ? zlink(jz_p, +1, &wq) : -1;
-            if (active && zq >= 0) {
-                load7(fin, N, col + zq * plane, fnn);
-                const float* e = entry(x, zq);
-#pragma unroll
-                for (int i = 0; i < 6; ++i) en[i] = e[i];
+            const int zq = more ? link_coord(jz_p, +1, n2, g.bc_lo[2], g.bc_hi[2], &wq) : -1;
+
+            // prefetch plane zq (own column, coefficient row) and plane z+1 (ring)
+            float fnn[7], hr[7];
+            float4 ea = make_float4(0.f, 0.f, 0.f, 0.f), eb = ea;
+            if (active && zq >= 0) load7(fin, N, col + (uint32_t)zq * plane, fnn);
+            if (erow_x >= 0 && zq >= 0) {
+                const int e2 = 2 * (erow_x + n0 * zq);
+                ea = tab4[e2];
+                eb = tab4[e2 + 1];
             }
-            const bool ring_next = ring_lds >= 0 && z + 1 < z1;
-            if (ring_next) load7(fin, N, ring_col + jz_p * plane, hr);
-            float nx00p = 0.f, nx02p = 0.f, nx00m = 0.f, nx02m = 0.f;
-            if (active) {
-                if (jx_p >= 0) {
-                    const float* e = entry(jx_p, z);
-                    nx00p = e[0];
-                    nx02p = e[3];
-                }
-                if (jx_m >= 0) {
-                    const float* e = entry(jx_m, z);
-                    nx00m = e[0];
-                    nx02m = e[3];
-                }
-            }
+            const bool ring_next = ring_lds >= 0 && more;
+            if (ring_next) load7(fin, N, ring_col + (uint32_t)jz_p * plane, hr);
             __syncthreads();
 
             if (active) {
-                const float* L = lds[b];
+                const float* L = sS[sb];
                 const float S = Sc;
-                const float cM00 = ec[0], cM11 = ec[1], cM22 = ec[2], cM02 = ec[3], hG0 = ec[4], hG2 = ec[5];
-                float A00p, A00m, A20p, A20m, A11p, A11m, A22p, A22m, A02p, A02m;
+                const float4 e_lo = sE[es][lx + 1][0];  // 00, 02, 22, 11
+                const float4 e_hi = sE[es][lx + 1][1];  // g0/2, g2/2, 0, 0
+                const float cM00 = e_lo.x, cM02 = e_lo.y, cM22 = e_lo.z, cM11 = e_lo.w;
+                const float hG0 = e_hi.x, hG2 = e_hi.y;
+                float A00p, A00m, A20p, A20m, A22p, A22m, A02p, A02m;
                 if (jx_p >= 0) {
+                    const float4 en = sE[es][lx + 2][0];
                     const float Sn = L[my_lds + 1];
-                    A00p = nx00p * Sn;
-                    A20p = nx02p * Sn;
+                    A00p = en.x * Sn;
+                    A20p = en.y * Sn;
                 } else {
-                    const float sg = wx_p == LBW_BC_FIXED ? -S : S;
+                    const float sg = ghost(wx_p, S);
                     A00p = cM00 * sg;
                     A20p = cM02 * sg;
                 }
                 if (jx_m >= 0) {
+                    const float4 en = sE[es][lx][0];
                     const float Sn = L[my_lds - 1];
-                    A00m = nx00m * Sn;
-                    A20m = nx02m * Sn;
+                    A00m = en.x * Sn;
+                    A20m = en.y * Sn;
                 } else {
-                    const float sg = wx_m == LBW_BC_FIXED ? -S : S;
+                    const float sg = ghost(wx_m, S);
                     A00m = cM00 * sg;
                     A20m = cM02 * sg;
                 }
-                A11p = cM11 * (jy_p >= 0 ? L[my_lds + W] : (wy_p == LBW_BC_FIXED ? -S : S));
-                A11m = cM11 * (jy_m >= 0 ? L[my_lds - W] : (wy_m == LBW_BC_FIXED ? -S : S));
+                const float A11p = cM11 * (jy_p >= 0 ? L[my_lds + W] : ghost(wy_p, S));
+                const float A11m = cM11 * (jy_m >= 0 ? L[my_lds - W] : ghost(wy_m, S));
                 if (jz_p >= 0) {
-                    A22p = ep[2] * Sp;
-                    A02p = ep[3] * Sp;
+                    const float4 en = sE[es1][lx + 1][0];
+                    A02p = en.y * Sp;
+                    A22p = en.z * Sp;
                 } else {
-                    const float sg = wz_p == LBW_BC_FIXED ? -S : S;
+                    const float sg = ghost(wz_p, S);
                     A22p = cM22 * sg;
                     A02p = cM02 * sg;
                 }
                 if (jz_m >= 0) {
-                    A22m = em22 * Sm;
-                    A02m = em02 * Sm;
+                    A02m = em.x * Sm;
+                    A22m = em.y * Sm;
                 } else {
-                    const float sg = wz_m == LBW_BC_FIXED ? -S : S;
+                    const float sg = ghost(wz_m, S);
                     A22m = cM22 * sg;
                     A02m = cM02 * sg;
                 }
@@ -253,47 +270,43 @@ __global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeAr
                 fs[5] = cs + K2 - fc[5];
                 fs[6] = cs - K2 - fc[6];
 
-                const int64_t n = col + (int64_t)z * plane;
+                const uint32_t n = col + (uint32_t)z * plane;
                 fout[n] = fs[0];
-                // +-e0
-                if (jx_p >= 0) fout[1 * N + n + (jx_p - x)] = fs[1];
-                else fout[2 * N + n] = wx_p == LBW_BC_BOUNCEBACK ? damp * fs[1] : (wx_p == LBW_BC_FREE ? fs[2] : -fs[1]);
-                if (jx_m >= 0) fout[2 * N + n + (jx_m - x)] = fs[2];
-                else fout[1 * N + n] = wx_m == LBW_BC_BOUNCEBACK ? damp * fs[2] : (wx_m == LBW_BC_FREE ? fs[1] : -fs[2]);
-                // +-e1
-                if (jy_p >= 0) fout[3 * N + n + (int64_t)(jy_p - y) * n0] = fs[3];
-                else fout[4 * N + n] = wy_p == LBW_BC_BOUNCEBACK ? damp * fs[3] : (wy_p == LBW_BC_FREE ? fs[4] : -fs[3]);
-                if (jy_m >= 0) fout[4 * N + n + (int64_t)(jy_m - y) * n0] = fs[4];
-                else fout[3 * N + n] = wy_m == LBW_BC_BOUNCEBACK ? damp * fs[4] : (wy_m == LBW_BC_FREE ? fs[3] : -fs[4]);
-                // +-e2
-                if (jz_p >= 0) fout[5 * N + col + (int64_t)jz_p * plane] = fs[5];
-                else fout[6 * N + n] = wz_p == LBW_BC_BOUNCEBACK ? damp * fs[5] : (wz_p == LBW_BC_FREE ? fs[6] : -fs[5]);
-                if (jz_m >= 0) fout[6 * N + col + (int64_t)jz_m * plane] = fs[6];
-                else fout[5 * N + n] = wz_m == LBW_BC_BOUNCEBACK ? damp * fs[6] : (wz_m == LBW_BC_FREE ? fs[5] : -fs[6]);
+                if (jx_p >= 0) fout[1 * N + n + (uint32_t)(jx_p - x)] = fs[1];
+                else fout[2 * N + n] = bounce(wx_p, damp, fs[1], fs[2]);
+                if (jx_m >= 0) fout[2 * N + n + (uint32_t)(jx_m - x)] = fs[2];
+                else fout[1 * N + n] = bounce(wx_m, damp, fs[2], fs[1]);
+                if (jy_p >= 0) fout[3 * N + n + (uint32_t)((jy_p - y) * n0)] = fs[3];
+                else fout[4 * N + n] = bounce(wy_p, damp, fs[3], fs[4]);
+                if (jy_m >= 0) fout[4 * N + n + (uint32_t)((jy_m - y) * n0)] = fs[4];
+                else fout[3 * N + n] = bounce(wy_m, damp, fs[4], fs[3]);
+                if (jz_p >= 0) fout[5 * N + col + (uint32_t)jz_p * plane] = fs[5];
+                else fout[6 * N + n] = bounce(wz_p, damp, fs[5], fs[6]);
+                if (jz_m >= 0) fout[6 * N + col + (uint32_t)jz_m * plane] = fs[6];
+                else fout[5 * N + n] = bounce(wz_m, damp, fs[6], fs[5]);
+                em = make_float2(cM02, cM22);
             }
 
-            // stage plane z+1 and rotate the register window
-            if (z + 1 < z1) {
-                if (ring_next) lds[b ^ 1][ring_lds] = sum7(hr);
+            if (more) {
+                if (ring_next) sS[sb ^ 1][ring_lds] = sum7(hr);
+                if (erow_x >= 0 && zq >= 0) {
+                    sE[es2][threadIdx.x][0] = ea;
+                    sE[es2][threadIdx.x][1] = eb;
+                }
                 if (active) {
-                    lds[b ^ 1][my_lds] = Sp;
+                    sS[sb ^ 1][my_lds] = Sp;
                     Sm = Sc;
                     Sc = Sp;
-                    em22 = ec[2];
-                    em02 = ec[3];
-#pragma unroll
-                    for (int i = 0; i < 6; ++i) ec[i] = ep[i];
 #pragma unroll
                     for (int l = 0; l < 7; ++l) fc[l] = fnx[l];
                     if (zq >= 0) {
 #pragma unroll
                         for (int l = 0; l < 7; ++l) fnx[l] = fnn[l];
                         Sp = sum7(fnn);
-#pragma unroll
-                        for (int i = 0; i < 6; ++i) ep[i] = en[i];
                     }
                 }
             }
+            es = es1;
         }
         __syncthreads();  // LDS reuse by the next tile
     }
