@@ -90,7 +90,10 @@ def main():
     N = W.num_nodes(geom)
     g = lbw.Geometry(geom)
     sim = lbw.Simulation(g, w["P0"], w["probes"], t_max=args.warmup + args.steps)
-    log("bench: %s, %d nodes, warmup %d, steps %d" % (w["name"], N, args.warmup, args.steps))
+    tuned_us = sim.autotune(reps=20)
+    tile = g.step_config()
+    log("bench: %s, %d nodes, warmup %d, steps %d, tuned shape %s (%.2f us)" % (w["name"], N, args.warmup,
+                                                                             args.steps, tile, tuned_us))
     sim.step(args.warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -126,7 +129,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w["name"], "nodes": N, "lattice": "D3Q7", "probes": int(len(w["probes"])),
-                   "c": geom["c"]},
+                   "c": geom["c"], "launch": {"tile_x": tile[0], "chunk_z": tile[1], "blocks": tile[2],
+                                              "graph_block": 32}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "copy_ceiling": {"achieved": round(copy_gbs, 1), "unit": "GB/s",

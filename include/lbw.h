@@ -151,6 +151,24 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
  * Errors: LBW_EINVAL for n < 0, LBW_EDEVICE on a launch failure. */
 int lbw_step_n(lbw_state_t s, int64_t n);
 
+/* Picks the fastest launch shape of the 3-D step kernel for this state's
+ * geometry by timing candidates (tile_x 32/64, chunk_z 4..64, one and two
+ * waves of resident workgroups) for reps launches each with HIP events.  The
+ * candidates run real ping-pong steps (each launch reads what the previous
+ * one wrote) from the state's current buffer into its other buffer and a
+ * temporary buffer of Q*N floats (allocated for the call), with
+ * probe recording off; the current buffer, step count and trace are
+ * unchanged.  The choice is stored in the geometry and in a per-process
+ * cache keyed by the grid shape, which later geometries of that shape start
+ * from.  Synchronises.  best_us (may be NULL) receives the best time per
+ * step in microseconds.  Errors: LBW_EINVAL (2-D geometry, reps < 1). */
+int lbw_autotune(lbw_state_t s, int reps, double* best_us);
+
+/* Number of steps lbw_step_n captures into one HIP graph and replays
+ * (0 disables graphs; default 32).  Graphs are rebuilt when the launch
+ * shape changes. */
+int lbw_set_graph_block(lbw_state_t s, int steps);
+
 /* Copies trace rows [t0, t1) (t1 <= recorded rows) to host memory,
  * n_probes doubles per row.  Synchronises.  Returns LBW_EUNSTABLE (after
  * copying) when a copied value is not finite. */

@@ -24,8 +24,8 @@ TABLE_PLANES = ("Mhat00", "Mhat11", "Mhat22", "Mhat02", "Gamh0", "Gamh1", "Gamh2
 # every symbol include/lbw.h declares
 SYMBOLS = ("lbw_make_geometry", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound",
            "lbw_set_step_config", "lbw_get_step_config", "lbw_init",
-           "lbw_step_n", "lbw_probe", "lbw_modes", "lbw_state_info", "lbw_pressure", "lbw_free_state",
-           "lbw_last_error")
+           "lbw_step_n", "lbw_autotune", "lbw_set_graph_block", "lbw_probe", "lbw_modes", "lbw_state_info",
+           "lbw_pressure", "lbw_free_state", "lbw_last_error")
 
 
 class GeometryDesc(ctypes.Structure):
@@ -92,6 +92,8 @@ def lib():
         L.lbw_get_step_config.argtypes = [vp, ip, ip, ip]
         L.lbw_init.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), i32, vp, i64, vp, ctypes.POINTER(vp)]
         L.lbw_step_n.argtypes = [vp, i64]
+        L.lbw_autotune.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+        L.lbw_set_graph_block.argtypes = [vp, i32]
         L.lbw_probe.argtypes = [vp, vp, i64, i64]
         L.lbw_modes.argtypes = [vp, i32, vp, vp]
         L.lbw_state_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(vp)]
@@ -220,6 +222,16 @@ class Simulation:
 
     def step(self, n: int = 1):
         check(lib().lbw_step_n(self.handle, int(n)))
+
+    def autotune(self, reps: int = 20) -> float:
+        """Times the step kernel's launch shapes on this state (unchanged by
+        the timing) and keeps the fastest; returns microseconds per step."""
+        us = ctypes.c_double()
+        check(lib().lbw_autotune(self.handle, int(reps), ctypes.byref(us)))
+        return us.value
+
+    def set_graph_block(self, steps: int):
+        check(lib().lbw_set_graph_block(self.handle, int(steps)))
 
     @property
     def t(self) -> int:

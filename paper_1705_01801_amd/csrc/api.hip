@@ -3,7 +3,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "lbw_internal.h"
@@ -20,6 +23,7 @@ struct lbw_geometry {
     hipStream_t stream = nullptr;
     GeomDev dev{};
     lbw::MarchPlan plan{};  // launch shape of the 3-D step
+    int plan_version = 0;   // bumped on every change of plan
 };
 
 struct lbw_state {
@@ -37,11 +41,20 @@ struct lbw_state {
     size_t mode_work_bytes = 0;
     double* mode_out = nullptr;  // device, 2 * mode_k
     int mode_k = 0;
+    int64_t* d_scratch_count = nullptr;  // step counter for timing launches
+    // graph-captured step blocks, one per starting buffer parity
+    int graph_block = 32;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_version = -1;
 };
 
 namespace {
 
 thread_local std::string g_err;
+
+// tuned launch shapes per grid shape (n0, n1, n2) -> (tile_x, chunk_z, blocks)
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, std::tuple<int, int, int>> g_tuned;
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -183,6 +196,11 @@ int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_
         }
         const int tx = lbw::march_tx_for(v.n0);
         g->plan = lbw::make_march_plan(v, tx, 16, cus * lbw::march_blocks_per_cu(tx));
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(std::make_tuple(v.n0, v.n1, v.n2));
+        if (it != g_tuned.end())
+            g->plan = lbw::make_march_plan(v, std::get<0>(it->second), std::get<1>(it->second),
+                                           std::get<2>(it->second));
     }
     *out = g;
     return LBW_OK;
@@ -260,6 +278,7 @@ int lbw_set_step_config(lbw_geometry_t g, int tile_x, int chunk_z, int blocks) {
         blocks = cus * lbw::march_blocks_per_cu(tile_x);
     }
     g->plan = lbw::make_march_plan(g->dev, tile_x, chunk_z, blocks);
+    g->plan_version += 1;
     return LBW_OK;
 }
 
@@ -291,6 +310,7 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
     s->trace = trace;
     s->stream = (hipStream_t)stream;
     hipError_t e = hipMalloc(&s->d_tcount, sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&s->d_scratch_count, sizeof(int64_t));
     if (e == hipSuccess && n_probes > 0) e = hipMalloc(&s->d_probes, sizeof(int64_t) * n_probes);
     if (e == hipSuccess && n_probes > 0)
         e = hipMemcpyAsync(s->d_probes, probes, sizeof(int64_t) * n_probes, hipMemcpyHostToDevice, s->stream);
@@ -300,6 +320,7 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
     if (e == hipSuccess && n_probes > 0) e = hipStreamSynchronize(s->stream);  // host probe list may go away
     if (e != hipSuccess) {
         (void)hipFree(s->d_tcount);
+        (void)hipFree(s->d_scratch_count);
         (void)hipFree(s->d_probes);
         delete s;
         return hip_fail(e, "lbw_init");
@@ -308,19 +329,147 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
     return LBW_OK;
 }
 
+namespace {
+
+hipError_t launch_one(lbw_state* s, const lbw::ProbeArgs& pr, int from, hipStream_t st) {
+    if (s->g->dev.dim == 3)
+        return lbw::launch_step_march(s->g->dev, pr, s->g->plan, s->f[from], s->f[1 - from], st);
+    return lbw::launch_step(s->g->dev, pr, s->f[from], s->f[1 - from], st);
+}
+
+void drop_graphs(lbw_state* s) {
+    for (auto& gx : s->graph) {
+        if (gx) (void)hipGraphExecDestroy(gx);
+        gx = nullptr;
+    }
+}
+
+// Captures graph_block steps starting from buffer `from` on a private
+// stream (capture only records; nothing runs there).
+hipError_t build_graph(lbw_state* s, int from) {
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    lbw::ProbeArgs pr{s->d_probes, s->n_probes, s->trace, s->t_max, s->d_tcount};
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        int cur = from;
+        hipError_t le = hipSuccess;
+        for (int i = 0; i < s->graph_block && le == hipSuccess; ++i) {
+            le = launch_one(s, pr, cur, cap);
+            cur ^= 1;
+        }
+        e = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&s->graph[from], graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    return e;
+}
+
+}  // namespace
+
 int lbw_step_n(lbw_state_t s, int64_t n) {
     if (!s) return fail(LBW_EINVAL, "state is NULL");
     if (n < 0) return fail(LBW_EINVAL, "negative step count");
     lbw::ProbeArgs pr{s->d_probes, s->n_probes, s->trace, s->t_max, s->d_tcount};
+    const int K = s->graph_block;
+    if (K > 0 && n >= K) {
+        if (s->graph_version != s->g->plan_version) {
+            drop_graphs(s);
+            s->graph_version = s->g->plan_version;
+        }
+        while (n >= K) {
+            if (!s->graph[s->cur]) HIP_TRY(build_graph(s, s->cur), "lbw_step_n: graph capture");
+            HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream), "lbw_step_n: graph launch");
+            if (K & 1) s->cur ^= 1;
+            s->t += K;
+            n -= K;
+        }
+    }
     for (int64_t i = 0; i < n; ++i) {
-        if (s->g->dev.dim == 3)
-            HIP_TRY(lbw::launch_step_march(s->g->dev, pr, s->g->plan, s->f[s->cur], s->f[1 - s->cur], s->stream),
-                    "lbw_step_n");
-        else
-            HIP_TRY(lbw::launch_step(s->g->dev, pr, s->f[s->cur], s->f[1 - s->cur], s->stream), "lbw_step_n");
+        HIP_TRY(launch_one(s, pr, s->cur, s->stream), "lbw_step_n");
         s->cur ^= 1;
         s->t += 1;
     }
+    return LBW_OK;
+}
+
+int lbw_set_graph_block(lbw_state_t s, int steps) {
+    if (!s) return fail(LBW_EINVAL, "state is NULL");
+    if (steps < 0 || steps > 4096) return fail(LBW_EINVAL, "graph block must be in [0, 4096]");
+    HIP_TRY(hipStreamSynchronize(s->stream), "lbw_set_graph_block");
+    drop_graphs(s);
+    s->graph_block = steps;
+    return LBW_OK;
+}
+
+int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
+    if (!s) return fail(LBW_EINVAL, "state is NULL");
+    if (reps < 1) return fail(LBW_EINVAL, "reps must be >= 1");
+    lbw_geometry* g = s->g;
+    if (g->dev.dim != 3) return fail(LBW_EINVAL, "autotune applies to 3-D geometries");
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev), "lbw_autotune");
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "lbw_autotune");
+    // Candidates are timed on real ping-pong traffic: the first launch reads
+    // the current buffer and writes the state's other buffer, later launches
+    // alternate between that buffer and a temporary one, so every launch
+    // reads what the previous one wrote (as lbw_step_n does) and the current
+    // buffer is never written.
+    float* tmp = nullptr;
+    HIP_TRY(hipMalloc((void**)&tmp, sizeof(float) * g->Q * g->N), "lbw_autotune");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    lbw::ProbeArgs pr{nullptr, 0, nullptr, 0, s->d_scratch_count};
+    const lbw::MarchPlan keep = g->plan;
+    lbw::MarchPlan best = keep;
+    float best_ms = 1e30f;
+    float* other = s->f[1 - s->cur];
+    for (int tx : {32, 64}) {
+        if (err != hipSuccess) break;
+        const int bpc = lbw::march_blocks_per_cu(tx);
+        for (int lz : {4, 8, 16, 32, 64}) {
+            if (lz > 2 * g->dev.n2 && lz != 4) continue;
+            for (int mult : {1, 2}) {
+                const lbw::MarchPlan p = lbw::make_march_plan(g->dev, tx, lz, mult * cus * bpc);
+                float* bufs[2] = {other, tmp};
+                int w = 0;
+                auto run = [&](int count) {
+                    for (int r = 0; r < count && err == hipSuccess; ++r, w ^= 1)
+                        err = lbw::launch_step_march(g->dev, pr, p, bufs[w], bufs[w ^ 1], s->stream);
+                };
+                if (err == hipSuccess) err = lbw::launch_step_march(g->dev, pr, p, s->f[s->cur], other, s->stream);
+                run(2);
+                if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
+                run(reps);
+                if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                if (err != hipSuccess) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = p;
+                }
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    g->plan = err == hipSuccess ? best : keep;
+    g->plan_version += 1;
+    if (err != hipSuccess) return hip_fail(err, "lbw_autotune");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[std::make_tuple(g->dev.n0, g->dev.n1, g->dev.n2)] = std::make_tuple(best.tx, best.lz, best.blocks);
+    }
+    if (best_us) *best_us = 1e3 * best_ms / reps;
     return LBW_OK;
 }
 
@@ -393,6 +542,8 @@ int lbw_pressure(lbw_state_t s, double* p_out) {
 int lbw_free_state(lbw_state_t s) {
     if (!s) return LBW_OK;
     (void)hipStreamSynchronize(s->stream);
+    drop_graphs(s);
+    (void)hipFree(s->d_scratch_count);
     (void)hipFree(s->d_tcount);
     (void)hipFree(s->d_probes);
     (void)hipFree(s->mode_work);

@@ -276,3 +276,29 @@ def test_launch_shapes_bit_identical():
             assert np.abs(sim.probe() - tr).max() <= 1e-5 * np.abs(tr).max()
         else:
             assert np.array_equal(fg, ref), (tx, lz, blocks)
+
+
+def test_graph_blocks_and_autotune_preserve_results():
+    """HIP-graph step blocks (even and odd lengths) and direct launches give
+    bit-identical states and traces; autotuning leaves the state untouched."""
+    w = W.workload(2, scale=4)
+    geom, P0, probes = w["geom"], w["P0"], w["probes"]
+    say("graphs/autotune", w["name"], geom["n"])
+    out = []
+    for block in (0, 32, 7):
+        g = lbw.Geometry(geom)
+        sim = lbw.Simulation(g, P0, probes, t_max=150)
+        sim.set_graph_block(block)
+        sim.step(45)
+        if block == 7:
+            before = sim.populations().cpu().numpy().copy()
+            us = sim.autotune(reps=3)
+            assert us > 0 and sim.t == 45
+            assert np.array_equal(sim.populations().cpu().numpy(), before)
+        sim.step(105)
+        out.append((sim.populations().cpu().numpy().copy(), sim.probe()))
+    for f, tr in out[1:]:
+        assert np.array_equal(f, out[0][0]) and np.array_equal(tr, out[0][1])
+    o = oracle.Oracle(geom)
+    f, tr = o.run(o.init(P0), 150, probes)
+    assert rel_l2(out[0][0].astype(np.float64), f) <= 1e-5
