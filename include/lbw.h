@@ -195,6 +195,61 @@ int lbw_pressure(lbw_state_t s, double* p_out);
  * untouched.  NULL is accepted. */
 int lbw_free_state(lbw_state_t s);
 
+/* ------------------------------------------------------------------------
+ * Batches: many D3Q7 geometries (e.g. horns of different profiles and grid
+ * sizes) advanced together, one launch per step for the whole batch, with
+ * the same per-node arithmetic as lbw_step_n.
+ *
+ * Layout (caller-owned device buffers):
+ *  populations  geometry h occupies floats [7 o_h, 7 o_{h+1}) of f_a and f_b,
+ *               SoA inside (f[7 o_h + l N_h + n]), o_h = sum_{j<h} N_j
+ *  p0           doubles [o_h, o_{h+1})
+ *  probes       host; geometry h's n_probes[h] node indices (local to h)
+ *               follow those of geometries < h
+ *  trace        device, t_max rows of P = sum_h n_probes[h] doubles; row t,
+ *               column (first probe of h) + j is probe j of geometry h
+ *               before step t
+ * ---------------------------------------------------------------------- */
+typedef struct lbw_batch* lbw_batch_t;
+
+/* Builds every geometry's tables (as lbw_make_geometry) into batch tables,
+ * initialises every geometry at rest (as lbw_init) into f_a, and prepares
+ * the tile list.  Errors: LBW_EINVAL (n < 1, a descriptor invalid or not
+ * 3-D, NULL pointers, f_a == f_b, a probe outside its geometry,
+ * n_probes[h] < 0), LBW_ENOMEM, LBW_EDEVICE. */
+int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, float* f_a, float* f_b,
+                   const int64_t* probes, const int32_t* n_probes, double* trace, int64_t t_max, void* stream,
+                   lbw_batch_t* out);
+
+/* Node offsets o_0..o_n and probe offsets (n + 1 values each, host). */
+int lbw_batch_layout(lbw_batch_t b, int64_t* node_offsets, int64_t* probe_offsets);
+
+/* Launch shape shared by all geometries of the batch (as
+ * lbw_set_step_config); lbw_batch_autotune times candidates on real
+ * ping-pong steps into the batch's other buffer and a temporary buffer,
+ * leaving the state unchanged. */
+int lbw_batch_set_step_config(lbw_batch_t b, int tile_x, int chunk_z, int blocks);
+int lbw_batch_get_step_config(lbw_batch_t b, int* tile_x, int* chunk_z, int* blocks);
+int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us);
+int lbw_batch_set_graph_block(lbw_batch_t b, int steps);
+
+/* Queues n steps of every geometry (probes recorded) without waiting. */
+int lbw_batch_step_n(lbw_batch_t b, int64_t n);
+
+/* Step count and the device buffer holding the current populations. */
+int lbw_batch_info(lbw_batch_t b, int64_t* t, float** f_current);
+
+/* Copies trace rows [t0, t1) (all P columns) to host; as lbw_probe. */
+int lbw_batch_probe(lbw_batch_t b, double* host_dst, int64_t t0, int64_t t1);
+
+/* Resonant frequencies of every geometry (rule of lbw_modes over that
+ * geometry's probes): freq_out and power_out (may be NULL) receive n * k
+ * values, geometry-major.  Synchronises.  Errors as lbw_modes. */
+int lbw_batch_modes(lbw_batch_t b, int k, double* freq_out, double* power_out);
+
+/* Releases the batch (waits for its stream); caller buffers untouched. */
+int lbw_batch_free(lbw_batch_t b);
+
 /* Message of the calling thread's last error ("" if none). */
 const char* lbw_last_error(void);
 

@@ -25,7 +25,9 @@ TABLE_PLANES = ("Mhat00", "Mhat11", "Mhat22", "Mhat02", "Gamh0", "Gamh1", "Gamh2
 SYMBOLS = ("lbw_make_geometry", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound",
            "lbw_set_step_config", "lbw_get_step_config", "lbw_init",
            "lbw_step_n", "lbw_autotune", "lbw_set_graph_block", "lbw_probe", "lbw_modes", "lbw_state_info",
-           "lbw_pressure", "lbw_free_state", "lbw_last_error")
+           "lbw_pressure", "lbw_free_state", "lbw_batch_make", "lbw_batch_layout", "lbw_batch_set_step_config",
+           "lbw_batch_get_step_config", "lbw_batch_autotune", "lbw_batch_set_graph_block", "lbw_batch_step_n",
+           "lbw_batch_info", "lbw_batch_probe", "lbw_batch_modes", "lbw_batch_free", "lbw_last_error")
 
 
 class GeometryDesc(ctypes.Structure):
@@ -87,8 +89,8 @@ def lib():
         L.lbw_free_geometry.argtypes = [vp]
         L.lbw_geometry_export.argtypes = [vp, i32, vp, ctypes.c_size_t]
         L.lbw_stability_bound.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
-        L.lbw_set_step_config.argtypes = [vp, i32, i32, i32]
         ip = ctypes.POINTER(ctypes.c_int)
+        L.lbw_set_step_config.argtypes = [vp, i32, i32, i32]
         L.lbw_get_step_config.argtypes = [vp, ip, ip, ip]
         L.lbw_init.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), i32, vp, i64, vp, ctypes.POINTER(vp)]
         L.lbw_step_n.argtypes = [vp, i64]
@@ -99,6 +101,18 @@ def lib():
         L.lbw_state_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(vp)]
         L.lbw_pressure.argtypes = [vp, vp]
         L.lbw_free_state.argtypes = [vp]
+        L.lbw_batch_make.argtypes = [ctypes.POINTER(GeometryDesc), i32, vp, vp, vp, ctypes.POINTER(i64),
+                                     ctypes.POINTER(ctypes.c_int32), vp, i64, vp, ctypes.POINTER(vp)]
+        L.lbw_batch_layout.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.lbw_batch_set_step_config.argtypes = [vp, i32, i32, i32]
+        L.lbw_batch_get_step_config.argtypes = [vp, ip, ip, ip]
+        L.lbw_batch_autotune.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+        L.lbw_batch_set_graph_block.argtypes = [vp, i32]
+        L.lbw_batch_step_n.argtypes = [vp, i64]
+        L.lbw_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(vp)]
+        L.lbw_batch_probe.argtypes = [vp, vp, i64, i64]
+        L.lbw_batch_modes.argtypes = [vp, i32, vp, vp]
+        L.lbw_batch_free.argtypes = [vp]
         L.lbw_last_error.restype = ctypes.c_char_p
         for name in SYMBOLS:
             getattr(L, name).restype = ctypes.c_int if name != "lbw_last_error" else ctypes.c_char_p
@@ -269,6 +283,105 @@ class Simulation:
     def close(self):
         if getattr(self, "handle", None):
             lib().lbw_free_state(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many D3Q7 geometries advanced by one launch per step.
+
+    geoms: list of geometry descriptions; P0s: list of initial pressure
+    arrays; probes: list of per-geometry node-index lists; t_max: trace rows.
+    Populations live in two caller-side float32 tensors of 7 * sum(N)
+    values; geometry h's block starts at 7 * node_offsets[h]."""
+
+    def __init__(self, geoms, P0s, probes, t_max: int, stream=None):
+        import torch
+        n = len(geoms)
+        assert n == len(P0s) == len(probes) and n > 0
+        self.geoms = [dict(g) for g in geoms]
+        self.n = n
+        descs = (GeometryDesc * n)(*[to_desc(g) for g in geoms])
+        dev = torch.device("cuda", torch.cuda.current_device())
+        sizes = [int(np.prod(g["n"][:3])) for g in geoms]
+        self.node_offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        total = int(self.node_offsets[-1])
+        p0 = torch.cat([torch.as_tensor(np.asarray(p, dtype=np.float64).reshape(-1)) for p in P0s]).to(dev)
+        if p0.numel() != total:
+            raise ValueError("P0 sizes do not match the grids")
+        self._P0 = p0
+        self.f = [torch.empty(7 * total, dtype=torch.float32, device=dev) for _ in range(2)]
+        counts = np.array([len(p) for p in probes], dtype=np.int32)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.int64).reshape(-1) for p in probes])
+                                    if counts.sum() else np.zeros(0, np.int64))
+        self.probe_offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        self.P = int(counts.sum())
+        self.t_max = int(t_max) if self.P else 0
+        self.trace = torch.zeros((max(self.t_max, 1), max(self.P, 1)), dtype=torch.float64, device=dev)
+        h = ctypes.c_void_p()
+        check(lib().lbw_batch_make(descs, n, p0.data_ptr(), self.f[0].data_ptr(), self.f[1].data_ptr(),
+                                   flat.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if self.P else None,
+                                   counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   self.trace.data_ptr() if self.P else None, self.t_max, _stream_ptr(stream),
+                                   ctypes.byref(h)))
+        self.handle = h
+
+    def step(self, n: int = 1):
+        check(lib().lbw_batch_step_n(self.handle, int(n)))
+
+    def set_step_config(self, tile_x: int, chunk_z: int, blocks: int = 0):
+        check(lib().lbw_batch_set_step_config(self.handle, int(tile_x), int(chunk_z), int(blocks)))
+
+    def step_config(self):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().lbw_batch_get_step_config(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def autotune(self, reps: int = 10) -> float:
+        us = ctypes.c_double()
+        check(lib().lbw_batch_autotune(self.handle, int(reps), ctypes.byref(us)))
+        return us.value
+
+    def set_graph_block(self, steps: int):
+        check(lib().lbw_batch_set_graph_block(self.handle, int(steps)))
+
+    @property
+    def t(self) -> int:
+        t = ctypes.c_int64()
+        check(lib().lbw_batch_info(self.handle, ctypes.byref(t), None))
+        return t.value
+
+    def populations(self, h: int):
+        """Current populations of geometry h as a (7, N_h) view."""
+        p = ctypes.c_void_p()
+        check(lib().lbw_batch_info(self.handle, None, ctypes.byref(p)))
+        f = self.f[0] if p.value == self.f[0].data_ptr() else self.f[1]
+        a, b = int(self.node_offsets[h]), int(self.node_offsets[h + 1])
+        return f[7 * a: 7 * b].view(7, b - a)
+
+    def probe(self, t0: int = 0, t1: int | None = None) -> np.ndarray:
+        rows = min(self.t, self.t_max)
+        t1 = rows if t1 is None else t1
+        out = np.zeros((max(t1 - t0, 0), self.P))
+        if out.size == 0:
+            return out
+        check(lib().lbw_batch_probe(self.handle, out.ctypes.data, int(t0), int(t1)))
+        return out
+
+    def modes(self, k: int):
+        freq = np.zeros((self.n, k))
+        power = np.zeros((self.n, k))
+        check(lib().lbw_batch_modes(self.handle, int(k), freq.ctypes.data, power.ctypes.data))
+        return freq, power
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lbw_batch_free(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -9,9 +9,11 @@
 #include <tuple>
 #include <vector>
 
-#include "lbw_internal.h"
+#include "host_util.h"
 
 using lbw::GeomDev;
+using lbw::fail;
+using lbw::hip_fail;
 
 struct lbw_geometry {
     lbw_geometry_desc d;
@@ -56,6 +58,12 @@ thread_local std::string g_err;
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, std::tuple<int, int, int>> g_tuned;
 
+bool is_finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+namespace lbw {
+
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -71,15 +79,46 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(LBW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                 \
-    do {                                    \
-        hipError_t e_ = (expr);             \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
+int device_cus(int* cus) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "device query");
+    HIP_TRY(hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev), "device query");
+    return LBW_OK;
+}
 
-bool finite(double v) { return std::isfinite(v); }
+lbw_geometry_desc normalised(const lbw_geometry_desc& in) {
+    lbw_geometry_desc d = in;
+    if (d.dim == 2) {
+        d.n[2] = 1;
+        d.bc_lo[2] = d.bc_hi[2] = LBW_BC_PERIODIC;
+        d.qmin[2] = 0.0;
+        d.qmax[2] = 1.0;
+    }
+    return d;
+}
 
-int validate(const lbw_geometry_desc* d) {
+GeomDev make_geomdev(const lbw_geometry_desc& d, const float* tab32, const double* sqrtg) {
+    GeomDev v{};
+    v.dim = d.dim;
+    v.n0 = d.n[0];
+    v.n1 = d.n[1];
+    v.n2 = d.n[2];
+    v.N = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    for (int a = 0; a < 3; ++a) {
+        v.bc_lo[a] = d.bc_lo[a];
+        v.bc_hi[a] = d.bc_hi[a];
+    }
+    const double c2 = d.c * d.c;
+    v.c2 = (float)c2;
+    v.two_w0 = (float)(2.0 * (1.0 - d.dim * c2));
+    v.damp = (float)d.damping;
+    v.c2_64 = c2;
+    v.tab = tab32;
+    v.sqrtg = sqrtg;
+    return v;
+}
+
+int validate_desc(const lbw_geometry_desc* d) {
     if (!d) return fail(LBW_EINVAL, "descriptor is NULL");
     if (d->kind < LBW_BOX || d->kind > LBW_BESSEL_HORN) return fail(LBW_EINVAL, "unknown kind %d", d->kind);
     if (d->dim != 2 && d->dim != 3) return fail(LBW_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
@@ -89,7 +128,7 @@ int validate(const lbw_geometry_desc* d) {
     int64_t N = 1;
     for (int a = 0; a < d->dim; ++a) {
         if (d->n[a] < 1) return fail(LBW_EINVAL, "n[%d] = %d < 1", a, d->n[a]);
-        if (!finite(d->qmin[a]) || !finite(d->qmax[a]) || !(d->qmax[a] > d->qmin[a]))
+        if (!is_finite(d->qmin[a]) || !is_finite(d->qmax[a]) || !(d->qmax[a] > d->qmin[a]))
             return fail(LBW_EINVAL, "axis %d: need qmin < qmax", a);
         for (int side = 0; side < 2; ++side) {
             int code = side ? d->bc_hi[a] : d->bc_lo[a];
@@ -101,9 +140,9 @@ int validate(const lbw_geometry_desc* d) {
     }
     if ((2 * d->dim + 1) * N > 2147483647LL)
         return fail(LBW_EINVAL, "too many nodes (%lld): Q * N must stay below 2^31", (long long)N);
-    if (!finite(d->h_ref) || !(d->h_ref > 0.0)) return fail(LBW_EINVAL, "h_ref must be > 0");
-    if (!finite(d->c) || !(d->c > 0.0)) return fail(LBW_EINVAL, "c must be > 0");
-    if (!finite(d->damping) || d->damping < 0.0 || d->damping > 1.0) return fail(LBW_EINVAL, "damping outside [0,1]");
+    if (!is_finite(d->h_ref) || !(d->h_ref > 0.0)) return fail(LBW_EINVAL, "h_ref must be > 0");
+    if (!is_finite(d->c) || !(d->c > 0.0)) return fail(LBW_EINVAL, "c must be > 0");
+    if (!is_finite(d->damping) || d->damping < 0.0 || d->damping > 1.0) return fail(LBW_EINVAL, "damping outside [0,1]");
     switch (d->kind) {
     case LBW_POLAR2D:
     case LBW_CYLINDER:
@@ -115,7 +154,7 @@ int validate(const lbw_geometry_desc* d) {
         for (int end = 0; end < 2; ++end) {
             const double z = end ? d->qmax[2] : d->qmin[2];
             const double s = a + b * std::exp(k * z);
-            if (!finite(s) || !(s > 0.0)) return fail(LBW_EINVAL, "horn radius must stay > 0");
+            if (!is_finite(s) || !(s > 0.0)) return fail(LBW_EINVAL, "horn radius must stay > 0");
         }
         if (!(a > 0.0) && !(b > 0.0)) return fail(LBW_EINVAL, "horn radius must stay > 0");
         break;
@@ -134,7 +173,7 @@ int validate(const lbw_geometry_desc* d) {
     return LBW_OK;
 }
 
-}  // namespace
+}  // namespace lbw
 
 extern "C" {
 
@@ -143,57 +182,29 @@ const char* lbw_last_error(void) { return g_err.c_str(); }
 int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_t* out) {
     if (!out) return fail(LBW_EINVAL, "out is NULL");
     *out = nullptr;
-    int rc = validate(desc);
+    int rc = lbw::validate_desc(desc);
     if (rc) return rc;
     lbw_geometry* g = new lbw_geometry();
-    g->d = *desc;
-    if (g->d.dim == 2) {
-        g->d.n[2] = 1;
-        g->d.bc_lo[2] = g->d.bc_hi[2] = LBW_BC_PERIODIC;
-        g->d.qmin[2] = 0.0;
-        g->d.qmax[2] = 1.0;
-    }
+    g->d = lbw::normalised(*desc);
     const lbw_geometry_desc& d = g->d;
     g->Q = 2 * d.dim + 1;
     g->N = (int64_t)d.n[0] * d.n[1] * d.n[2];
     g->E = (int64_t)d.n[0] * d.n[2];
     g->stream = (hipStream_t)stream;
+    int cus = 0;
     hipError_t e = hipMalloc(&g->tab64, sizeof(double) * lbw::kTabF64 * g->E);
     if (e == hipSuccess) e = hipMalloc(&g->tab32, sizeof(float) * lbw::kTabF32 * g->E);
     if (e == hipSuccess) e = lbw::launch_geometry_tables(d, g->tab64, g->tab32, g->stream);
+    if (e == hipSuccess && lbw::device_cus(&cus) != LBW_OK) e = hipErrorInvalidDevice;
     if (e != hipSuccess) {
         (void)hipFree(g->tab64);
         (void)hipFree(g->tab32);
         delete g;
         return hip_fail(e, "lbw_make_geometry");
     }
-    GeomDev& v = g->dev;
-    v.dim = d.dim;
-    v.n0 = d.n[0];
-    v.n1 = d.n[1];
-    v.n2 = d.n[2];
-    v.N = g->N;
-    for (int a = 0; a < 3; ++a) {
-        v.bc_lo[a] = d.bc_lo[a];
-        v.bc_hi[a] = d.bc_hi[a];
-    }
-    const double c2 = d.c * d.c;
-    v.c2 = (float)c2;
-    v.two_w0 = (float)(2.0 * (1.0 - d.dim * c2));
-    v.damp = (float)d.damping;
-    v.c2_64 = c2;
-    v.tab = g->tab32;
-    v.sqrtg = g->tab64 + 7 * g->E;
+    g->dev = lbw::make_geomdev(d, g->tab32, g->tab64 + 7 * g->E);
+    const GeomDev& v = g->dev;
     if (d.dim == 3) {
-        int dev = 0, cus = 0;
-        e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) {
-            (void)hipFree(g->tab64);
-            (void)hipFree(g->tab32);
-            delete g;
-            return hip_fail(e, "lbw_make_geometry");
-        }
         const int tx = lbw::march_tx_for(v.n0);
         g->plan = lbw::make_march_plan(v, tx, 16, cus * lbw::march_blocks_per_cu(tx));
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -497,7 +508,8 @@ int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out) {
     if (s->n_probes < 1) return fail(LBW_EINVAL, "state has no probes");
     const int64_t T = s->t < s->t_max ? s->t : s->t_max;
     if (T < 8) return fail(LBW_EINVAL, "need at least 8 recorded rows (have %lld)", (long long)T);
-    const size_t need = lbw::modes_work_bytes(T, s->n_probes);
+    if (s->n_probes > lbw::modes_max_cols(T)) return fail(LBW_EINVAL, "too many probes for one spectrum");
+    const size_t need = lbw::modes_work_bytes(T, s->n_probes, 1);
     if (need > s->mode_work_bytes) {
         (void)hipFree(s->mode_work);
         s->mode_work = nullptr;
@@ -512,8 +524,9 @@ int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out) {
         HIP_TRY(hipMalloc(&s->mode_out, sizeof(double) * 2 * k), "lbw_modes");
         s->mode_k = k;
     }
-    HIP_TRY(lbw::launch_modes(s->trace, T, s->n_probes, k, s->mode_work, s->mode_work_bytes, s->mode_out,
-                              s->mode_out + k, s->stream),
+    const int ncols = s->n_probes;
+    HIP_TRY(lbw::launch_modes_grouped(s->trace, T, s->n_probes, &ncols, 1, k, s->mode_work, s->mode_work_bytes,
+                                      s->mode_out, s->mode_out + k, s->stream),
             "lbw_modes");
     std::vector<double> host(2 * (size_t)k);
     HIP_TRY(hipMemcpyAsync(host.data(), s->mode_out, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, s->stream),

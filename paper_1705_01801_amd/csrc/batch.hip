@@ -1,0 +1,443 @@
+// C-ABI for batches of D3Q7 geometries advanced by one launch per step.
+#include <cmath>
+#include <vector>
+
+#include "host_util.h"
+
+using lbw::fail;
+using lbw::hip_fail;
+
+struct lbw_batch {
+    int n = 0;
+    std::vector<lbw_geometry_desc> d;
+    std::vector<int64_t> node_off, probe_off, rec_off, tab64_off;  // prefix sums, n + 1 entries
+    double* tab64 = nullptr;
+    float* tab32 = nullptr;
+    std::vector<lbw::BatchItem> items;
+    lbw::BatchItem* d_items = nullptr;
+    int tx = 32, lz = 16, blocks = 8;
+    int64_t tiles = 0;
+    int plan_version = 0;
+    float* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t t = 0, t_max = 0;
+    int64_t P = 0;  // total probes
+    double* trace = nullptr;
+    int64_t* d_nodes = nullptr;
+    int64_t* d_tcount = nullptr;
+    int64_t* d_scratch_count = nullptr;
+    hipStream_t stream = nullptr;
+    int graph_block = 32;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_version = -1;
+    double* mode_work = nullptr;
+    size_t mode_work_bytes = 0;
+    double* mode_out = nullptr;
+    int mode_k = 0;
+};
+
+namespace {
+
+void release(lbw_batch* b) {
+    for (auto& gx : b->graph)
+        if (gx) (void)hipGraphExecDestroy(gx);
+    (void)hipFree(b->tab64);
+    (void)hipFree(b->tab32);
+    (void)hipFree(b->d_items);
+    (void)hipFree(b->d_nodes);
+    (void)hipFree(b->d_tcount);
+    (void)hipFree(b->d_scratch_count);
+    (void)hipFree(b->mode_work);
+    (void)hipFree(b->mode_out);
+    delete b;
+}
+
+// Tile list for the current (tx, lz); uploads it on the batch stream.
+hipError_t build_items(lbw_batch* b) {
+    const int ty = 256 / b->tx;
+    int64_t tile = 0;
+    for (int h = 0; h < b->n; ++h) {
+        const lbw_geometry_desc& d = b->d[h];
+        const lbw::GeomDev v = lbw::make_geomdev(d, nullptr, nullptr);
+        lbw::BatchItem& it = b->items[h];
+        it.n0 = v.n0;
+        it.n1 = v.n1;
+        it.n2 = v.n2;
+        it.N = (uint32_t)v.N;
+        for (int a = 0; a < 3; ++a) {
+            it.bc_lo[a] = v.bc_lo[a];
+            it.bc_hi[a] = v.bc_hi[a];
+        }
+        it.c2 = v.c2;
+        it.two_w0 = v.two_w0;
+        it.damp = v.damp;
+        it.ntx = (v.n0 + b->tx - 1) / b->tx;
+        it.nty = (v.n1 + ty - 1) / ty;
+        it.lz = b->lz;
+        const int nchunks = (v.n2 + b->lz - 1) / b->lz;
+        it.tile_begin = tile;
+        it.tiles = (int64_t)it.ntx * it.nty * nchunks;
+        tile += it.tiles;
+        it.f_off = (uint64_t)(7 * b->node_off[h]);
+        it.tab_off = (uint32_t)b->rec_off[h];
+        it.sg_off = (uint32_t)(b->tab64_off[h] + 7 * (b->rec_off[h + 1] - b->rec_off[h]));
+        it.probe_off = (uint32_t)b->probe_off[h];
+        it.n_probes = (int)(b->probe_off[h + 1] - b->probe_off[h]);
+    }
+    b->tiles = tile;
+    b->plan_version += 1;
+    return hipMemcpyAsync(b->d_items, b->items.data(), sizeof(lbw::BatchItem) * b->n, hipMemcpyHostToDevice,
+                          b->stream);
+}
+
+lbw::BatchProbeArgs probe_args(lbw_batch* b, bool record) {
+    lbw::BatchProbeArgs bp{};
+    bp.nodes = b->d_nodes;
+    bp.trace = b->trace;
+    bp.stride = b->P;
+    bp.t_max = record ? b->t_max : 0;
+    bp.tcount = record ? b->d_tcount : b->d_scratch_count;
+    bp.sqrtg = b->tab64;
+    bp.tab4 = reinterpret_cast<const float4*>(b->tab32);
+    return bp;
+}
+
+hipError_t launch_batch(lbw_batch* b, const lbw::BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st) {
+    return lbw::launch_step_batch(b->d_items, b->n, b->tiles, b->tx, b->blocks, bp, fin, fout, st);
+}
+
+hipError_t build_graph(lbw_batch* b, int from) {
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    const lbw::BatchProbeArgs bp = probe_args(b, true);
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        int cur = from;
+        hipError_t le = hipSuccess;
+        for (int i = 0; i < b->graph_block && le == hipSuccess; ++i) {
+            le = launch_batch(b, bp, b->f[cur], b->f[1 - cur], cap);
+            cur ^= 1;
+        }
+        e = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->graph[from], graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    return e;
+}
+
+void drop_graphs(lbw_batch* b) {
+    for (auto& gx : b->graph) {
+        if (gx) (void)hipGraphExecDestroy(gx);
+        gx = nullptr;
+    }
+}
+
+int set_config(lbw_batch* b, int tile_x, int chunk_z, int blocks) {
+    int cus = 0;
+    int rc = lbw::device_cus(&cus);
+    if (rc) return rc;
+    if (blocks == 0) blocks = cus * lbw::batch_blocks_per_cu(tile_x);
+    blocks = (blocks / 8) * 8;
+    if (blocks < 8) blocks = 8;
+    b->tx = tile_x;
+    b->lz = chunk_z;
+    b->blocks = blocks;
+    HIP_TRY(build_items(b), "batch step configuration");
+    return LBW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, float* f_a, float* f_b,
+                   const int64_t* probes, const int32_t* n_probes, double* trace, int64_t t_max, void* stream,
+                   lbw_batch_t* out) {
+    if (!out) return fail(LBW_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !descs || !p0 || !f_a || !f_b || !n_probes) return fail(LBW_EINVAL, "invalid batch arguments");
+    if (f_a == f_b) return fail(LBW_EINVAL, "f_a and f_b must be distinct");
+    if (t_max < 0) return fail(LBW_EINVAL, "negative t_max");
+    lbw_batch* b = new lbw_batch();
+    b->n = n;
+    b->stream = (hipStream_t)stream;
+    b->node_off.assign(n + 1, 0);
+    b->probe_off.assign(n + 1, 0);
+    b->rec_off.assign(n + 1, 0);
+    b->tab64_off.assign(n + 1, 0);
+    for (int h = 0; h < n; ++h) {
+        int rc = lbw::validate_desc(&descs[h]);
+        if (rc) {
+            delete b;
+            return fail(rc, "geometry %d: %s", h, lbw_last_error());
+        }
+        if (descs[h].dim != 3) {
+            delete b;
+            return fail(LBW_EINVAL, "geometry %d: batches hold 3-D geometries", h);
+        }
+        if (n_probes[h] < 0) {
+            delete b;
+            return fail(LBW_EINVAL, "geometry %d: negative probe count", h);
+        }
+        b->d.push_back(lbw::normalised(descs[h]));
+        const lbw_geometry_desc& d = b->d.back();
+        const int64_t N = (int64_t)d.n[0] * d.n[1] * d.n[2];
+        const int64_t E = (int64_t)d.n[0] * d.n[2];
+        b->node_off[h + 1] = b->node_off[h] + N;
+        b->probe_off[h + 1] = b->probe_off[h] + n_probes[h];
+        b->rec_off[h + 1] = b->rec_off[h] + E;
+        b->tab64_off[h + 1] = b->tab64_off[h] + lbw::kTabF64 * E;
+    }
+    b->P = b->probe_off[n];
+    if (b->P > 0 && (!probes || (!trace && t_max > 0))) {
+        delete b;
+        return fail(LBW_EINVAL, "probes need a trace buffer");
+    }
+    if (b->rec_off[n] > 0xffffffffLL || b->tab64_off[n] > 0xffffffffLL) {
+        delete b;
+        return fail(LBW_EINVAL, "batch tables too large");
+    }
+    for (int h = 0; h < n; ++h) {
+        const int64_t N = b->node_off[h + 1] - b->node_off[h];
+        for (int64_t p = b->probe_off[h]; p < b->probe_off[h + 1]; ++p)
+            if (probes[p] < 0 || probes[p] >= N) {
+                delete b;
+                return fail(LBW_EINVAL, "geometry %d: probe %lld out of range", h, (long long)(p - b->probe_off[h]));
+            }
+    }
+    b->f[0] = f_a;
+    b->f[1] = f_b;
+    b->t_max = b->P > 0 ? t_max : 0;
+    b->trace = trace;
+    b->items.resize(n);
+    hipError_t e = hipMalloc(&b->tab64, sizeof(double) * b->tab64_off[n]);
+    if (e == hipSuccess) e = hipMalloc(&b->tab32, sizeof(float) * lbw::kTabF32 * b->rec_off[n]);
+    if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(lbw::BatchItem) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_tcount, sizeof(int64_t) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_scratch_count, sizeof(int64_t) * n);
+    if (e == hipSuccess && b->P > 0) e = hipMalloc(&b->d_nodes, sizeof(int64_t) * b->P);
+    if (e == hipSuccess && b->P > 0)
+        e = hipMemcpyAsync(b->d_nodes, probes, sizeof(int64_t) * b->P, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_tcount, 0, sizeof(int64_t) * n, b->stream);
+    for (int h = 0; h < n && e == hipSuccess; ++h) {
+        const int64_t E = b->rec_off[h + 1] - b->rec_off[h];
+        double* t64 = b->tab64 + b->tab64_off[h];
+        float* t32 = b->tab32 + lbw::kTabF32 * b->rec_off[h];
+        e = lbw::launch_geometry_tables(b->d[h], t64, t32, b->stream);
+        if (e == hipSuccess) {
+            const lbw::GeomDev v = lbw::make_geomdev(b->d[h], t32, t64 + 7 * E);
+            e = lbw::launch_init(v, p0 + b->node_off[h], f_a + 7 * b->node_off[h], b->stream);
+        }
+    }
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "lbw_batch_make");
+    }
+    int rc = set_config(b, 32, 16, 0);
+    if (rc == LBW_OK && b->P > 0 && hipStreamSynchronize(b->stream) != hipSuccess)
+        rc = fail(LBW_EDEVICE, "lbw_batch_make: synchronise");
+    if (rc) {
+        release(b);
+        return rc;
+    }
+    *out = b;
+    return LBW_OK;
+}
+
+int lbw_batch_layout(lbw_batch_t b, int64_t* node_offsets, int64_t* probe_offsets) {
+    if (!b) return fail(LBW_EINVAL, "batch is NULL");
+    for (int h = 0; h <= b->n; ++h) {
+        if (node_offsets) node_offsets[h] = b->node_off[h];
+        if (probe_offsets) probe_offsets[h] = b->probe_off[h];
+    }
+    return LBW_OK;
+}
+
+int lbw_batch_set_step_config(lbw_batch_t b, int tile_x, int chunk_z, int blocks) {
+    if (!b) return fail(LBW_EINVAL, "batch is NULL");
+    if (tile_x != 32 && tile_x != 64) return fail(LBW_EINVAL, "tile_x must be 32 or 64");
+    if (chunk_z < 1 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 1 and blocks >= 0");
+    return set_config(b, tile_x, chunk_z, blocks);
+}
+
+int lbw_batch_get_step_config(lbw_batch_t b, int* tile_x, int* chunk_z, int* blocks) {
+    if (!b) return fail(LBW_EINVAL, "batch is NULL");
+    if (tile_x) *tile_x = b->tx;
+    if (chunk_z) *chunk_z = b->lz;
+    if (blocks) *blocks = b->blocks;
+    return LBW_OK;
+}
+
+int lbw_batch_set_graph_block(lbw_batch_t b, int steps) {
+    if (!b) return fail(LBW_EINVAL, "batch is NULL");
+    if (steps < 0 || steps > 4096) return fail(LBW_EINVAL, "graph block must be in [0, 4096]");
+    HIP_TRY(hipStreamSynchronize(b->stream), "lbw_batch_set_graph_block");
+    drop_graphs(b);
+    b->graph_block = steps;
+    return LBW_OK;
+}
+
+int lbw_batch_step_n(lbw_batch_t b, int64_t n) {
+    if (!b) return fail(LBW_EINVAL, "batch is NULL");
+    if (n < 0) return fail(LBW_EINVAL, "negative step count");
+    const int K = b->graph_block;
+    if (K > 0 && n >= K) {
+        if (b->graph_version != b->plan_version) {
+            drop_graphs(b);
+            b->graph_version = b->plan_version;
+        }
+        while (n >= K) {
+            if (!b->graph[b->cur]) HIP_TRY(build_graph(b, b->cur), "lbw_batch_step_n: graph capture");
+            HIP_TRY(hipGraphLaunch(b->graph[b->cur], b->stream), "lbw_batch_step_n: graph launch");
+            if (K & 1) b->cur ^= 1;
+            b->t += K;
+            n -= K;
+        }
+    }
+    const lbw::BatchProbeArgs bp = probe_args(b, true);
+    for (int64_t i = 0; i < n; ++i) {
+        HIP_TRY(launch_batch(b, bp, b->f[b->cur], b->f[1 - b->cur], b->stream), "lbw_batch_step_n");
+        b->cur ^= 1;
+        b->t += 1;
+    }
+    return LBW_OK;
+}
+
+int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us) {
+    if (!b) return fail(LBW_EINVAL, "batch is NULL");
+    if (reps < 1) return fail(LBW_EINVAL, "reps must be >= 1");
+    int cus = 0;
+    int rc = lbw::device_cus(&cus);
+    if (rc) return rc;
+    float* tmp = nullptr;
+    HIP_TRY(hipMalloc((void**)&tmp, sizeof(float) * 7 * b->node_off[b->n]), "lbw_batch_autotune");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    const lbw::BatchProbeArgs bp = probe_args(b, false);
+    const int keep_tx = b->tx, keep_lz = b->lz, keep_blocks = b->blocks;
+    int best_tx = keep_tx, best_lz = keep_lz, best_blocks = keep_blocks;
+    float best_ms = 1e30f;
+    float* other = b->f[1 - b->cur];
+    for (int tx : {32, 64}) {
+        if (err != hipSuccess) break;
+        const int bpc = lbw::batch_blocks_per_cu(tx);
+        for (int lz : {4, 8, 16, 32, 64}) {
+            for (int mult : {1, 2}) {
+                if (set_config(b, tx, lz, mult * cus * bpc) != LBW_OK) {
+                    err = hipErrorUnknown;
+                    break;
+                }
+                float* bufs[2] = {other, tmp};
+                int w = 0;
+                if (err == hipSuccess) err = launch_batch(b, bp, b->f[b->cur], other, b->stream);
+                for (int r = 0; r < 2 && err == hipSuccess; ++r, w ^= 1)
+                    err = launch_batch(b, bp, bufs[w], bufs[w ^ 1], b->stream);
+                if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
+                for (int r = 0; r < reps && err == hipSuccess; ++r, w ^= 1)
+                    err = launch_batch(b, bp, bufs[w], bufs[w ^ 1], b->stream);
+                if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                if (err != hipSuccess) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_tx = tx;
+                    best_lz = lz;
+                    best_blocks = b->blocks;
+                }
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipFree(tmp);
+    if (err == hipSuccess) rc = set_config(b, best_tx, best_lz, best_blocks);
+    else rc = set_config(b, keep_tx, keep_lz, keep_blocks);
+    if (err != hipSuccess) return hip_fail(err, "lbw_batch_autotune");
+    if (rc) return rc;
+    if (best_us) *best_us = 1e3 * best_ms / reps;
+    return LBW_OK;
+}
+
+int lbw_batch_info(lbw_batch_t b, int64_t* t, float** f_current) {
+    if (!b) return fail(LBW_EINVAL, "batch is NULL");
+    if (t) *t = b->t;
+    if (f_current) *f_current = b->f[b->cur];
+    return LBW_OK;
+}
+
+int lbw_batch_probe(lbw_batch_t b, double* host_dst, int64_t t0, int64_t t1) {
+    if (!b || !host_dst) return fail(LBW_EINVAL, "NULL argument");
+    const int64_t rows = b->t < b->t_max ? b->t : b->t_max;
+    if (t0 < 0 || t1 < t0 || t1 > rows)
+        return fail(LBW_EINVAL, "rows [%lld, %lld) outside [0, %lld)", (long long)t0, (long long)t1, (long long)rows);
+    const size_t cnt = (size_t)(t1 - t0) * b->P;
+    if (cnt)
+        HIP_TRY(hipMemcpyAsync(host_dst, b->trace + t0 * b->P, cnt * sizeof(double), hipMemcpyDeviceToHost, b->stream),
+                "lbw_batch_probe");
+    HIP_TRY(hipStreamSynchronize(b->stream), "lbw_batch_probe");
+    for (size_t i = 0; i < cnt; ++i)
+        if (!std::isfinite(host_dst[i]))
+            return fail(LBW_EUNSTABLE, "non-finite probe value at row %lld", (long long)(t0 + i / b->P));
+    return LBW_OK;
+}
+
+int lbw_batch_modes(lbw_batch_t b, int k, double* freq_out, double* power_out) {
+    if (!b || !freq_out) return fail(LBW_EINVAL, "NULL argument");
+    if (k < 1) return fail(LBW_EINVAL, "k must be >= 1");
+    if (b->P < 1) return fail(LBW_EINVAL, "batch has no probes");
+    const int64_t T = b->t < b->t_max ? b->t : b->t_max;
+    if (T < 8) return fail(LBW_EINVAL, "need at least 8 recorded rows (have %lld)", (long long)T);
+    std::vector<int> cols(b->n);
+    int max_group = 0;
+    for (int h = 0; h < b->n; ++h) {
+        cols[h] = (int)(b->probe_off[h + 1] - b->probe_off[h]);
+        if (cols[h] > max_group) max_group = cols[h];
+    }
+    const int cap = lbw::modes_max_cols(T);
+    if (max_group > cap) return fail(LBW_EINVAL, "too many probes in one geometry for one spectrum");
+    const int chunk_cols = (int)std::min<int64_t>(cap, b->P);
+    const size_t need = lbw::modes_work_bytes(T, chunk_cols, b->n);
+    if (need > b->mode_work_bytes) {
+        (void)hipFree(b->mode_work);
+        b->mode_work = nullptr;
+        b->mode_work_bytes = 0;
+        HIP_TRY(hipMalloc(&b->mode_work, need), "lbw_batch_modes");
+        b->mode_work_bytes = need;
+    }
+    if (k > b->mode_k) {
+        (void)hipFree(b->mode_out);
+        b->mode_out = nullptr;
+        b->mode_k = 0;
+        HIP_TRY(hipMalloc(&b->mode_out, sizeof(double) * 2 * (size_t)k * b->n), "lbw_batch_modes");
+        b->mode_k = k;
+    }
+    double* fr = b->mode_out;
+    double* pw = b->mode_out + (size_t)k * b->n;
+    HIP_TRY(lbw::launch_modes_grouped(b->trace, T, b->P, cols.data(), b->n, k, b->mode_work, b->mode_work_bytes, fr,
+                                      pw, b->stream),
+            "lbw_batch_modes");
+    HIP_TRY(hipMemcpyAsync(freq_out, fr, sizeof(double) * k * b->n, hipMemcpyDeviceToHost, b->stream),
+            "lbw_batch_modes");
+    if (power_out)
+        HIP_TRY(hipMemcpyAsync(power_out, pw, sizeof(double) * k * b->n, hipMemcpyDeviceToHost, b->stream),
+                "lbw_batch_modes");
+    HIP_TRY(hipStreamSynchronize(b->stream), "lbw_batch_modes");
+    return LBW_OK;
+}
+
+int lbw_batch_free(lbw_batch_t b) {
+    if (!b) return LBW_OK;
+    (void)hipStreamSynchronize(b->stream);
+    release(b);
+    return LBW_OK;
+}
+
+}  // extern "C"

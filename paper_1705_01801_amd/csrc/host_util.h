@@ -1,0 +1,25 @@
+// Host-side helpers shared by the C-ABI sources.
+#pragma once
+
+#include <string>
+
+#include "lbw_internal.h"
+
+namespace lbw {
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int validate_desc(const lbw_geometry_desc* d);
+// Normalised copy of a descriptor (unused axis 2 of a 2-D grid filled in).
+lbw_geometry_desc normalised(const lbw_geometry_desc& d);
+// Kernel view of a geometry whose tables live at tab32 / sqrtg.
+GeomDev make_geomdev(const lbw_geometry_desc& d, const float* tab32, const double* sqrtg);
+int device_cus(int* cus);
+
+}  // namespace lbw
+
+#define HIP_TRY(expr, what)                                          \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) return ::lbw::hip_fail(e_, what);      \
+    } while (0)

@@ -77,9 +77,41 @@ int march_blocks_per_cu(int tx);
 hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
                              float* fout, hipStream_t st);
 
-// Spectrum: fills freq/power (device, k each) from trace rows [0, T).
-hipError_t launch_modes(const double* trace, int64_t T, int n_probes, int k, double* work, size_t work_bytes,
-                        double* freq, double* power, hipStream_t st);
-size_t modes_work_bytes(int64_t T, int n_probes);
+// One geometry of a batch (all D3Q7), as read by the batch step kernel.
+struct BatchItem {
+    int n0, n1, n2;
+    uint32_t N;
+    int bc_lo[3], bc_hi[3];
+    float c2, two_w0, damp;
+    int ntx, nty, lz;
+    int64_t tile_begin;  // first global tile of this geometry
+    int64_t tiles;
+    uint64_t f_off;      // float offset of the population block (Q * N floats)
+    uint32_t tab_off;    // first 32-byte record in the batch float table
+    uint32_t sg_off;     // first double in the batch sqrt(g) array
+    uint32_t probe_off;  // first probe (global numbering; trace column)
+    int n_probes;
+};
+struct BatchProbeArgs {
+    const int64_t* nodes;  // device, all probes, node index within its geometry
+    double* trace;         // device, t_max rows of `stride` doubles
+    int64_t stride;        // total probes (trace row length)
+    int64_t t_max;
+    int64_t* tcount;       // device, one step counter per geometry
+    const double* sqrtg;   // device, batch sqrt(g) array
+    const float4* tab4;    // device, batch float table (2 float4 per record)
+};
+int batch_blocks_per_cu(int tx);
+hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int blocks,
+                             const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st);
+
+// Spectra of probe groups (consecutive trace columns, one group per
+// geometry): fills freq/power (device, groups * k each) from trace rows
+// [0, T) of row length `stride`.  Synchronises the stream per chunk.
+int64_t modes_nfft(int64_t T);
+int modes_max_cols(int64_t T);
+size_t modes_work_bytes(int64_t T, int max_cols, int max_groups);
+hipError_t launch_modes_grouped(const double* trace, int64_t T, int64_t stride, const int* group_ncols, int groups,
+                                int k, double* work, size_t work_bytes, double* freq, double* power, hipStream_t st);
 
 }  // namespace lbw

@@ -5,9 +5,17 @@
 // spectrum of the probe signal.  Rule: per probe subtract the mean, apply
 // the symmetric Hann window 1/2 - 1/2 cos(2 pi t / (T - 1)), zero-pad to
 // nfft = 4 * nextpow2(T), FFT (radix-2 Stockham, natural-order output),
-// P_k = sum over probes |X_k|^2 for k in [0, nfft/2]; peaks are bins
-// b in [2, nfft/2 - 1] with P[b-1] < P[b] >= P[b+1] and P[b] > 1e-3 max P[2:],
-// refined by a parabola through ln P (no refinement when a neighbour is 0).
+// P_k = sum over a group's probes of |X_k|^2 for k in [0, nfft/2]; peaks are
+// bins b in [2, nfft/2 - 1] with P[b-1] < P[b] >= P[b+1] and
+// P[b] > 1e-3 max P[2:], refined by a parabola through ln P (no refinement
+// when a neighbour is 0).
+//
+// A "group" is the set of probes of one geometry: consecutive columns of a
+// trace whose rows hold `stride` values.  Groups are processed in chunks so
+// that the FFT work space stays bounded.
+#include <algorithm>
+#include <vector>
+
 #include "lbw_internal.h"
 
 namespace lbw {
@@ -15,19 +23,15 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kPeakBlock = 1024;
+constexpr size_t kChunkBytes = size_t(1) << 30;  // FFT work space per chunk
 
-int64_t nfft_for(int64_t T) {
-    int64_t p = 1;
-    while (p < T) p *= 2;
-    return 4 * p;
-}
-
-// One block per probe: mean, then windowed and zero-padded complex input.
-__global__ void prepare_kernel(const double* __restrict__ trace, int64_t T, int np, int64_t nfft, double2* __restrict__ x) {
+// One block per column: mean, then windowed and zero-padded complex input.
+__global__ void prepare_kernel(const double* __restrict__ trace, int64_t T, int64_t stride, int col_begin,
+                               int64_t nfft, double2* __restrict__ x) {
     __shared__ double part[kBlock];
-    const int p = blockIdx.x;
+    const int64_t c = col_begin + blockIdx.x;
     double s = 0.0;
-    for (int64_t t = threadIdx.x; t < T; t += kBlock) s += trace[t * np + p];
+    for (int64_t t = threadIdx.x; t < T; t += kBlock) s += trace[t * stride + c];
     part[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -35,12 +39,12 @@ __global__ void prepare_kernel(const double* __restrict__ trace, int64_t T, int 
         __syncthreads();
     }
     const double mean = part[0] / (double)T;
-    double2* xp = x + (size_t)p * nfft;
+    double2* xp = x + (size_t)blockIdx.x * nfft;
     for (int64_t t = threadIdx.x; t < nfft; t += kBlock) {
         double v = 0.0;
         if (t < T) {
             const double win = T > 1 ? 0.5 - 0.5 * cospi(2.0 * (double)t / (double)(T - 1)) : 1.0;
-            v = (trace[t * np + p] - mean) * win;
+            v = (trace[t * stride + c] - mean) * win;
         }
         xp[t] = make_double2(v, 0.0);
     }
@@ -48,17 +52,17 @@ __global__ void prepare_kernel(const double* __restrict__ trace, int64_t T, int 
 
 // Radix-2 Stockham pass: Ns = size of the sub-transforms already formed.
 __global__ void fft_pass_kernel(const double2* __restrict__ in, double2* __restrict__ out, int64_t nfft, int64_t Ns,
-                                int np) {
+                                int ncols) {
     const int64_t half = nfft / 2;
     const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (gid >= half * np) return;
+    if (gid >= half * ncols) return;
     const int64_t p = gid / half;
     const int64_t j = gid - p * half;
     const double2* ip = in + p * nfft;
     double2* op = out + p * nfft;
     const int64_t k = j % Ns;
-    double2 a = ip[j];
-    double2 b = ip[j + half];
+    const double2 a = ip[j];
+    const double2 b = ip[j + half];
     double sn, cs;
     sincospi(-(double)k / (double)Ns, &sn, &cs);  // exp(-2 pi i k / (2 Ns))
     const double2 bw = make_double2(b.x * cs - b.y * sn, b.x * sn + b.y * cs);
@@ -67,24 +71,32 @@ __global__ void fft_pass_kernel(const double2* __restrict__ in, double2* __restr
     op[o + Ns] = make_double2(a.x - bw.x, a.y - bw.y);
 }
 
-__global__ void power_kernel(const double2* __restrict__ X, int64_t nfft, int np, double* __restrict__ P) {
+// P[g][k] = sum over the group's columns of |X|^2; gcol[g] = first column of
+// group g relative to the chunk, gcnt[g] = its column count.
+__global__ void power_kernel(const double2* __restrict__ X, int64_t nfft, const int* __restrict__ gcol,
+                             const int* __restrict__ gcnt, double* __restrict__ P) {
+    const int g = blockIdx.y;
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k > nfft / 2) return;
+    const int64_t nb = nfft / 2 + 1;
+    if (k >= nb) return;
     double s = 0.0;
-    for (int p = 0; p < np; ++p) {
-        const double2 v = X[(size_t)p * nfft + k];
+    for (int p = 0; p < gcnt[g]; ++p) {
+        const double2 v = X[(size_t)(gcol[g] + p) * nfft + k];
         s += v.x * v.x + v.y * v.y;
     }
-    P[k] = s;
+    P[(size_t)g * nb + k] = s;
 }
 
-// Single block: global max over bins >= 2, then an ordered scan for peaks.
-__global__ __launch_bounds__(kPeakBlock) void peaks_kernel(const double* __restrict__ P, int64_t nfft, int k,
+// One block per group: global max over bins >= 2, then an ordered scan.
+__global__ __launch_bounds__(kPeakBlock) void peaks_kernel(const double* __restrict__ Pall, int64_t nfft, int k,
                                                            double* __restrict__ freq, double* __restrict__ power) {
     __shared__ double red[kPeakBlock];
     __shared__ int cnt[kPeakBlock];
     __shared__ int found;
-    const int64_t last = nfft / 2;  // P has last + 1 entries
+    const int64_t last = nfft / 2;
+    const double* P = Pall + (size_t)blockIdx.x * (last + 1);
+    freq += (size_t)blockIdx.x * k;
+    power += (size_t)blockIdx.x * k;
     double m = 0.0;
     for (int64_t b = 2 + threadIdx.x; b <= last; b += kPeakBlock) m = fmax(m, P[b]);
     red[threadIdx.x] = m;
@@ -107,8 +119,7 @@ __global__ __launch_bounds__(kPeakBlock) void peaks_kernel(const double* __restr
         if (b < last) flag = P[b - 1] < P[b] && P[b] >= P[b + 1] && P[b] > thr;
         cnt[threadIdx.x] = flag;
         __syncthreads();
-        // inclusive scan (Hillis-Steele)
-        for (int off = 1; off < kPeakBlock; off <<= 1) {
+        for (int off = 1; off < kPeakBlock; off <<= 1) {  // inclusive scan
             const int v = threadIdx.x >= off ? cnt[threadIdx.x - off] : 0;
             __syncthreads();
             cnt[threadIdx.x] += v;
@@ -136,32 +147,74 @@ __global__ __launch_bounds__(kPeakBlock) void peaks_kernel(const double* __restr
 
 }  // namespace
 
-size_t modes_work_bytes(int64_t T, int n_probes) {
-    const int64_t nfft = nfft_for(T);
-    return 2 * (size_t)nfft * n_probes * sizeof(double2) + (size_t)(nfft / 2 + 1) * sizeof(double);
+int64_t modes_nfft(int64_t T) {
+    int64_t p = 1;
+    while (p < T) p *= 2;
+    return 4 * p;
 }
 
-hipError_t launch_modes(const double* trace, int64_t T, int np, int k, double* work, size_t work_bytes, double* freq,
-                        double* power, hipStream_t st) {
-    const int64_t nfft = nfft_for(T);
-    if (work_bytes < modes_work_bytes(T, np)) return hipErrorInvalidValue;
-    double2* x0 = reinterpret_cast<double2*>(work);
-    double2* x1 = x0 + (size_t)nfft * np;
-    double* P = reinterpret_cast<double*>(x1 + (size_t)nfft * np);
-    hipLaunchKernelGGL(prepare_kernel, dim3(np), dim3(kBlock), 0, st, trace, T, np, nfft, x0);
-    const unsigned fft_blocks = (unsigned)(((nfft / 2) * np + kBlock - 1) / kBlock);
-    double2* src = x0;
-    double2* dst = x1;
-    for (int64_t Ns = 1; Ns < nfft; Ns *= 2) {
-        hipLaunchKernelGGL(fft_pass_kernel, dim3(fft_blocks), dim3(kBlock), 0, st, src, dst, nfft, Ns, np);
-        double2* t = src;
-        src = dst;
-        dst = t;
+size_t modes_work_bytes(int64_t T, int max_cols, int max_groups) {
+    const int64_t nfft = modes_nfft(T);
+    return 2 * (size_t)nfft * max_cols * sizeof(double2) + (size_t)(nfft / 2 + 1) * max_groups * sizeof(double) +
+           2 * sizeof(int) * (size_t)max_groups + 256;
+}
+
+int modes_max_cols(int64_t T) {
+    const size_t per_col = 2 * (size_t)modes_nfft(T) * sizeof(double2);
+    return (int)std::max<size_t>(1, kChunkBytes / per_col);
+}
+
+hipError_t launch_modes_grouped(const double* trace, int64_t T, int64_t stride, const int* group_ncols, int groups,
+                                int k, double* work, size_t work_bytes, double* freq, double* power,
+                                hipStream_t st) {
+    const int64_t nfft = modes_nfft(T);
+    const int cap = modes_max_cols(T);
+    int max_group = 0;
+    for (int g = 0; g < groups; ++g) max_group = std::max(max_group, group_ncols[g]);
+    if (max_group > cap) return hipErrorInvalidValue;
+    int g0 = 0, col0 = 0;
+    while (g0 < groups) {
+        // chunk: groups [g0, g1) with at most cap columns
+        int g1 = g0, cols = 0;
+        while (g1 < groups && cols + group_ncols[g1] <= cap) cols += group_ncols[g1++];
+        const int ng = g1 - g0;
+        if (work_bytes < modes_work_bytes(T, cols, ng)) return hipErrorInvalidValue;
+        double2* x0 = reinterpret_cast<double2*>(work);
+        double2* x1 = x0 + (size_t)nfft * cols;
+        double* P = reinterpret_cast<double*>(x1 + (size_t)nfft * cols);
+        int* gcol = reinterpret_cast<int*>(P + (size_t)(nfft / 2 + 1) * ng);
+        int* gcnt = gcol + ng;
+        std::vector<int> h(2 * ng);
+        for (int g = 0, c = 0; g < ng; ++g) {
+            h[g] = c;
+            h[ng + g] = group_ncols[g0 + g];
+            c += group_ncols[g0 + g];
+        }
+        hipError_t e = hipMemcpyAsync(gcol, h.data(), sizeof(int) * 2 * ng, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        double2* src = x0;
+        double2* dst = x1;
+        if (cols > 0) {
+            hipLaunchKernelGGL(prepare_kernel, dim3(cols), dim3(kBlock), 0, st, trace, T, stride, col0, nfft, x0);
+            const unsigned fft_blocks = (unsigned)(((nfft / 2) * cols + kBlock - 1) / kBlock);
+            for (int64_t Ns = 1; Ns < nfft; Ns *= 2) {
+                hipLaunchKernelGGL(fft_pass_kernel, dim3(fft_blocks), dim3(kBlock), 0, st, src, dst, nfft, Ns, cols);
+                std::swap(src, dst);
+            }
+        }
+        hipLaunchKernelGGL(power_kernel, dim3((unsigned)((nfft / 2 + 1 + kBlock - 1) / kBlock), ng), dim3(kBlock), 0,
+                           st, src, nfft, gcol, gcnt, P);
+        hipLaunchKernelGGL(peaks_kernel, dim3(ng), dim3(kPeakBlock), 0, st, P, nfft, k, freq + (size_t)g0 * k,
+                           power + (size_t)g0 * k);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // the host group table is reused next chunk: wait for the copy
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        g0 = g1;
+        col0 += cols;
     }
-    hipLaunchKernelGGL(power_kernel, dim3((unsigned)((nfft / 2 + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, src,
-                       nfft, np, P);
-    hipLaunchKernelGGL(peaks_kernel, dim3(1), dim3(kPeakBlock), 0, st, P, nfft, k, freq, power);
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace lbw

@@ -37,6 +37,15 @@ __device__ inline float sum7(const float v[7]) {
     return v[0] + v[1] + v[2] + v[3] + v[4] + v[5] + v[6];
 }
 
+struct TileGeom {
+    int n0, n1, n2;
+    uint32_t N;
+    int bc_lo[3], bc_hi[3];
+    float c2, two_w0, damp;
+    const float4* tab4;
+    int ntx, nty, lz;
+};
+
 __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* __restrict__ fin) {
     const int64_t t = *(volatile const int64_t*)pr.tcount;
     __syncthreads();
@@ -61,38 +70,28 @@ __device__ inline float bounce(int wall, float damp, float out_l, float own_lb) 
     return wall == LBW_BC_BOUNCEBACK ? damp * out_l : (wall == LBW_BC_FREE ? own_lb : -out_l);
 }
 
+// One tile of one geometry: columns [x0, x0 + TX) x [y0, y0 + TY), planes
+// [z0, z0 + lz).  fin/fout point at the geometry's own population block.
 template <int TX>
-__global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
-                                                              const float* __restrict__ fin,
-                                                              float* __restrict__ fout) {
+__device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
+                                           float* __restrict__ fout, float (&sS)[2][(kThreads / TX + 2) * (TX + 2)],
+                                           float4 (&sE)[3][TX + 2][2]) {
     constexpr int TY = kThreads / TX;
     constexpr int W = TX + 2;
-    __shared__ float sS[2][(TY + 2) * W];
-    __shared__ float4 sE[3][W][2];
-
-    if (blockIdx.x == 0) probe_block(g, pr, fin);
-
     const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
-    const uint32_t N = (uint32_t)g.N;
+    const uint32_t N = g.N;
     const uint32_t plane = (uint32_t)n0 * (uint32_t)n1;
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     const float c2 = g.c2, two_w0 = g.two_w0, damp = g.damp;
-    const float4* __restrict__ tab4 = reinterpret_cast<const float4*>(g.tab);
-
-    const int xcd = blockIdx.x % kXcds;
-    const int slot = blockIdx.x / kXcds;
-    const int per_xcd_blocks = gridDim.x / kXcds;
-    const int t_begin = (int)(plan.tiles * xcd / kXcds);
-    const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
-
-    for (int tile = t_begin + slot; tile < t_end; tile += per_xcd_blocks) {
-        const int tx = tile % plan.ntx;
-        const int r1 = tile / plan.ntx;
-        const int ty = r1 % plan.nty;
-        const int chunk = r1 / plan.nty;
+    const float4* __restrict__ tab4 = g.tab4;
+    {
+        const int tx = tile % g.ntx;
+        const int r1 = tile / g.ntx;
+        const int ty = r1 % g.nty;
+        const int chunk = r1 / g.nty;
         const int x0 = tx * TX, y0 = ty * TY;
-        const int z0 = chunk * plan.lz;
-        const int z1 = min(z0 + plan.lz, n2);
+        const int z0 = chunk * g.lz;
+        const int z1 = min(z0 + g.lz, n2);
         const int wdt = min(TX, n0 - x0);
         const int hgt = min(TY, n1 - y0);
         const int x = x0 + lx, y = y0 + ly;
@@ -312,6 +311,103 @@ __global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeAr
     }
 }
 
+template <int TX>
+__global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
+                                                              const float* __restrict__ fin,
+                                                              float* __restrict__ fout) {
+    __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2)];
+    __shared__ float4 sE[3][TX + 2][2];
+    if (blockIdx.x == 0) probe_block(g, pr, fin);
+    TileGeom tg;
+    tg.n0 = g.n0;
+    tg.n1 = g.n1;
+    tg.n2 = g.n2;
+    tg.N = (uint32_t)g.N;
+    for (int a = 0; a < 3; ++a) {
+        tg.bc_lo[a] = g.bc_lo[a];
+        tg.bc_hi[a] = g.bc_hi[a];
+    }
+    tg.c2 = g.c2;
+    tg.two_w0 = g.two_w0;
+    tg.damp = g.damp;
+    tg.tab4 = reinterpret_cast<const float4*>(g.tab);
+    tg.ntx = plan.ntx;
+    tg.nty = plan.nty;
+    tg.lz = plan.lz;
+    const int xcd = blockIdx.x % kXcds;
+    const int per_xcd_blocks = gridDim.x / kXcds;
+    const int t_begin = (int)(plan.tiles * xcd / kXcds);
+    const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
+    for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
+        march_tile<TX>(tg, tile, fin, fout, sS, sE);
+}
+
+// Batch of geometries advanced by one launch: tiles of all geometries form
+// one list (geometry h owns tiles [tile_begin, tile_begin + tiles)), split
+// into one contiguous range per XCD.  Block b first records the probes of
+// geometries b, b + gridDim.x, ... (one step counter per geometry).
+template <int TX>
+__global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* __restrict__ items, int n_items,
+                                                              int64_t tiles_total, BatchProbeArgs bp,
+                                                              const float* __restrict__ fin,
+                                                              float* __restrict__ fout) {
+    __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2)];
+    __shared__ float4 sE[3][TX + 2][2];
+    for (int h = blockIdx.x; h < n_items; h += gridDim.x) {
+        const BatchItem& it = items[h];
+        const int64_t t = *(volatile const int64_t*)(bp.tcount + h);
+        __syncthreads();
+        if (t < bp.t_max) {
+            const float* f = fin + it.f_off;
+            for (int p = threadIdx.x; p < it.n_probes; p += blockDim.x) {
+                const uint32_t node = (uint32_t)bp.nodes[it.probe_off + p];
+                double s = 0.0;
+                for (int l = 0; l < 7; ++l) s += (double)f[l * it.N + node];
+                const uint32_t i0 = node % (uint32_t)it.n0;
+                const uint32_t i2 = node / ((uint32_t)it.n0 * (uint32_t)it.n1);
+                bp.trace[t * bp.stride + it.probe_off + p] = s / bp.sqrtg[it.sg_off + i0 + (uint32_t)it.n0 * i2];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) *(volatile int64_t*)(bp.tcount + h) = t + 1;
+    }
+    const int xcd = blockIdx.x % kXcds;
+    const int per_xcd_blocks = gridDim.x / kXcds;
+    const int64_t t_begin = tiles_total * xcd / kXcds;
+    const int64_t t_end = tiles_total * (xcd + 1) / kXcds;
+    int h = 0;
+    for (int64_t tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks) {
+        // geometry owning this tile (tiles ascend, so search upward from the last one)
+        if (!(tile >= items[h].tile_begin && tile < items[h].tile_begin + items[h].tiles)) {
+            int lo = 0, hi = n_items - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (items[mid].tile_begin <= tile) lo = mid;
+                else hi = mid - 1;
+            }
+            h = lo;
+        }
+        const BatchItem& it = items[h];
+        TileGeom tg;
+        tg.n0 = it.n0;
+        tg.n1 = it.n1;
+        tg.n2 = it.n2;
+        tg.N = it.N;
+        for (int a = 0; a < 3; ++a) {
+            tg.bc_lo[a] = it.bc_lo[a];
+            tg.bc_hi[a] = it.bc_hi[a];
+        }
+        tg.c2 = it.c2;
+        tg.two_w0 = it.two_w0;
+        tg.damp = it.damp;
+        tg.tab4 = bp.tab4 + 2 * (size_t)it.tab_off;
+        tg.ntx = it.ntx;
+        tg.nty = it.nty;
+        tg.lz = it.lz;
+        march_tile<TX>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sE);
+    }
+}
+
 }  // namespace
 
 int march_tx_for(int n0) { return n0 <= 32 ? 32 : 64; }
@@ -329,6 +425,24 @@ hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchP
         hipLaunchKernelGGL(step_march_kernel<32>, dim3(plan.blocks), dim3(kThreads), 0, st, g, pr, plan, fin, fout);
     else
         hipLaunchKernelGGL(step_march_kernel<64>, dim3(plan.blocks), dim3(kThreads), 0, st, g, pr, plan, fin, fout);
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int tx) {
+    int nb = 0;
+    hipError_t e = tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32>, kThreads, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64>, kThreads, 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int blocks,
+                             const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st) {
+    if (tx == 32)
+        hipLaunchKernelGGL(step_batch_kernel<32>, dim3(blocks), dim3(kThreads), 0, st, items, n_items, tiles_total,
+                           bp, fin, fout);
+    else
+        hipLaunchKernelGGL(step_batch_kernel<64>, dim3(blocks), dim3(kThreads), 0, st, items, n_items, tiles_total,
+                           bp, fin, fout);
     return hipGetLastError();
 }
 
