@@ -250,6 +250,38 @@ int lbw_batch_modes(lbw_batch_t b, int k, double* freq_out, double* power_out);
 /* Releases the batch (waits for its stream); caller buffers untouched. */
 int lbw_batch_free(lbw_batch_t b);
 
+/* ------------------------------------------------------------------------
+ * Surrogate MLP (learned map from horn-profile parameters to resonant
+ * frequencies, trained on spectra from the batched LBM).  Dense layers
+ * widths[0] -> ... -> widths[n_layers], tanh on hidden layers, linear output.
+ * BF16 weights and activations, FP32 accumulation (MFMA), FP32 master
+ * weights and Adam.  Parameters are library-owned: FP32, layer by layer,
+ * W_l (widths[l+1] x widths[l], row-major) then b_l (widths[l+1]).
+ * Device pointers (x, t, w, y, loss, grad) are caller-owned, row-major.
+ * ---------------------------------------------------------------------- */
+typedef struct lbw_mlp* lbw_mlp_t;
+
+/* Zero parameters; max_batch bounds B of every later call.  Errors:
+ * LBW_EINVAL (n_layers outside [1, 16], a width outside [1, 4096],
+ * max_batch < 1), LBW_ENOMEM. */
+int lbw_mlp_create(const int32_t* widths, int n_layers, int max_batch, void* stream, lbw_mlp_t* out);
+int lbw_mlp_param_count(lbw_mlp_t m, int64_t* count);
+/* Copies host FP32 parameters in (and resets the Adam state) / out.  Synchronises. */
+int lbw_mlp_set_params(lbw_mlp_t m, const float* host_params);
+int lbw_mlp_get_params(lbw_mlp_t m, float* host_params);
+/* y[B, widths[L]] = network(x[B, widths[0]]) (device, FP32). */
+int lbw_mlp_forward(lbw_mlp_t m, const float* x, int B, float* y);
+/* Loss sum_ij w_ij (y_ij - t_ij)^2 / weight_sum (w may be NULL: all 1) and
+ * its gradient with respect to the FP32 parameters, kept for
+ * lbw_mlp_adam_step; loss (1 float) and grad (param_count floats) receive
+ * copies when not NULL. */
+int lbw_mlp_loss_grad(lbw_mlp_t m, const float* x, const float* t, const float* w, int B, float weight_sum,
+                      float* loss, float* grad);
+/* One Adam step (bias-corrected) on the last gradient.  Errors: LBW_ESTATE
+ * before any lbw_mlp_loss_grad, LBW_EINVAL for bad hyper-parameters. */
+int lbw_mlp_adam_step(lbw_mlp_t m, float lr, float beta1, float beta2, float eps);
+int lbw_mlp_free(lbw_mlp_t m);
+
 /* Message of the calling thread's last error ("" if none). */
 const char* lbw_last_error(void);
 

@@ -27,7 +27,9 @@ SYMBOLS = ("lbw_make_geometry", "lbw_free_geometry", "lbw_geometry_export", "lbw
            "lbw_step_n", "lbw_autotune", "lbw_set_graph_block", "lbw_probe", "lbw_modes", "lbw_state_info",
            "lbw_pressure", "lbw_free_state", "lbw_batch_make", "lbw_batch_layout", "lbw_batch_set_step_config",
            "lbw_batch_get_step_config", "lbw_batch_autotune", "lbw_batch_set_graph_block", "lbw_batch_step_n",
-           "lbw_batch_info", "lbw_batch_probe", "lbw_batch_modes", "lbw_batch_free", "lbw_last_error")
+           "lbw_batch_info", "lbw_batch_probe", "lbw_batch_modes", "lbw_batch_free", "lbw_mlp_create",
+           "lbw_mlp_param_count", "lbw_mlp_set_params", "lbw_mlp_get_params", "lbw_mlp_forward", "lbw_mlp_loss_grad",
+           "lbw_mlp_adam_step", "lbw_mlp_free", "lbw_last_error")
 
 
 class GeometryDesc(ctypes.Structure):
@@ -113,6 +115,14 @@ def lib():
         L.lbw_batch_probe.argtypes = [vp, vp, i64, i64]
         L.lbw_batch_modes.argtypes = [vp, i32, vp, vp]
         L.lbw_batch_free.argtypes = [vp]
+        L.lbw_mlp_create.argtypes = [ctypes.POINTER(ctypes.c_int32), i32, i32, vp, ctypes.POINTER(vp)]
+        L.lbw_mlp_param_count.argtypes = [vp, ctypes.POINTER(i64)]
+        L.lbw_mlp_set_params.argtypes = [vp, vp]
+        L.lbw_mlp_get_params.argtypes = [vp, vp]
+        L.lbw_mlp_forward.argtypes = [vp, vp, i32, vp]
+        L.lbw_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
+        L.lbw_mlp_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        L.lbw_mlp_free.argtypes = [vp]
         L.lbw_last_error.restype = ctypes.c_char_p
         for name in SYMBOLS:
             getattr(L, name).restype = ctypes.c_int if name != "lbw_last_error" else ctypes.c_char_p
@@ -382,6 +392,70 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             lib().lbw_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """Surrogate network on the device (BF16 weights/activations, FP32
+    accumulation and master weights, Adam)."""
+
+    def __init__(self, widths, max_batch: int, stream=None):
+        import torch
+        self.widths = [int(v) for v in widths]
+        arr = (ctypes.c_int32 * len(self.widths))(*self.widths)
+        h = ctypes.c_void_p()
+        check(lib().lbw_mlp_create(arr, len(self.widths) - 1, int(max_batch), _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_int64()
+        check(lib().lbw_mlp_param_count(self.handle, ctypes.byref(n)))
+        self.n_params = n.value
+        self.max_batch = int(max_batch)
+        self._dev = torch.device("cuda", torch.cuda.current_device())
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        assert p.size == self.n_params
+        check(lib().lbw_mlp_set_params(self.handle, p.ctypes.data))
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.n_params, dtype=np.float32)
+        check(lib().lbw_mlp_get_params(self.handle, p.ctypes.data))
+        return p
+
+    def forward(self, x):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float32, device=self._dev).contiguous()
+        B = x.shape[0]
+        y = torch.empty((B, self.widths[-1]), dtype=torch.float32, device=self._dev)
+        for s in range(0, B, self.max_batch):
+            e = min(B, s + self.max_batch)
+            check(lib().lbw_mlp_forward(self.handle, x[s:e].data_ptr(), e - s, y[s:e].data_ptr()))
+        return y
+
+    def loss_grad(self, x, t, w=None, want_grad=False):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float32, device=self._dev).contiguous()
+        t = torch.as_tensor(t, dtype=torch.float32, device=self._dev).contiguous()
+        w = None if w is None else torch.as_tensor(w, dtype=torch.float32, device=self._dev).contiguous()
+        wsum = float(t.numel() if w is None else w.sum().item())
+        loss = torch.zeros(1, dtype=torch.float32, device=self._dev)
+        grad = torch.zeros(self.n_params, dtype=torch.float32, device=self._dev) if want_grad else None
+        check(lib().lbw_mlp_loss_grad(self.handle, x.data_ptr(), t.data_ptr(), None if w is None else w.data_ptr(),
+                                      x.shape[0], wsum, loss.data_ptr(), None if grad is None else grad.data_ptr()))
+        return loss, grad
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        check(lib().lbw_mlp_adam_step(self.handle, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lbw_mlp_free(self.handle)
             self.handle = None
 
     def __del__(self):
