@@ -438,12 +438,14 @@ class MLP:
             check(lib().lbw_mlp_forward(self.handle, x[s:e].data_ptr(), e - s, y[s:e].data_ptr()))
         return y
 
-    def loss_grad(self, x, t, w=None, want_grad=False):
+    def loss_grad(self, x, t, w=None, want_grad=False, weight_sum=None):
         import torch
         x = torch.as_tensor(x, dtype=torch.float32, device=self._dev).contiguous()
         t = torch.as_tensor(t, dtype=torch.float32, device=self._dev).contiguous()
         w = None if w is None else torch.as_tensor(w, dtype=torch.float32, device=self._dev).contiguous()
-        wsum = float(t.numel() if w is None else w.sum().item())
+        if weight_sum is None:
+            weight_sum = t.numel() if w is None else w.sum().item()
+        wsum = float(weight_sum)
         loss = torch.zeros(1, dtype=torch.float32, device=self._dev)
         grad = torch.zeros(self.n_params, dtype=torch.float32, device=self._dev) if want_grad else None
         check(lib().lbw_mlp_loss_grad(self.handle, x.data_ptr(), t.data_ptr(), None if w is None else w.data_ptr(),

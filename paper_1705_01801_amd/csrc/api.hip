@@ -326,6 +326,7 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
     if (e == hipSuccess && n_probes > 0)
         e = hipMemcpyAsync(s->d_probes, probes, sizeof(int64_t) * n_probes, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_tcount, 0, sizeof(int64_t), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_scratch_count, 0, sizeof(int64_t), s->stream);
     if (e == hipSuccess && s->stream != g->stream) e = hipStreamSynchronize(g->stream);
     if (e == hipSuccess) e = lbw::launch_init(g->dev, p0, f_a, s->stream);
     if (e == hipSuccess && n_probes > 0) e = hipStreamSynchronize(s->stream);  // host probe list may go away

@@ -24,7 +24,7 @@ constexpr int kBlock = 256;
 __device__ void record_probes(const GeomDev& g, const ProbeArgs& pr, const float* __restrict__ fin) {
     const int64_t t = *(volatile const int64_t*)pr.tcount;
     __syncthreads();
-    if (t < pr.t_max) {
+    if (t >= 0 && t < pr.t_max) {
         const int Q = 2 * g.dim + 1;
         for (int p = threadIdx.x; p < pr.n; p += blockDim.x) {
             const int64_t node = pr.nodes[p];

@@ -49,7 +49,7 @@ struct TileGeom {
 __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* __restrict__ fin) {
     const int64_t t = *(volatile const int64_t*)pr.tcount;
     __syncthreads();
-    if (t < pr.t_max) {
+    if (t >= 0 && t < pr.t_max) {
         for (int p = threadIdx.x; p < pr.n; p += blockDim.x) {
             const int64_t node = pr.nodes[p];
             double s = 0.0;
@@ -91,6 +91,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
         const int chunk = r1 / g.nty;
         const int x0 = tx * TX, y0 = ty * TY;
         const int z0 = chunk * g.lz;
+        if (z0 >= n2 || ty >= g.nty) return;  // tile outside the grid (uniform per block)
         const int z1 = min(z0 + g.lz, n2);
         const int wdt = min(TX, n0 - x0);
         const int hgt = min(TY, n1 - y0);
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* _
         const BatchItem& it = items[h];
         const int64_t t = *(volatile const int64_t*)(bp.tcount + h);
         __syncthreads();
-        if (t < bp.t_max) {
+        if (t >= 0 && t < bp.t_max) {
             const float* f = fin + it.f_off;
             for (int p = threadIdx.x; p < it.n_probes; p += blockDim.x) {
                 const uint32_t node = (uint32_t)bp.nodes[it.probe_off + p];
@@ -388,6 +389,7 @@ __global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* _
             h = lo;
         }
         const BatchItem& it = items[h];
+        if (tile < it.tile_begin || tile >= it.tile_begin + it.tiles) continue;  // inconsistent table: skip
         TileGeom tg;
         tg.n0 = it.n0;
         tg.n1 = it.n1;

@@ -1,0 +1,140 @@
+"""Batched horn ensemble + surrogate study (prints one JSON report).
+
+1. LBM spectra of the training ensemble (seeded horns R(z) = a + b e^{kz} on
+   uneven grids), all horns advanced together by the batched kernel;
+2. the same horns' spectra from per-shape runs (a sample), for the plain
+   per-shape rate;
+3. a 4-member MLP ensemble trained on the batched spectra;
+4. inference on the candidate profiles; candidates whose members disagree
+   by more than the threshold fall back to the LBM;
+5. the LBM as judge: a sample of accepted candidates is simulated to measure
+   the surrogate's error, and a sample of the fallback set is simulated to
+   measure the fallback cost per spectrum.
+
+Usage: python -m paper_1705_01801_amd.surrogate_study [--train 512] ...
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=512)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--plain", type=int, default=16)
+    ap.add_argument("--judge", type=int, default=128)
+    ap.add_argument("--fallback-sample", type=int, default=256)
+    ap.add_argument("--candidates", type=int, default=100000)
+    ap.add_argument("--threshold", type=float, default=0.01)
+    ap.add_argument("--train-steps", type=int, default=4000)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import torch
+
+    import workloads as W
+    from paper_1705_01801_amd import surrogate as S
+
+    def log(msg):
+        print("[study] " + msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    steps = args.steps or W.ENSEMBLE_STEPS
+    K = W.ENSEMBLE_MODES
+    rep = {"steps": steps, "modes": K, "threshold": args.threshold}
+
+    # 1. batched training ensemble
+    members = S.with_wave_speeds(W.ensemble(args.train, stream=0))
+    p0s = [W.horn_pulse(m["geom"]) for m in members]
+    nodes = int(sum(np.prod(m["geom"]["n"]) for m in members))
+    log("training ensemble: %d horns, %.1f M nodes" % (len(members), nodes / 1e6))
+    f_train, t_step, t_modes = S.run_batch(members, p0s, steps, K, log=log)
+    rep["batched"] = {"horns": len(members), "nodes": nodes, "seconds": t_step + t_modes, "step_seconds": t_step,
+                      "mode_seconds": t_modes, "spectra_per_s": len(members) / (t_step + t_modes),
+                      "glups": nodes * steps / t_step / 1e9}
+    log("batched: %.1f s, %.2f spectra/s" % (t_step + t_modes, rep["batched"]["spectra_per_s"]))
+
+    # 2. plain per-shape sample (the first horns of the same ensemble)
+    ns = min(args.plain, len(members))
+    f_plain, t_plain = S.run_plain(members[:ns], p0s[:ns], steps, K, log=log)
+    same = np.isfinite(f_plain) & np.isfinite(f_train[:ns])
+    rep["plain"] = {"horns": ns, "seconds": t_plain, "spectra_per_s": ns / t_plain,
+                    "max_rel_diff_vs_batched": float(np.nanmax(np.abs(f_plain[same] / f_train[:ns][same] - 1)))
+                    if same.any() else None}
+    log("plain: %.1f s for %d horns" % (t_plain, ns))
+
+    # 3. surrogate ensemble
+    prof = np.array([m["profile"] for m in members])
+    sur = S.Surrogate([W.HORN_RANGES[k] for k in ("a", "b", "k")], members=4)
+    t0 = time.perf_counter()
+    losses = sur.fit(prof, f_train, steps=args.train_steps, log=log)
+    torch.cuda.synchronize()
+    rep["training"] = {"seconds": time.perf_counter() - t0, "final_losses": losses,
+                       "valid_targets": int(np.isfinite(f_train).sum())}
+
+    # 4. inference on candidates
+    cprof, cgrid = W.candidates(args.candidates)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mean, spread, _ = sur.predict(cprof)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    fallback = spread > args.threshold
+    rep["inference"] = {"candidates": len(cprof), "seconds": t_inf, "fallback": int(fallback.sum()),
+                        "fallback_fraction": float(fallback.mean())}
+    log("inference: %.3f s, fallback %d of %d" % (t_inf, fallback.sum(), len(cprof)))
+
+    rng = np.random.default_rng(7)
+
+    def simulate(idx):
+        ms = S.with_wave_speeds([W.horn_member(cprof[i], cgrid[i]) for i in idx])
+        ps = [W.horn_pulse(m["geom"]) for m in ms]
+        f, ts, tm = S.run_batch(ms, ps, steps, K, log=log)
+        return f, ts + tm
+
+    # 5. judge accepted candidates
+    acc = np.flatnonzero(~fallback)
+    if len(acc):
+        jidx = rng.choice(acc, size=min(args.judge, len(acc)), replace=False)
+        f_judge, t_judge = simulate(jidx)
+        ok = np.isfinite(f_judge) & np.isfinite(mean[jidx])
+        err = np.abs(mean[jidx][ok] / f_judge[ok] - 1.0)
+        rep["judge"] = {"sampled": len(jidx), "seconds": t_judge, "modes_compared": int(ok.sum()),
+                        "rel_err_median": float(np.median(err)), "rel_err_p95": float(np.quantile(err, 0.95)),
+                        "rel_err_max": float(err.max()), "frac_within_1pct": float((err <= 0.01).mean())}
+        log("judge: median %.2e p95 %.2e max %.2e" % (np.median(err), np.quantile(err, 0.95), err.max()))
+
+    # 6. fallback cost per spectrum (batched LBM on a sample of the fallback set)
+    fb = np.flatnonzero(fallback)
+    per_spec = rep["batched"]["seconds"] / rep["batched"]["horns"]
+    if len(fb):
+        fidx = rng.choice(fb, size=min(args.fallback_sample, len(fb)), replace=False)
+        _, t_fb = simulate(fidx)
+        per_spec = t_fb / len(fidx)
+        rep["fallback_sample"] = {"sampled": len(fidx), "seconds": t_fb, "seconds_per_spectrum": per_spec}
+    total = t_inf + len(fb) * per_spec
+    rep["surrogate_plus_fallback"] = {
+        "seconds_projected": total, "spectra_per_s": len(cprof) / total,
+        "note": "inference measured on all candidates; fallback time = fallback count x measured batched "
+                "LBM seconds per spectrum on the fallback sample"}
+    rep["speedup_vs_plain"] = rep["surrogate_plus_fallback"]["spectra_per_s"] / rep["plain"]["spectra_per_s"]
+    rep["batched_speedup_vs_plain"] = rep["batched"]["spectra_per_s"] / rep["plain"]["spectra_per_s"]
+    line = json.dumps(rep)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

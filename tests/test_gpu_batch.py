@@ -78,6 +78,9 @@ def test_batch_member_matches_oracle():
         assert np.abs(b.probe()[:, cols] - tr).max() <= 1e-5 * np.abs(tr).max()
 
 
+@pytest.mark.skip(reason="batch autotuning faulted the GPU twice (uninitialised step counters read as a trace "
+                         "row); the counters are now zeroed and the row check requires t >= 0, but the path stays "
+                         "disabled until that fix has been checked on a GPU")
 def test_batch_launch_shapes_autotune_graphs_identical():
     geoms, P0s, probes = members()
     ref = None
@@ -122,6 +125,25 @@ def test_batch_modes_equal_single_modes():
         assert np.array_equal(fs[ok], fb[h][ok]) and np.array_equal(ps[ok], pb[h][ok])
         fo, _ = oracle.modes(sim.probe(), k)
         assert np.abs(fs[ok] / fo[ok] - 1).max() <= 1e-10
+
+
+def test_batch_launch_shapes_and_graphs_identical():
+    """Launch shapes and graph blocks change nothing (no autotuning)."""
+    geoms, P0s, probes = members()
+    ref = None
+    for cfg, block in [((32, 16, 0), 0), ((64, 5, 8), 16), ((32, 64, 24), 7)]:
+        say("batch shape", cfg, block)
+        b = lbw.Batch(geoms, P0s, probes, t_max=70)
+        b.set_step_config(*cfg)
+        b.set_graph_block(block)
+        b.step(70)
+        out = [b.populations(h).cpu().numpy().copy() for h in range(len(geoms))], b.probe()
+        if ref is None:
+            ref = out
+        else:
+            for x, y in zip(out[0], ref[0]):
+                assert np.array_equal(x, y)
+            assert np.array_equal(out[1], ref[1])
 
 
 def test_batch_rejects_bad_input():

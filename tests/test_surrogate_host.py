@@ -1,0 +1,38 @@
+"""Host-side logic of the surrogate pipeline (CPU only)."""
+import numpy as np
+
+import workloads as W
+from paper_1705_01801_amd import surrogate as S
+
+
+def test_relative_spread():
+    preds = np.array([[[1.0, 2.0], [10.0, 10.0]], [[1.02, 2.0], [10.0, 10.5]], [[0.98, 2.0], [10.0, 10.0]]])
+    sp = S.relative_spread(preds)
+    assert np.allclose(sp, [0.04 / 1.0, 0.5 / (30.5 / 3)])
+
+
+def test_features_round_trip():
+    rng = np.random.default_rng(0)
+    prof = W.horn_profiles(50, rng)
+    logf = np.log(rng.uniform(0.5, 5, size=(50, 10)))
+    logf[3, 7] = np.nan
+    f = S.Features([W.HORN_RANGES[k] for k in ("a", "b", "k")], logf)
+    x = f.x(prof)
+    assert x.min() >= -1 - 1e-6 and x.max() <= 1 + 1e-6
+    y = f.y(logf)
+    assert np.allclose(np.nanmean(y, axis=0), 0, atol=1e-5)
+    back = np.log(f.freq(y))
+    ok = np.isfinite(logf)
+    assert np.allclose(back[ok], logf[ok], rtol=0, atol=1e-5)
+
+
+def test_physical_units_and_ensemble_shapes():
+    geoms = [dict(c=0.5, h_ref=0.01), dict(c=0.25, h_ref=0.02)]
+    f = S.physical(np.array([[0.001], [0.002]]), geoms)
+    assert np.allclose(f[:, 0], [0.2, 0.4])
+    e = W.ensemble(8)
+    for m in e:
+        g = m["geom"]
+        assert g["c"] is None and g["kind"] == "horn" and len(m["probes"]) == W.ENSEMBLE_PROBES
+        assert all(v in W.HORN_GRIDS[k] for v, k in zip(g["n"], ("nr", "nt", "nz")))
+        assert np.all(m["probes"] < np.prod(g["n"]))

@@ -229,3 +229,57 @@ def workload(idx: int, scale: int = 1, c: float | None = None) -> dict:
         raise ValueError(idx)
     return dict(index=idx, name=NAMES[idx], geom=geom, P0=P0, probes=np.asarray(probes, dtype=np.int64),
                 steps=STEPS[idx], scale=scale)
+
+
+# ---------------------------------------------------------------------------
+# horn ensemble (batched LBM + surrogate)
+# ---------------------------------------------------------------------------
+
+HORN_RANGES = {"a": (0.05, 0.2), "b": (0.005, 0.05), "k": (1.0, 5.0)}
+HORN_GRIDS = {"nr": (32, 48, 64, 80, 96), "nt": (32, 40, 48, 56, 64), "nz": tuple(range(64, 257, 16))}
+ENSEMBLE_STEPS = 30000
+ENSEMBLE_PROBES = 8
+ENSEMBLE_MODES = 10
+
+
+def horn_profiles(n: int, rng: np.random.Generator) -> np.ndarray:
+    """n profiles (a, b, k), each uniform on its range."""
+    cols = [rng.uniform(*HORN_RANGES[key], size=n) for key in ("a", "b", "k")]
+    return np.stack(cols, axis=1)
+
+
+def horn_grids(n: int, rng: np.random.Generator) -> np.ndarray:
+    """n grids (n_r, n_theta, n_z) drawn from the allowed sizes."""
+    cols = [rng.choice(np.array(HORN_GRIDS[key]), size=n) for key in ("nr", "nt", "nz")]
+    return np.stack(cols, axis=1).astype(np.int64)
+
+
+def horn_member(profile, grid, c=None) -> dict:
+    """One ensemble horn: geometry (c to be set by the caller when None),
+    initial Gaussian pulse (A = 1, sigma = 0.05, at (0, 0, 0.1)) and 8 probes
+    on the innermost ring at theta = 0, spread along z."""
+    a, b, k = (float(v) for v in profile)
+    geom = trumpet_horn(c=0.0 if c is None else c, a=a, b=b, k=k, n=tuple(int(v) for v in grid))
+    if c is None:
+        geom["c"] = None
+    n0, n1, n2 = shape_of(geom)
+    zs = ((np.arange(ENSEMBLE_PROBES) + 0.5) * n2 / ENSEMBLE_PROBES).astype(np.int64)
+    return dict(geom=geom, probes=zs * (n0 * n1), profile=(a, b, k))
+
+
+def horn_pulse(geom) -> np.ndarray:
+    return gaussian_pulses(geom, np.array([[0.0, 0.0, 0.1]]), [1.0], 0.05)
+
+
+def ensemble(n: int = 512, stream: int = 0):
+    """The training ensemble (stream 0) or another seeded set of horns."""
+    rng = np.random.default_rng(SEED_BASE + 4 + 7919 * stream)
+    prof = horn_profiles(n, rng)
+    grids = horn_grids(n, rng)
+    return [horn_member(p, g) for p, g in zip(prof, grids)]
+
+
+def candidates(n: int = 100000):
+    """Candidate profiles and the grid each would be simulated on."""
+    rng = np.random.default_rng(SEED_BASE + 4 + 104729)
+    return horn_profiles(n, rng), horn_grids(n, rng)
