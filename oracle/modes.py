@@ -9,8 +9,11 @@ information is the peak set of the probe signal's power spectrum.  Rule:
      w[t] = 1/2 - 1/2 cos(2 pi t / (T - 1));
   2. zero-pad to nfft = 4 * (smallest power of two >= T), FFT, power |X_k|^2;
   3. sum the power over probes;
-  4. peaks: bins k in [2, nfft/2 - 1] with P[k-1] < P[k] >= P[k+1] and
-     P[k] > rel_threshold * max_{k >= 2} P;
+  4. peaks: bins k in [16, nfft/2 - 1] with P[k-1] < P[k] >= P[k+1] and
+     P[k] > rel_threshold * max_{k >= 16} P.  The main lobe of the window's
+     transform is 2/T cycles per step wide on each side, 8 nfft/(4T) <= 16
+     bins: below bin 16 a peak can be the leakage of a slow drift that the
+     mean removal leaves (a decaying baseline), not a resonance;
   5. refine each by a parabola through ln P at k-1, k, k+1 (no refinement,
      delta = 0, when P[k-1] or P[k+1] is zero):
      delta = (ln P[k-1] - ln P[k+1]) / (2 (ln P[k-1] - 2 ln P[k] + ln P[k+1])),
@@ -21,6 +24,9 @@ information is the peak set of the probe signal's power spectrum.  Rule:
 from __future__ import annotations
 
 import numpy as np
+
+
+FIRST_BIN = 16
 
 
 def nfft_for(T: int) -> int:
@@ -49,11 +55,11 @@ def modes(trace: np.ndarray, k: int, rel_threshold: float = 1e-3):
     nfft = 2 * (P.size - 1)
     freq = np.full(k, np.nan)
     powr = np.full(k, np.nan)
-    if P.size < 5:
+    if nfft // 2 <= FIRST_BIN + 1:
         return freq, powr
-    pmax = P[2:].max()
+    pmax = P[FIRST_BIN:].max()
     found = 0
-    for b in range(2, nfft // 2):
+    for b in range(FIRST_BIN, nfft // 2):
         if found == k:
             break
         if P[b - 1] < P[b] and P[b] >= P[b + 1] and P[b] > rel_threshold * pmax:

@@ -6,9 +6,11 @@
 // the symmetric Hann window 1/2 - 1/2 cos(2 pi t / (T - 1)), zero-pad to
 // nfft = 4 * nextpow2(T), FFT (radix-2 Stockham, natural-order output),
 // P_k = sum over a group's probes of |X_k|^2 for k in [0, nfft/2]; peaks are
-// bins b in [2, nfft/2 - 1] with P[b-1] < P[b] >= P[b+1] and
-// P[b] > 1e-3 max P[2:], refined by a parabola through ln P (no refinement
-// when a neighbour is 0).
+// bins b in [16, nfft/2 - 1] with P[b-1] < P[b] >= P[b+1] and
+// P[b] > 1e-3 max P[16:], refined by a parabola through ln P (no refinement
+// when a neighbour is 0).  Bin 16 is the first bin outside the Hann window's
+// DC main lobe (half-width 2/T cycles per step = at most 16 bins), where the
+// leakage of a slow baseline drift would otherwise show up as a peak.
 //
 // A "group" is the set of probes of one geometry: consecutive columns of a
 // trace whose rows hold `stride` values.  Groups are processed in chunks so
@@ -23,6 +25,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kPeakBlock = 1024;
+constexpr int64_t kFirstBin = 16;
 constexpr size_t kChunkBytes = size_t(1) << 30;  // FFT work space per chunk
 
 // One block per column: mean, then windowed and zero-padded complex input.
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(kPeakBlock) void peaks_kernel(const double* __restr
     freq += (size_t)blockIdx.x * k;
     power += (size_t)blockIdx.x * k;
     double m = 0.0;
-    for (int64_t b = 2 + threadIdx.x; b <= last; b += kPeakBlock) m = fmax(m, P[b]);
+    for (int64_t b = kFirstBin + threadIdx.x; b <= last; b += kPeakBlock) m = fmax(m, P[b]);
     red[threadIdx.x] = m;
     __syncthreads();
     for (int w = kPeakBlock / 2; w > 0; w >>= 1) {
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(kPeakBlock) void peaks_kernel(const double* __restr
     }
     if (threadIdx.x == 0) found = 0;
     __syncthreads();
-    for (int64_t base = 2; base < last; base += kPeakBlock) {
+    for (int64_t base = kFirstBin; base < last; base += kPeakBlock) {
         if (found >= k) break;  // uniform: found is read after a barrier
         const int64_t b = base + threadIdx.x;
         int flag = 0;

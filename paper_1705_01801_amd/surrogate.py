@@ -47,7 +47,7 @@ def physical(freq_steps: np.ndarray, geoms) -> np.ndarray:
     return freq_steps * scale[:, None]
 
 
-def run_batch(members, p0s, steps: int, k: int, chunk: int = 2000, tune: bool = False, log=None):
+def run_batch(members, p0s, steps: int, k: int, chunk: int = 2000, tune: bool = False, log=None, keep_trace=False):
     """Advances all members together; returns (physical frequencies [n, k],
     seconds of stepping, seconds of mode extraction)."""
     import torch
@@ -68,9 +68,12 @@ def run_batch(members, p0s, steps: int, k: int, chunk: int = 2000, tune: bool = 
     torch.cuda.synchronize()
     t_step = time.perf_counter() - t0
     t1 = time.perf_counter()
-    f, _ = b.modes(k)
+    f, pw = b.modes(k)
     t_modes = time.perf_counter() - t1
+    trace = b.probe() if keep_trace else None
     b.close()
+    if keep_trace:
+        return physical(f, geoms), t_step, t_modes, pw, trace
     return physical(f, geoms), t_step, t_modes
 
 

@@ -35,6 +35,8 @@ def main(argv=None):
     ap.add_argument("--threshold", type=float, default=0.01)
     ap.add_argument("--train-steps", type=int, default=4000)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--save-npz", default=None, help="write training spectra (and traces) here")
+    ap.add_argument("--train-only", action="store_true", help="stop after the batched training ensemble")
     args = ap.parse_args(argv)
 
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -58,11 +60,20 @@ def main(argv=None):
     p0s = [W.horn_pulse(m["geom"]) for m in members]
     nodes = int(sum(np.prod(m["geom"]["n"]) for m in members))
     log("training ensemble: %d horns, %.1f M nodes" % (len(members), nodes / 1e6))
-    f_train, t_step, t_modes = S.run_batch(members, p0s, steps, K, log=log)
+    f_train, t_step, t_modes, p_train, tr_train = S.run_batch(members, p0s, steps, K, log=log, keep_trace=True)
+    if args.save_npz:
+        np.savez_compressed(args.save_npz, profiles=np.array([m["profile"] for m in members]),
+                            grids=np.array([m["geom"]["n"] for m in members]),
+                            c=np.array([m["geom"]["c"] for m in members]),
+                            h_ref=np.array([m["geom"]["h_ref"] for m in members]), freq=f_train, power=p_train,
+                            trace=tr_train[::2, 1::W.ENSEMBLE_PROBES].astype(np.float32))
     rep["batched"] = {"horns": len(members), "nodes": nodes, "seconds": t_step + t_modes, "step_seconds": t_step,
                       "mode_seconds": t_modes, "spectra_per_s": len(members) / (t_step + t_modes),
                       "glups": nodes * steps / t_step / 1e9}
     log("batched: %.1f s, %.2f spectra/s" % (t_step + t_modes, rep["batched"]["spectra_per_s"]))
+    if args.train_only:
+        print(json.dumps(rep), flush=True)
+        return
 
     # 2. plain per-shape sample (the first horns of the same ensemble)
     ns = min(args.plain, len(members))

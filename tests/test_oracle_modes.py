@@ -138,6 +138,13 @@ def test_extractor_recovers_sinusoids():
         nfft = oracle.modes.__globals__["nfft_for"](T)
         assert np.abs(est - fs).max() * nfft < 2e-3
         assert np.all(np.diff(est) > 0)
+    # a slowly decaying baseline (time constant 2T) leaks into the window's
+    # DC main lobe; no peak is reported there
+    T = 30000
+    t = np.arange(T)
+    x = 0.3 * (np.cos(2 * math.pi * 31 / T * t + 1.0) + np.cos(2 * math.pi * 72 / T * t + 1.0)) + 3.0 * np.exp(-t / (2.0 * T))
+    est, _ = oracle.modes(x[:, None], 3)
+    assert np.abs(est[:2] * T - (31, 72)).max() < 0.05 and np.isnan(est[2])
     # fewer peaks than requested are NaN-padded
     est, _ = oracle.modes(np.cos(0.3 * np.arange(1000))[:, None], 3)
     assert abs(est[0] - 0.3 / (2 * math.pi)) < 1e-4 and np.isnan(est[1:]).all()

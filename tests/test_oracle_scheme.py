@@ -349,3 +349,39 @@ def test_gradient_force_coefficient_threshold():
     g_ok, m_ok = growth(1.0)
     assert m_bad > 1.0 and g_bad > 1e3
     assert abs(m_ok) < 1e-14 and g_ok < 2.0
+
+
+def test_ensemble_horn_lattice_unit():
+    """Ensemble horns take h_z as lattice unit on a grid whose radial links
+    are nowhere shorter than h_z, so Mhat^zz = 0, Mhat^rr <= 0 and
+    |Mhat^rz| < 1 (checked with the oracle's tables for a sample of the
+    training ensemble).  The same horn with the mouthpiece's radial link as
+    unit on a fine axial grid (Mhat^zz > 0.6 along the flare) grows; on its
+    ensemble grid it does not.  The runs use one theta node: the metric does
+    not depend on theta, so this lattice is exactly the axisymmetric part of
+    any theta resolution."""
+    for m in W.ensemble(512)[::16]:
+        n0, _, n2 = m["geom"]["n"]
+        assert m["geom"]["h_ref"] == 1.0 / n2 and n0 % 8 == 0 and n0 >= 16
+        o = oracle.Oracle(dict(m["geom"], n=(n0, 1, n2), c=0.1))
+        assert np.abs(o.Mhat[2]).max() < 1e-12
+        assert o.Mhat[0].max() <= 1e-12 and np.abs(o.Mhat[4]).max() < 1.0
+
+    a, b, k = 0.19, 0.03, 2.0
+    hr = 0.95 / 32
+
+    def growth(n, h_ref):
+        g = W.trumpet_horn(c=0.1, a=a, b=b, k=k, n=n)
+        g["h_ref"] = h_ref
+        g["c"] = 0.9 * leapfrog_bound(oracle.Oracle(g))
+        o = oracle.Oracle(g)
+        f = np.random.default_rng(3).normal(size=(o.Q, o.N))
+        n_start = np.sqrt((f * f).sum())
+        o.step(f, 6000)
+        return np.sqrt((f * f).sum()) / n_start, o
+
+    g_bad, o_bad = growth((32, 1, 224), (a + b) * hr / math.sqrt(1.0 + (b * k) ** 2))
+    assert o_bad.Mhat[2].max() > 0.6 and g_bad > 5.0, g_bad
+    n_ok = W.horn_grid((a, b, k), 1, 224)
+    g_ok, _ = growth(n_ok, 1.0 / n_ok[2])
+    assert g_ok < 1.2, g_ok

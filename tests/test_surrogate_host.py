@@ -34,5 +34,10 @@ def test_physical_units_and_ensemble_shapes():
     for m in e:
         g = m["geom"]
         assert g["c"] is None and g["kind"] == "horn" and len(m["probes"]) == W.ENSEMBLE_PROBES
-        assert all(v in W.HORN_GRIDS[k] for v, k in zip(g["n"], ("nr", "nt", "nz")))
+        nr, nt, nz = g["n"]
+        assert nt in W.HORN_GRIDS["nt"] and nz >= min(W.HORN_GRIDS["nz"]) and nz % 16 == 0
+        assert nr >= 16 and nr % 8 == 0 and g["h_ref"] == 1.0 / nz
+        # no radial link shorter than the lattice unit, and the largest such n_r
+        rho = 0.95 * W.shortest_radial_link(m["profile"])
+        assert rho / nr >= g["h_ref"] * (1 - 1e-12) and (nr == 16 or rho / (nr + 8) < g["h_ref"])
         assert np.all(m["probes"] < np.prod(g["n"]))

@@ -170,13 +170,20 @@ def trumpet_horn(scale: int = 1, c: float | None = None, a=0.1, b=0.02, k=3.0, n
     r in [0.05, 1]; closed mouthpiece (z = 0, bounce-back), open bell (z = 1,
     free), bounce-back wall at r = 1 and r = 0.05.
 
-    One lattice unit is the physical length of a radial link at the
-    mouthpiece wall, R(0) h_r / sqrt(1 + R'(0)^2): the radial links are then
-    nowhere shorter than a lattice unit, which keeps the scheme's radial
-    gradient-force coefficient non-positive."""
+    One lattice unit is the shorter of the axial link h_z and the shortest
+    radial link, min over z of R(z) h_r / sqrt(1 + R'(z)^2) at r = 1; that
+    minimum sits at z = 0 or z = 1 because (1 + R'^2) / R^2 has a single
+    interior minimum for this profile.  With this unit the scheme's
+    gradient-force coefficients M^rr and M^zz are non-positive everywhere and
+    |M^rz| < 1, which keeps the z-varying coefficients inside the range where
+    the tau = 1/2 scheme is neutral."""
     n = _scaled(n, scale)
     hr = 0.95 / n[0]
-    h_ref = (a + b) * hr / math.sqrt(1.0 + (b * k) ** 2)
+    hz = 1.0 / n[2]
+    def radial(z):
+        s, ds = a + b * math.exp(k * z), b * k * math.exp(k * z)
+        return s * hr / math.sqrt(1.0 + ds * ds)
+    h_ref = min(radial(0.0), radial(1.0), hz)
     return dict(kind="horn", dim=3, n=n, qmin=(0.05, 0.0, 0.0), qmax=(1.0, TWO_PI, 1.0),
                 bc_lo=("bounceback", "periodic", "bounceback"), bc_hi=("bounceback", "periodic", "free"),
                 h_ref=h_ref, c=_c(2) if c is None else c, damp=1.0, params=(a, b, k))
@@ -235,8 +242,8 @@ def workload(idx: int, scale: int = 1, c: float | None = None) -> dict:
 # horn ensemble (batched LBM + surrogate)
 # ---------------------------------------------------------------------------
 
-HORN_RANGES = {"a": (0.05, 0.2), "b": (0.005, 0.05), "k": (1.0, 5.0)}
-HORN_GRIDS = {"nr": (32, 48, 64, 80, 96), "nt": (32, 40, 48, 56, 64), "nz": tuple(range(64, 257, 16))}
+HORN_RANGES = {"a": (0.05, 0.2), "b": (0.005, 0.03), "k": (1.0, 2.0)}
+HORN_GRIDS = {"nt": (32, 40, 48, 56, 64), "nz": tuple(range(64, 257, 16))}
 ENSEMBLE_STEPS = 30000
 ENSEMBLE_PROBES = 8
 ENSEMBLE_MODES = 10
@@ -249,26 +256,77 @@ def horn_profiles(n: int, rng: np.random.Generator) -> np.ndarray:
 
 
 def horn_grids(n: int, rng: np.random.Generator) -> np.ndarray:
-    """n grids (n_r, n_theta, n_z) drawn from the allowed sizes."""
-    cols = [rng.choice(np.array(HORN_GRIDS[key]), size=n) for key in ("nr", "nt", "nz")]
+    """n drawn (n_theta, n_z) pairs; n_r follows from the profile
+    (horn_grid)."""
+    cols = [rng.choice(np.array(HORN_GRIDS[key]), size=n) for key in ("nt", "nz")]
     return np.stack(cols, axis=1).astype(np.int64)
 
 
-def horn_member(profile, grid, c=None) -> dict:
-    """One ensemble horn: geometry (c to be set by the caller when None),
-    initial Gaussian pulse (A = 1, sigma = 0.05, at (0, 0, 0.1)) and 8 probes
-    on the innermost ring at theta = 0, spread along z."""
+MAX_DLOG_R_PER_CELL = 0.02
+
+
+def axial_cells(profile, nz: int) -> int:
+    """nz raised, in steps of 16, until ln R(z) changes by at most
+    MAX_DLOG_R_PER_CELL per axial cell.  On coarser axial grids strongly
+    flared horns grow slowly, at a rate that falls roughly as h_z^3: the
+    coefficients then vary too fast per cell for the tau = 1/2 scheme to stay
+    neutral."""
     a, b, k = (float(v) for v in profile)
-    geom = trumpet_horn(c=0.0 if c is None else c, a=a, b=b, k=k, n=tuple(int(v) for v in grid))
+    dlog_max = b * k * math.exp(k) / (a + b * math.exp(k))  # R'/R is largest at z = 1
+    need = int(math.ceil(dlog_max / MAX_DLOG_R_PER_CELL / 16.0)) * 16
+    return max(int(nz), need)
+
+
+def shortest_radial_link(profile) -> float:
+    """min over z of R(z) / sqrt(1 + R'(z)^2): the length of a radial link at
+    r = 1 per unit of h_r.  (1 + R'^2) / R^2 has one interior minimum for
+    R = a + b e^{kz}, so the minimum sits at z = 0 or z = 1."""
+    a, b, k = (float(v) for v in profile)
+
+    def at(z):
+        e = math.exp(k * z)
+        return (a + b * e) / math.sqrt(1.0 + (b * k * e) ** 2)
+    return min(at(0.0), at(1.0))
+
+
+def horn_grid(profile, nt: int, nz: int):
+    """The (n_r, n_theta, n_z) grid of an ensemble horn.  The lattice unit is
+    the axial link h_z = 1/n_z and n_r (a multiple of 8, at least 16) is the
+    largest for which no radial link is shorter than h_z; where even 16 radial
+    cells would be too fine, n_z is raised instead.  Then Mhat^zz = 0 and
+    Mhat^rr <= 0 everywhere: the scheme loses neutrality both when Mhat^dd
+    exceeds about 0.6 and when it approaches -1 along an axis on which the
+    coefficients vary (here z, through the flare)."""
+    rho = 0.95 * shortest_radial_link(profile)  # radial extent 0.95 (r in [0.05, 1])
+    nz = axial_cells(profile, nz)
+    nr = 8 * int(math.floor(rho * nz / 8.0))
+    if nr < 16:
+        nr = 16
+        nz = 16 * int(math.ceil(16.0 / rho / 16.0))
+    return nr, int(nt), nz
+
+
+def horn_member(profile, draw, c=None) -> dict:
+    """One ensemble horn: geometry on horn_grid(profile, *draw) with h_ref =
+    h_z (c to be set by the caller when None), the plane pulse of horn_pulse
+    and 8 probes on the innermost ring at theta = 0, spread along z."""
+    a, b, k = (float(v) for v in profile)
+    n = horn_grid(profile, *(int(v) for v in draw))
+    geom = trumpet_horn(c=0.0 if c is None else c, a=a, b=b, k=k, n=n)
+    geom["h_ref"] = 1.0 / n[2]
     if c is None:
         geom["c"] = None
-    n0, n1, n2 = shape_of(geom)
+    n0, n1, n2 = n
     zs = ((np.arange(ENSEMBLE_PROBES) + 0.5) * n2 / ENSEMBLE_PROBES).astype(np.int64)
     return dict(geom=geom, probes=zs * (n0 * n1), profile=(a, b, k))
 
 
 def horn_pulse(geom) -> np.ndarray:
-    return gaussian_pulses(geom, np.array([[0.0, 0.0, 0.1]]), [1.0], 0.05)
+    """Plane pulse at the mouthpiece, P0 = exp(-(z - 0.1)^2 / (2 * 0.05^2)),
+    uniform over the cross-section: it drives the longitudinal family of
+    modes and leaves the radial ones nearly at rest."""
+    z = node_grid(geom)[2]
+    return np.exp(-0.5 * ((z - 0.1) / 0.05) ** 2)
 
 
 def ensemble(n: int = 512, stream: int = 0):
@@ -280,6 +338,7 @@ def ensemble(n: int = 512, stream: int = 0):
 
 
 def candidates(n: int = 100000):
-    """Candidate profiles and the grid each would be simulated on."""
+    """Candidate profiles and the (n_theta, n_z) draw each would be simulated
+    with."""
     rng = np.random.default_rng(SEED_BASE + 4 + 104729)
     return horn_profiles(n, rng), horn_grids(n, rng)
