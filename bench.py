@@ -29,7 +29,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("step.hip", "lbw_internal.h"):
+    for name in ("step_march.hip", "step.hip", "lbw_internal.h"):
         with open(os.path.join(ROOT, "paper_1705_01801_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -67,6 +67,33 @@ def cpu_baseline(w, steps):
                       % (steps, w["name"], dt, os.cpu_count() or 0)}
 
 
+def spectra_leg(n_horns, n_plain=4):
+    """Shape-spectra per second of the batched LBM (n_horns ensemble horns in
+    one launch per step) and of the per-shape LBM (the first n_plain of them,
+    one after another), 30000 steps and 10 modes each."""
+    import numpy as np
+
+    import workloads as W
+    from paper_1705_01801_amd import surrogate as S
+    members = S.with_wave_speeds(W.ensemble(n_horns, stream=2))
+    p0s = [W.horn_pulse(m["geom"]) for m in members]
+    steps, k = W.ENSEMBLE_STEPS, W.ENSEMBLE_MODES
+    log("bench: spectra leg, %d horns batched, %d per shape" % (n_horns, n_plain))
+    f_b, t_step, t_modes = S.run_batch(members, p0s, steps, k)
+    f_p, t_plain = S.run_plain(members[:n_plain], p0s[:n_plain], steps, k)
+    same = np.isfinite(f_p) & np.isfinite(f_b[:n_plain])
+    nodes = int(sum(np.prod(m["geom"]["n"]) for m in members))
+    batched = n_horns / (t_step + t_modes)
+    plain = n_plain / t_plain
+    return {"unit": "spectra/s", "batched": round(batched, 3), "plain": round(plain, 3),
+            "batched_vs_plain": round(batched / plain, 2), "horns": n_horns, "plain_horns": n_plain,
+            "nodes": nodes, "steps": steps, "modes": k,
+            "max_rel_diff_plain_vs_batched": float(np.max(np.abs(f_p[same] / f_b[:n_plain][same] - 1.0)))
+            if same.any() else None,
+            "note": "surrogate + LBM fallback rate comes from the surrogate study (python -m "
+                    "paper_1705_01801_amd.surrogate_study), which trains the surrogate first"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +101,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch", default="auto",
+                    help="'auto' (autotune) or TILE_X,CHUNK_Z,BLOCKS to fix the step kernel's launch shape")
+    ap.add_argument("--spectra-horns", type=int, default=64,
+                    help="horns in the batched-vs-plain spectra leg (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this build", file=sys.stderr)
@@ -90,10 +121,14 @@ def main():
     N = W.num_nodes(geom)
     g = lbw.Geometry(geom)
     sim = lbw.Simulation(g, w["P0"], w["probes"], t_max=args.warmup + args.steps)
-    tuned_us = sim.autotune(reps=20)
+    if args.launch == "auto":
+        tuned_us = sim.autotune(reps=20)
+    else:
+        sim.geometry.set_step_config(*(int(v) for v in args.launch.split(",")))
+        tuned_us = float("nan")
     tile = g.step_config()
-    log("bench: %s, %d nodes, warmup %d, steps %d, tuned shape %s (%.2f us)" % (w["name"], N, args.warmup,
-                                                                             args.steps, tile, tuned_us))
+    log("bench: %s, %d nodes, warmup %d, steps %d, launch shape %s (tuner %.2f us)" % (w["name"], N, args.warmup,
+                                                                                   args.steps, tile, tuned_us))
     sim.step(args.warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -136,6 +171,8 @@ def main():
         "copy_ceiling": {"achieved": round(copy_gbs, 1), "unit": "GB/s",
                          "note": "device copy of the same 56 B/node, torch copy_"},
     }
+    if args.spectra_horns > 0:
+        out["spectra"] = spectra_leg(args.spectra_horns)
     if not args.no_cpu_baseline:
         log("bench: oracle baseline, %d steps" % args.cpu_steps)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
