@@ -280,7 +280,7 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max) {
 int lbw_set_step_config(lbw_geometry_t g, int tile_x, int chunk_z, int blocks) {
     if (!g) return fail(LBW_EINVAL, "geometry is NULL");
     if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
-    if (tile_x != 32 && tile_x != 64) return fail(LBW_EINVAL, "tile_x must be 32 or 64");
+    if (tile_x != 16 && tile_x != 32 && tile_x != 64) return fail(LBW_EINVAL, "tile_x must be 16, 32 or 64");
     if (chunk_z < 1 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 1 and blocks >= 0");
     if (blocks == 0) {
         int dev = 0, cus = 0;
@@ -441,7 +441,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     lbw::MarchPlan best = keep;
     float best_ms = 1e30f;
     float* other = s->f[1 - s->cur];
-    for (int tx : {32, 64}) {
+    for (int tx : {16, 32, 64}) {
         if (err != hipSuccess) break;
         const int bpc = lbw::march_blocks_per_cu(tx);
         for (int lz : {4, 8, 16, 32, 64}) {

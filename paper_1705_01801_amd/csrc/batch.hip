@@ -144,6 +144,27 @@ void drop_graphs(lbw_batch* b) {
     }
 }
 
+// Tile width with the fewest idle lanes over the whole batch: lanes
+// allotted = sum over geometries of ceil(n0 / TX) TX * ceil(n1 / TY) TY * n2;
+// ties go to the wider tile (longer contiguous rows per wave).
+int default_tile_x(const lbw_batch* b) {
+    int best = 64;
+    double best_slots = 0.0;
+    for (int tx : {64, 32, 16}) {
+        const int ty = 256 / tx;
+        double slots = 0.0;
+        for (int h = 0; h < b->n; ++h) {
+            const lbw_geometry_desc& d = b->d[h];
+            slots += (double)((d.n[0] + tx - 1) / tx * tx) * (double)((d.n[1] + ty - 1) / ty * ty) * (double)d.n[2];
+        }
+        if (tx == 64 || slots < best_slots) {
+            best = tx;
+            best_slots = slots;
+        }
+    }
+    return best;
+}
+
 int set_config(lbw_batch* b, int tile_x, int chunk_z, int blocks) {
     int cus = 0;
     int rc = lbw::device_cus(&cus);
@@ -246,7 +267,7 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
         release(b);
         return hip_fail(e, "lbw_batch_make");
     }
-    int rc = set_config(b, 32, 16, 0);
+    int rc = set_config(b, default_tile_x(b), 16, 0);
     if (rc == LBW_OK && b->P > 0 && hipStreamSynchronize(b->stream) != hipSuccess)
         rc = fail(LBW_EDEVICE, "lbw_batch_make: synchronise");
     if (rc) {
@@ -268,7 +289,7 @@ int lbw_batch_layout(lbw_batch_t b, int64_t* node_offsets, int64_t* probe_offset
 
 int lbw_batch_set_step_config(lbw_batch_t b, int tile_x, int chunk_z, int blocks) {
     if (!b) return fail(LBW_EINVAL, "batch is NULL");
-    if (tile_x != 32 && tile_x != 64) return fail(LBW_EINVAL, "tile_x must be 32 or 64");
+    if (tile_x != 16 && tile_x != 32 && tile_x != 64) return fail(LBW_EINVAL, "tile_x must be 16, 32 or 64");
     if (chunk_z < 1 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 1 and blocks >= 0");
     return set_config(b, tile_x, chunk_z, blocks);
 }
@@ -336,7 +357,7 @@ int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us) {
     int best_tx = keep_tx, best_lz = keep_lz, best_blocks = keep_blocks;
     float best_ms = 1e30f;
     float* other = b->f[1 - b->cur];
-    for (int tx : {32, 64}) {
+    for (int tx : {16, 32, 64}) {
         if (err != hipSuccess) break;
         const int bpc = lbw::batch_blocks_per_cu(tx);
         for (int lz : {4, 8, 16, 32, 64}) {

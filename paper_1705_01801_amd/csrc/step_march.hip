@@ -4,7 +4,8 @@
 // corrected equilibrium, Christoffel and metric-gradient forcing, push
 // streaming with wall rules); only the data movement differs:
 //  - a workgroup of 256 threads owns a TX x TY tile of (axis 0, axis 1)
-//    columns and walks a chunk of LZ planes along axis 2;
+//    columns (TX = 16, 32 or 64, TY = 256 / TX) and walks a chunk of LZ
+//    planes along axis 2;
 //  - each thread keeps its own column's populations and S = sum_l f_l of
 //    planes z-1, z, z+1 in registers, so axis-2 neighbours cost no loads;
 //  - S of the tile plus a one-node ring is staged in LDS (two plane slots)
@@ -412,18 +413,21 @@ __global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* _
 
 }  // namespace
 
-int march_tx_for(int n0) { return n0 <= 32 ? 32 : 64; }
+int march_tx_for(int n0) { return n0 <= 16 ? 16 : (n0 <= 32 ? 32 : 64); }
 
 int march_blocks_per_cu(int tx) {
     int nb = 0;
-    hipError_t e = tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<32>, kThreads, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<64>, kThreads, 0);
+    hipError_t e = tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<16>, kThreads, 0)
+                   : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<32>, kThreads, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<64>, kThreads, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
                              float* fout, hipStream_t st) {
-    if (plan.tx == 32)
+    if (plan.tx == 16)
+        hipLaunchKernelGGL(step_march_kernel<16>, dim3(plan.blocks), dim3(kThreads), 0, st, g, pr, plan, fin, fout);
+    else if (plan.tx == 32)
         hipLaunchKernelGGL(step_march_kernel<32>, dim3(plan.blocks), dim3(kThreads), 0, st, g, pr, plan, fin, fout);
     else
         hipLaunchKernelGGL(step_march_kernel<64>, dim3(plan.blocks), dim3(kThreads), 0, st, g, pr, plan, fin, fout);
@@ -432,14 +436,18 @@ hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchP
 
 int batch_blocks_per_cu(int tx) {
     int nb = 0;
-    hipError_t e = tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32>, kThreads, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64>, kThreads, 0);
+    hipError_t e = tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<16>, kThreads, 0)
+                   : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32>, kThreads, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64>, kThreads, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int blocks,
                              const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st) {
-    if (tx == 32)
+    if (tx == 16)
+        hipLaunchKernelGGL(step_batch_kernel<16>, dim3(blocks), dim3(kThreads), 0, st, items, n_items, tiles_total,
+                           bp, fin, fout);
+    else if (tx == 32)
         hipLaunchKernelGGL(step_batch_kernel<32>, dim3(blocks), dim3(kThreads), 0, st, items, n_items, tiles_total,
                            bp, fin, fout);
     else

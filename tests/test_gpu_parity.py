@@ -263,7 +263,8 @@ def test_launch_shapes_bit_identical():
     o = oracle.Oracle(geom)
     f, tr = o.run(o.init(P0), 60, probes)
     ref = None
-    for tx, lz, blocks in [(64, 16, 0), (32, 1, 8), (32, 5, 16), (64, 37, 24), (64, 64, 8), (32, 7, 0)]:
+    for tx, lz, blocks in [(64, 16, 0), (32, 1, 8), (32, 5, 16), (64, 37, 24), (64, 64, 8), (32, 7, 0), (16, 16, 0),
+                           (16, 3, 8)]:
         say("launch shape", tx, lz, blocks)
         g = lbw.Geometry(geom)
         g.set_step_config(tx, lz, blocks)
@@ -276,6 +277,8 @@ def test_launch_shapes_bit_identical():
             assert np.abs(sim.probe() - tr).max() <= 1e-5 * np.abs(tr).max()
         else:
             assert np.array_equal(fg, ref), (tx, lz, blocks)
+    with pytest.raises(lbw.LbwError):
+        lbw.Geometry(geom).set_step_config(48, 16, 0)
 
 
 def test_graph_blocks_and_autotune_preserve_results():
