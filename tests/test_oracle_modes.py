@@ -7,6 +7,12 @@
   radial condition is dP/dr = 0 (zeros built from J'_m, Y'_m); fixed walls
   give P = 0.  m = 0 modes pin the sqrt(g) factor of the Christoffel force,
   m >= 1 and z-dependent modes pin the sign of the gradient force.
+* horn longitudinal modes: for a slowly flaring horn the plane-wave modes
+  are the eigenvalues of Webster's horn equation (1/S) d/dz (S dp/dz) +
+  (2 pi f)^2 p = 0, S ~ R(z)^2, a one-dimensional problem solved here by
+  finite volumes; its own error is of order R'^2.  This pins the horn's
+  metric terms (the Mhat^rz gradient force in particular) that no closed
+  form of the full problem reaches;
 * the frequency extractor recovers known sinusoids;
 * the zeros the paper prints for the pipe's wall condition (golden file).
 """
@@ -15,6 +21,7 @@ import os
 
 import numpy as np
 import pytest
+from scipy.linalg import eigh_tridiagonal
 from scipy.optimize import brentq, minimize_scalar
 from scipy.special import jv, jvp, yv, yvp
 
@@ -157,3 +164,69 @@ def test_paper_robin_zero_table():
     zeros = [brentq(fun, lo, lo + 1.5) for lo in (0.5, 3.5, 6.5)]
     assert abs(zeros[0] - printed[0]) < 5e-4 and abs(zeros[1] - printed[1]) < 5e-4
     assert abs(zeros[2] - 7.1558) < 1e-3 and abs(zeros[2] - printed[2]) > 1e-2
+
+
+def webster_frequencies(a, b, k, open_end, n_modes, cells=20000):
+    """Eigenfrequencies (wave speed 1, length 1) of Webster's equation for
+    S = (a + b e^{kz})^2: p' = 0 at z = 0; p = 0 (open_end) or p' = 0 at z = 1.
+    Cell-centred finite volumes, symmetrised generalised eigenproblem."""
+    h = 1.0 / cells
+    zc = (np.arange(cells) + 0.5) * h
+    zf = np.arange(cells + 1) * h
+    Sc = (a + b * np.exp(k * zc)) ** 2
+    Sf = (a + b * np.exp(k * zf)) ** 2
+    diag = np.zeros(cells)
+    diag[:-1] += Sf[1:-1]
+    diag[1:] += Sf[1:-1]
+    if open_end:
+        diag[-1] += 2.0 * Sf[-1]  # p = 0 on the end face (odd ghost)
+    off = -Sf[1:-1]
+    d = 1.0 / np.sqrt(Sc)
+    lam = eigh_tridiagonal(diag * d * d / h ** 2, off * d[:-1] * d[1:] / h ** 2, select="i",
+                           select_range=(0, n_modes), eigvals_only=True)
+    f = np.sqrt(np.maximum(lam, 0.0)) / (2.0 * math.pi)
+    return f[f > 1e-6][:n_modes]
+
+
+def horn_spectrum(a, b, k, n, bell, steps, n_modes):
+    """Axisymmetric horn (one theta node: the metric does not depend on
+    theta, so this lattice is exactly the theta-independent part of any
+    theta resolution), h_ref = h_z, plane pulse, probes along z."""
+    nr, nz = n
+    geom = W.trumpet_horn(c=0.1, a=a, b=b, k=k, n=(nr, 1, nz))
+    geom["h_ref"] = 1.0 / nz
+    geom["bc_hi"] = ("bounceback", "periodic", bell)
+    o = oracle.Oracle(geom)
+    tot = np.zeros(o.N)
+    for ax in range(3):  # frozen-coefficient bound, as in the scheme pins
+        m = o.Mhat[ax] + (np.abs(o.Mhat[4]) if ax in (0, 2) else 0.0)
+        tot += np.where(m <= 1.0, 4.0, (1.0 + m) ** 2 / np.maximum(m, 1e-300))
+    geom["c"] = 0.9 * 2.0 / math.sqrt(tot.max())
+    o = oracle.Oracle(geom)
+    # well inside the neutral range of the scheme (Mhat^dd below about 0.6)
+    assert o.Mhat[0].max() < 0.15 and np.abs(o.Mhat[2]).max() < 1e-12
+    z = W.node_grid(geom)[2]
+    P0 = np.exp(-0.5 * ((z - 0.1) / 0.05) ** 2)
+    i0 = int(round((0.63 - 0.05) / (0.95 / nr) - 0.5))
+    probes = ((np.arange(8) + 0.5) * nz / 8).astype(np.int64) * nr + i0
+    _, trace = o.run(o.init(P0), steps, probes)
+    freq, _ = oracle.modes(trace, n_modes)
+    return freq / (geom["c"] * geom["h_ref"])
+
+
+def test_horn_modes_follow_webster():
+    a, b, k = 0.06, 0.012, 2.0  # bell/mouth radius 2.07, bell slope 0.18
+    closed = webster_frequencies(a, b, k, open_end=False, n_modes=4)
+    # the flare matters at the level checked: a straight pipe has n/2
+    assert abs(closed[0] / 0.5 - 1.0) > 0.015
+    f = horn_spectrum(a, b, k, (16, 224), "bounceback", 16000, 4)
+    err = np.abs(f / closed - 1.0)
+    assert err.max() < 2.5e-3, err
+    # pressure-release bell: the fundamental converges at first order (the
+    # end condition on a flared bell), the other modes to the Webster level
+    opened = webster_frequencies(a, b, k, open_end=True, n_modes=5)
+    assert opened[0] / 0.25 - 1.0 > 0.2
+    e1 = np.abs(horn_spectrum(a, b, k, (8, 112), "fixed", 8000, 5) / opened - 1.0)
+    e2 = np.abs(horn_spectrum(a, b, k, (16, 224), "fixed", 16000, 5) / opened - 1.0)
+    assert e2[0] < 0.025 and e1[0] / e2[0] > 1.6, (e1, e2)
+    assert e2[1:].max() < 7e-3, e2
