@@ -92,7 +92,9 @@ typedef struct lbw_state* lbw_state_t;
  * Errors: LBW_EINVAL for an invalid descriptor (bad kind/dim pairing, n < 1,
  * qmax <= qmin, h_ref <= 0, c <= 0 or not finite, damping outside [0, 1],
  * unpaired periodic faces, radius <= 0, torus rho >= R, horn s(z) <= 0,
- * more than 2^31 - 1 nodes); LBW_ENOMEM; LBW_EDEVICE. */
+ * a population buffer of 2^31 bytes or more, i.e. 4 Q N >= 2^31: the step
+ * kernels address it with 32-bit byte offsets; at most 76,695,844 nodes for
+ * D3Q7); LBW_ENOMEM; LBW_EDEVICE. */
 int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_t* out);
 
 /* Releases a geometry (waits for its stream first).  NULL is accepted. */

@@ -138,8 +138,9 @@ int validate_desc(const lbw_geometry_desc* d) {
             return fail(LBW_EINVAL, "axis %d: periodic faces must be paired", a);
         N *= d->n[a];
     }
-    if ((2 * d->dim + 1) * N > 2147483647LL)
-        return fail(LBW_EINVAL, "too many nodes (%lld): Q * N must stay below 2^31", (long long)N);
+    // each population buffer (Q * N floats) is addressed with 32-bit byte offsets
+    if (4LL * (2 * d->dim + 1) * N > 2147483647LL)
+        return fail(LBW_EINVAL, "too many nodes (%lld): 4 Q N bytes must stay below 2^31", (long long)N);
     if (!is_finite(d->h_ref) || !(d->h_ref > 0.0)) return fail(LBW_EINVAL, "h_ref must be > 0");
     if (!is_finite(d->c) || !(d->c > 0.0)) return fail(LBW_EINVAL, "c must be > 0");
     if (!is_finite(d->damping) || d->damping < 0.0 || d->damping > 1.0) return fail(LBW_EINVAL, "damping outside [0,1]");

@@ -14,13 +14,24 @@
 //  - the coefficient row of a plane (entries x0-1 .. x0+TX, 32 bytes each)
 //    is staged in LDS (three plane slots: z, z+1 and the one being filled),
 //    so a node reads its own and its axis-0 neighbours' coefficients there;
-//  - populations, ring and coefficient row of plane z+2 (z+1 for the ring)
-//    are loaded before plane z is computed and stored after it, so their
-//    latency hides behind the computation;
+//  - loads run one plane step ahead of their use: while plane z is
+//    computed, the own column of plane z+2, the ring of plane z+2 and the
+//    coefficient row of plane z+3 are in flight, and what plane z+1 needs
+//    (loaded during plane z-1) is consumed; the loop is unrolled by three so
+//    the register sets rotate by name, not by copies;
+//  - every load and store of the plane loop is a buffer instruction issued by
+//    every lane with a 32-bit byte offset from the geometry's own base;
+//    disabled ones carry an offset outside the buffer, which the hardware
+//    range check turns into a zero load or a dropped store.  With no branch
+//    around a memory operation the compiler's wait counts stay exact (a
+//    branch makes it drain every outstanding access at the join), and no
+//    access can leave the geometry's buffers;
 //  - a persistent grid walks the tiles; each XCD (blocks b with the same
 //    b mod 8) gets one contiguous range of tiles, so ring and chunk-boundary
 //    planes shared by neighbouring tiles are re-read from the same L2.
-// Node offsets are 32-bit (the library keeps Q * N below 2^31).
+// Byte offsets are 32-bit: the library keeps 4 Q N below 2^31.
+#include <type_traits>
+
 #include "lbw_internal.h"
 
 namespace lbw {
@@ -64,6 +75,33 @@ __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* 
     if (threadIdx.x == 0) *(volatile int64_t*)pr.tcount = t + 1;
 }
 
+// Buffer addressing: 32-bit byte offsets from a per-geometry base; an offset
+// of kOff is outside every range, so such a load returns 0 and such a store
+// is dropped by the hardware range check.  Every load and store of the plane
+// loop is issued by every lane, disabled ones with kOff, so the loop has no
+// branch around a memory operation and the wait counts stay exact.
+constexpr uint32_t kOff = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family format word
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ inline float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ inline float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
+}
+__device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)off, 0, 0);
+}
+// the 7 populations of the node at byte offset nb, or nothing (all zeros)
+__device__ inline void bload7(__amdgpu_buffer_rsrc_t r, uint32_t N4, bool on, uint32_t nb, float v[7]) {
+#pragma unroll
+    for (int l = 0; l < 7; ++l) v[l] = bld(r, on ? nb + (uint32_t)l * N4 : kOff);
+}
+
 // value beyond a wall: mirrored, odd for fixed walls
 __device__ inline float ghost(int wall, float v) { return wall == LBW_BC_FIXED ? -v : v; }
 
@@ -76,7 +114,7 @@ __device__ inline float bounce(int wall, float damp, float out_l, float own_lb) 
 template <int TX>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
                                            float* __restrict__ fout, float (&sS)[2][(kThreads / TX + 2) * (TX + 2)],
-                                           float4 (&sE)[3][TX + 2][2]) {
+                                           float4 (&sElo)[3][TX + 2], float4 (&sEhi)[3][TX + 2]) {
     constexpr int TY = kThreads / TX;
     constexpr int W = TX + 2;
     const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
@@ -152,162 +190,193 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
         const int zm0 = link_coord(z0, -1, n2, g.bc_lo[2], g.bc_hi[2], &wz);
         const int zp0 = link_coord(z0, +1, n2, g.bc_lo[2], g.bc_hi[2], &wz);
 
-        // ---- prologue: planes z0-1 (S only), z0, z0+1 ----
+        const uint32_t N4 = N * 4u, plane4 = plane * 4u, col4 = col * 4u, ring4 = ring_col * 4u;
+        const __amdgpu_buffer_rsrc_t rin = make_rsrc(fin, 7u * N4);
+        const __amdgpu_buffer_rsrc_t rout = make_rsrc(fout, 7u * N4);
+        const __amdgpu_buffer_rsrc_t rtab = make_rsrc(tab4, (uint32_t)n0 * (uint32_t)n2 * 32u);
+        const bool ring_on = ring_lds >= 0, erow_on = erow_x >= 0;
+
+        // ---- prologue: planes z0-1 (S only), z0 (populations, S, ring S,
+        // coefficient rows z0 and z0+1); pending into the loop: own column
+        // and ring of plane z0+1 ----
         float fc[7], fnx[7], tmp[7];
         float Sm = 0.f, Sc = 0.f, Sp = 0.f;
         float2 em = make_float2(0.f, 0.f);  // (c^2 Mhat02, c^2 Mhat22) at z-1
-        if (active) {
-            if (zm0 >= 0) {
-                load7(fin, N, col + (uint32_t)zm0 * plane, tmp);
-                Sm = sum7(tmp);
-                const float4 e = tab4[2 * (x + n0 * zm0)];
-                em = make_float2(e.y, e.z);
-            }
-            load7(fin, N, col + (uint32_t)z0 * plane, fc);
+        {
+            const bool m_on = active && zm0 >= 0;
+            bload7(rin, N4, m_on, col4 + (uint32_t)zm0 * plane4, tmp);
+            const float4 e = bld4(rtab, m_on ? (uint32_t)(x + n0 * zm0) * 32u : kOff);
+            bload7(rin, N4, active, col4 + (uint32_t)z0 * plane4, fc);
+            const bool e0_on = erow_on, e1_on = erow_on && zp0 >= 0;
+            const float4 a0 = bld4(rtab, e0_on ? (uint32_t)(erow_x + n0 * z0) * 32u : kOff);
+            const float4 b0 = bld4(rtab, e0_on ? (uint32_t)(erow_x + n0 * z0) * 32u + 16u : kOff);
+            const float4 a1 = bld4(rtab, e1_on ? (uint32_t)(erow_x + n0 * zp0) * 32u : kOff);
+            const float4 b1 = bld4(rtab, e1_on ? (uint32_t)(erow_x + n0 * zp0) * 32u + 16u : kOff);
+            float rz[7];
+            bload7(rin, N4, ring_on, ring4 + (uint32_t)z0 * plane4, rz);
+            Sm = sum7(tmp);
+            em = make_float2(e.y, e.z);
             Sc = sum7(fc);
-            if (zp0 >= 0) {
-                load7(fin, N, col + (uint32_t)zp0 * plane, fnx);
-                Sp = sum7(fnx);
+            if (e0_on) {
+                sElo[0][threadIdx.x] = a0;
+                sEhi[0][threadIdx.x] = b0;
             }
-        }
-        if (erow_x >= 0) {
-            const int e0 = 2 * (erow_x + n0 * z0);
-            sE[0][threadIdx.x][0] = tab4[e0];
-            sE[0][threadIdx.x][1] = tab4[e0 + 1];
-            if (zp0 >= 0) {
-                const int e1 = 2 * (erow_x + n0 * zp0);
-                sE[1][threadIdx.x][0] = tab4[e1];
-                sE[1][threadIdx.x][1] = tab4[e1 + 1];
+            if (e1_on) {
+                sElo[1][threadIdx.x] = a1;
+                sEhi[1][threadIdx.x] = b1;
             }
+            if (ring_on) sS[0][ring_lds] = sum7(rz);
+            if (active) sS[0][my_lds] = Sc;
         }
-        if (ring_lds >= 0) {
-            load7(fin, N, ring_col + (uint32_t)z0 * plane, tmp);
-            sS[0][ring_lds] = sum7(tmp);
+        float rA[7], rB[7], rC[7];  // ring populations: plane z+1 (loaded one step ago), plane z+2 (loading)
+        float4 eA[2], eB[2], eC[2];  // coefficient rows: plane z+2 (loaded one step ago), plane z+3 (loading)
+        bload7(rin, N4, active && zp0 >= 0, col4 + (uint32_t)zp0 * plane4, fnx);
+        bload7(rin, N4, ring_on && z0 + 1 < z1, ring4 + (uint32_t)zp0 * plane4, rA);
+        {
+            int w = 0;
+            const int zq0 = z0 + 1 < z1 && zp0 >= 0 ? link_coord(zp0, +1, n2, g.bc_lo[2], g.bc_hi[2], &w) : -1;
+            const bool on = erow_on && zq0 >= 0;
+            const uint32_t off = (uint32_t)(erow_x + n0 * zq0) * 32u;
+            eA[0] = bld4(rtab, on ? off : kOff);
+            eA[1] = bld4(rtab, on ? off + 16u : kOff);
         }
-        if (active) sS[0][my_lds] = Sc;
 
-        int es = 0;  // coefficient-row slot of plane z (z+1 in es+1 mod 3)
-        for (int z = z0; z < z1; ++z) {
+        // One plane.  fc: populations of plane z, fnx: of plane z+1 (loaded
+        // one step ago), fnn: receives plane z+2; r1: ring of plane z+1
+        // (loaded one step ago), r2: receives the ring of plane z+2.  The
+        // caller rotates the arrays by argument order (no register copies);
+        // the coefficient-row slot of plane z is es (z+1 in es+1, z+2 in
+        // es+2, mod 3).
+        auto plane_step = [&](auto es_c, float (&fc)[7], float (&fnx)[7], float (&fnn)[7], float (&r1)[7],
+                              float (&r2)[7], float4 (&e1)[2], float4 (&e2)[2], int z) {
+            constexpr int es = decltype(es_c)::value;
+            constexpr int es1 = (es + 1) % 3;
+            constexpr int es2 = (es + 2) % 3;
             const int sb = (z - z0) & 1;
-            const int es1 = es == 2 ? 0 : es + 1;
-            const int es2 = es1 == 2 ? 0 : es1 + 1;
             int wz_p = 0, wz_m = 0;
             const int jz_p = link_coord(z, +1, n2, g.bc_lo[2], g.bc_hi[2], &wz_p);
             const int jz_m = link_coord(z, -1, n2, g.bc_lo[2], g.bc_hi[2], &wz_m);
             const bool more = z + 1 < z1;
+            const bool more2 = z + 2 < z1;
             int wq = 0;
-            const int zq = more ? link_coord(jz_p, +1, n2, g.bc_lo[2], g.bc_hi[2], &wq) : -1;
+            const int zq = more ? link_coord(jz_p, +1, n2, g.bc_lo[2], g.bc_hi[2], &wq) : -1;  // plane z+2
 
-            // prefetch plane zq (own column, coefficient row) and plane z+1 (ring)
-            float fnn[7], hr[7];
-            float4 ea = make_float4(0.f, 0.f, 0.f, 0.f), eb = ea;
-            if (active && zq >= 0) load7(fin, N, col + (uint32_t)zq * plane, fnn);
-            if (erow_x >= 0 && zq >= 0) {
-                const int e2 = 2 * (erow_x + n0 * zq);
-                ea = tab4[e2];
-                eb = tab4[e2 + 1];
-            }
-            const bool ring_next = ring_lds >= 0 && more;
-            if (ring_next) load7(fin, N, ring_col + (uint32_t)jz_p * plane, hr);
+            // loads consumed one step later: coefficient row of plane z+3,
+            // own column and ring of plane z+2
+            const bool e_on = erow_on && zq >= 0;  // row of plane z+2 (in e1) is staged
+            const int z3 = more2 && zq >= 0 ? link_coord(zq, +1, n2, g.bc_lo[2], g.bc_hi[2], &wq) : -1;
+            const bool e3_on = erow_on && z3 >= 0;
+            const uint32_t eoff = (uint32_t)(erow_x + n0 * z3) * 32u;
+            e2[0] = bld4(rtab, e3_on ? eoff : kOff);
+            e2[1] = bld4(rtab, e3_on ? eoff + 16u : kOff);
+            bload7(rin, N4, active && zq >= 0, col4 + (uint32_t)zq * plane4, fnn);
+            bload7(rin, N4, ring_on && more2, ring4 + (uint32_t)zq * plane4, r2);
+            Sp = sum7(fnx);  // S of plane z+1 (zeros when there is none: then unused)
             __syncthreads();
 
-            if (active) {
-                const float* L = sS[sb];
-                const float S = Sc;
-                const float4 e_lo = sE[es][lx + 1][0];  // 00, 02, 22, 11
-                const float4 e_hi = sE[es][lx + 1][1];  // g0/2, g2/2, 0, 0
-                const float cM00 = e_lo.x, cM02 = e_lo.y, cM22 = e_lo.z, cM11 = e_lo.w;
-                const float hG0 = e_hi.x, hG2 = e_hi.y;
-                float A00p, A00m, A20p, A20m, A22p, A22m, A02p, A02m;
-                if (jx_p >= 0) {
-                    const float4 en = sE[es][lx + 2][0];
-                    const float Sn = L[my_lds + 1];
-                    A00p = en.x * Sn;
-                    A20p = en.y * Sn;
-                } else {
-                    const float sg = ghost(wx_p, S);
-                    A00p = cM00 * sg;
-                    A20p = cM02 * sg;
-                }
-                if (jx_m >= 0) {
-                    const float4 en = sE[es][lx][0];
-                    const float Sn = L[my_lds - 1];
-                    A00m = en.x * Sn;
-                    A20m = en.y * Sn;
-                } else {
-                    const float sg = ghost(wx_m, S);
-                    A00m = cM00 * sg;
-                    A20m = cM02 * sg;
-                }
-                const float A11p = cM11 * (jy_p >= 0 ? L[my_lds + W] : ghost(wy_p, S));
-                const float A11m = cM11 * (jy_m >= 0 ? L[my_lds - W] : ghost(wy_m, S));
-                if (jz_p >= 0) {
-                    const float4 en = sE[es1][lx + 1][0];
-                    A02p = en.y * Sp;
-                    A22p = en.z * Sp;
-                } else {
-                    const float sg = ghost(wz_p, S);
-                    A22p = cM22 * sg;
-                    A02p = cM02 * sg;
-                }
-                if (jz_m >= 0) {
-                    A02m = em.x * Sm;
-                    A22m = em.y * Sm;
-                } else {
-                    const float sg = ghost(wz_m, S);
-                    A22m = cM22 * sg;
-                    A02m = cM02 * sg;
-                }
-                const float K0 = (fc[1] - fc[2]) - hG0 * S - 0.25f * (A00p - A00m) - 0.25f * (A02p - A02m);
-                const float K1 = (fc[3] - fc[4]) - 0.25f * (A11p - A11m);
-                const float K2 = (fc[5] - fc[6]) - hG2 * S - 0.25f * ((A22p - A22m) + (A20p - A20m));
-                const float cs = c2 * S;
-                float fs[7];
-                fs[0] = two_w0 * S - fc[0];
-                fs[1] = cs + K0 - fc[1];
-                fs[2] = cs - K0 - fc[2];
-                fs[3] = cs + K1 - fc[3];
-                fs[4] = cs - K1 - fc[4];
-                fs[5] = cs + K2 - fc[5];
-                fs[6] = cs - K2 - fc[6];
-
-                const uint32_t n = col + (uint32_t)z * plane;
-                fout[n] = fs[0];
-                if (jx_p >= 0) fout[1 * N + n + (uint32_t)(jx_p - x)] = fs[1];
-                else fout[2 * N + n] = bounce(wx_p, damp, fs[1], fs[2]);
-                if (jx_m >= 0) fout[2 * N + n + (uint32_t)(jx_m - x)] = fs[2];
-                else fout[1 * N + n] = bounce(wx_m, damp, fs[2], fs[1]);
-                if (jy_p >= 0) fout[3 * N + n + (uint32_t)((jy_p - y) * n0)] = fs[3];
-                else fout[4 * N + n] = bounce(wy_p, damp, fs[3], fs[4]);
-                if (jy_m >= 0) fout[4 * N + n + (uint32_t)((jy_m - y) * n0)] = fs[4];
-                else fout[3 * N + n] = bounce(wy_m, damp, fs[4], fs[3]);
-                if (jz_p >= 0) fout[5 * N + col + (uint32_t)jz_p * plane] = fs[5];
-                else fout[6 * N + n] = bounce(wz_p, damp, fs[5], fs[6]);
-                if (jz_m >= 0) fout[6 * N + col + (uint32_t)jz_m * plane] = fs[6];
-                else fout[5 * N + n] = bounce(wz_m, damp, fs[6], fs[5]);
-                em = make_float2(cM02, cM22);
+            const float* L = sS[sb];
+            const float S = Sc;
+            const float4 e_lo = sElo[es][lx + 1];  // 00, 02, 22, 11
+            const float4 e_hi = sEhi[es][lx + 1];  // g0/2, g2/2, 0, 0
+            const float cM00 = e_lo.x, cM02 = e_lo.y, cM22 = e_lo.z, cM11 = e_lo.w;
+            const float hG0 = e_hi.x, hG2 = e_hi.y;
+            float A00p, A00m, A20p, A20m, A22p, A22m, A02p, A02m;
+            if (jx_p >= 0) {
+                const float4 en = sElo[es][lx + 2];
+                const float Sn = L[my_lds + 1];
+                A00p = en.x * Sn;
+                A20p = en.y * Sn;
+            } else {
+                const float sg = ghost(wx_p, S);
+                A00p = cM00 * sg;
+                A20p = cM02 * sg;
             }
+            if (jx_m >= 0) {
+                const float4 en = sElo[es][lx];
+                const float Sn = L[my_lds - 1];
+                A00m = en.x * Sn;
+                A20m = en.y * Sn;
+            } else {
+                const float sg = ghost(wx_m, S);
+                A00m = cM00 * sg;
+                A20m = cM02 * sg;
+            }
+            const float A11p = cM11 * (jy_p >= 0 ? L[my_lds + W] : ghost(wy_p, S));
+            const float A11m = cM11 * (jy_m >= 0 ? L[my_lds - W] : ghost(wy_m, S));
+            if (jz_p >= 0) {
+                const float4 en = sElo[es1][lx + 1];
+                A02p = en.y * Sp;
+                A22p = en.z * Sp;
+            } else {
+                const float sg = ghost(wz_p, S);
+                A22p = cM22 * sg;
+                A02p = cM02 * sg;
+            }
+            if (jz_m >= 0) {
+                A02m = em.x * Sm;
+                A22m = em.y * Sm;
+            } else {
+                const float sg = ghost(wz_m, S);
+                A22m = cM22 * sg;
+                A02m = cM02 * sg;
+            }
+            const float K0 = (fc[1] - fc[2]) - hG0 * S - 0.25f * (A00p - A00m) - 0.25f * (A02p - A02m);
+            const float K1 = (fc[3] - fc[4]) - 0.25f * (A11p - A11m);
+            const float K2 = (fc[5] - fc[6]) - hG2 * S - 0.25f * ((A22p - A22m) + (A20p - A20m));
+            const float cs = c2 * S;
+            float fs[7];
+            fs[0] = two_w0 * S - fc[0];
+            fs[1] = cs + K0 - fc[1];
+            fs[2] = cs - K0 - fc[2];
+            fs[3] = cs + K1 - fc[3];
+            fs[4] = cs - K1 - fc[4];
+            fs[5] = cs + K2 - fc[5];
+            fs[6] = cs - K2 - fc[6];
+
+            // push with the wall rules: destination offset and value by select
+            const uint32_t nb = col4 + (uint32_t)z * plane4;
+            const uint32_t o0 = nb;
+            const uint32_t o1 = jx_p >= 0 ? 1u * N4 + nb + (uint32_t)(jx_p - x) * 4u : 2u * N4 + nb;
+            const uint32_t o2 = jx_m >= 0 ? 2u * N4 + nb + (uint32_t)(jx_m - x) * 4u : 1u * N4 + nb;
+            const uint32_t o3 = jy_p >= 0 ? 3u * N4 + nb + (uint32_t)((jy_p - y) * n0) * 4u : 4u * N4 + nb;
+            const uint32_t o4 = jy_m >= 0 ? 4u * N4 + nb + (uint32_t)((jy_m - y) * n0) * 4u : 3u * N4 + nb;
+            const uint32_t o5 = jz_p >= 0 ? 5u * N4 + col4 + (uint32_t)jz_p * plane4 : 6u * N4 + nb;
+            const uint32_t o6 = jz_m >= 0 ? 6u * N4 + col4 + (uint32_t)jz_m * plane4 : 5u * N4 + nb;
+            const float v1 = jx_p >= 0 ? fs[1] : bounce(wx_p, damp, fs[1], fs[2]);
+            const float v2 = jx_m >= 0 ? fs[2] : bounce(wx_m, damp, fs[2], fs[1]);
+            const float v3 = jy_p >= 0 ? fs[3] : bounce(wy_p, damp, fs[3], fs[4]);
+            const float v4 = jy_m >= 0 ? fs[4] : bounce(wy_m, damp, fs[4], fs[3]);
+            const float v5 = jz_p >= 0 ? fs[5] : bounce(wz_p, damp, fs[5], fs[6]);
+            const float v6 = jz_m >= 0 ? fs[6] : bounce(wz_m, damp, fs[6], fs[5]);
+            bst(rout, active ? o0 : kOff, fs[0]);
+            bst(rout, active ? o1 : kOff, v1);
+            bst(rout, active ? o2 : kOff, v2);
+            bst(rout, active ? o3 : kOff, v3);
+            bst(rout, active ? o4 : kOff, v4);
+            bst(rout, active ? o5 : kOff, v5);
+            bst(rout, active ? o6 : kOff, v6);
+            em = make_float2(cM02, cM22);
 
             if (more) {
-                if (ring_next) sS[sb ^ 1][ring_lds] = sum7(hr);
-                if (erow_x >= 0 && zq >= 0) {
-                    sE[es2][threadIdx.x][0] = ea;
-                    sE[es2][threadIdx.x][1] = eb;
+                if (ring_on) sS[sb ^ 1][ring_lds] = sum7(r1);
+                if (e_on) {
+                    sElo[es2][threadIdx.x] = e1[0];
+                    sEhi[es2][threadIdx.x] = e1[1];
                 }
-                if (active) {
-                    sS[sb ^ 1][my_lds] = Sp;
-                    Sm = Sc;
-                    Sc = Sp;
-#pragma unroll
-                    for (int l = 0; l < 7; ++l) fc[l] = fnx[l];
-                    if (zq >= 0) {
-#pragma unroll
-                        for (int l = 0; l < 7; ++l) fnx[l] = fnn[l];
-                        Sp = sum7(fnn);
-                    }
-                }
+                if (active) sS[sb ^ 1][my_lds] = Sp;
+                Sm = Sc;
+                Sc = Sp;
             }
-            es = es1;
+        };
+        float fz[7];
+        for (int z = z0;;) {
+            if (z >= z1) break;
+            plane_step(std::integral_constant<int, 0>{}, fc, fnx, fz, rA, rB, eA, eB, z);
+            if (++z >= z1) break;
+            plane_step(std::integral_constant<int, 1>{}, fnx, fz, fc, rB, rC, eB, eC, z);
+            if (++z >= z1) break;
+            plane_step(std::integral_constant<int, 2>{}, fz, fc, fnx, rC, rA, eC, eA, z);
+            ++z;
         }
         __syncthreads();  // LDS reuse by the next tile
     }
@@ -318,7 +387,8 @@ __global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeAr
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
     __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2)];
-    __shared__ float4 sE[3][TX + 2][2];
+    __shared__ float4 sElo[3][TX + 2];
+    __shared__ float4 sEhi[3][TX + 2];
     if (blockIdx.x == 0) probe_block(g, pr, fin);
     TileGeom tg;
     tg.n0 = g.n0;
@@ -341,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeAr
     const int t_begin = (int)(plan.tiles * xcd / kXcds);
     const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
     for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
-        march_tile<TX>(tg, tile, fin, fout, sS, sE);
+        march_tile<TX>(tg, tile, fin, fout, sS, sElo, sEhi);
 }
 
 // Batch of geometries advanced by one launch: tiles of all geometries form
@@ -354,7 +424,8 @@ __global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* _
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
     __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2)];
-    __shared__ float4 sE[3][TX + 2][2];
+    __shared__ float4 sElo[3][TX + 2];
+    __shared__ float4 sEhi[3][TX + 2];
     for (int h = blockIdx.x; h < n_items; h += gridDim.x) {
         const BatchItem& it = items[h];
         const int64_t t = *(volatile const int64_t*)(bp.tcount + h);
@@ -407,7 +478,7 @@ __global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* _
         tg.ntx = it.ntx;
         tg.nty = it.nty;
         tg.lz = it.lz;
-        march_tile<TX>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sE);
+        march_tile<TX>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sElo, sEhi);
     }
 }
 
