@@ -228,7 +228,7 @@ int lbw_batch_layout(lbw_batch_t b, int64_t* node_offsets, int64_t* probe_offset
 
 /* Launch shape shared by all geometries of the batch (as
  * lbw_set_step_config).  The default made by lbw_batch_make is chunk_z 16,
- * one wave of resident workgroups, and the tile_x with the fewest idle lanes
+ * two waves of resident workgroups, and the tile_x with the fewest idle lanes
  * over all geometries (sum of ceil(n0/tile_x) tile_x * ceil(n1/tile_y)
  * tile_y * n2; ties to the wider tile).  lbw_batch_autotune is switched
  * off in this version and returns LBW_ESTATE without launching anything;

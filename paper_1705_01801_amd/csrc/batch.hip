@@ -267,7 +267,15 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
         release(b);
         return hip_fail(e, "lbw_batch_make");
     }
-    int rc = set_config(b, default_tile_x(b), 16, 0);
+    int rc = LBW_OK;
+    {
+        // default: chunk 16, two waves of resident workgroups (measured best
+        // on the 512-horn ensemble among chunks 8..128 and one or two waves)
+        int cus = 0;
+        rc = lbw::device_cus(&cus);
+        const int tx = default_tile_x(b);
+        if (rc == LBW_OK) rc = set_config(b, tx, 16, 2 * cus * lbw::batch_blocks_per_cu(tx));
+    }
     if (rc == LBW_OK && b->P > 0 && hipStreamSynchronize(b->stream) != hipSuccess)
         rc = fail(LBW_EDEVICE, "lbw_batch_make: synchronise");
     if (rc) {
