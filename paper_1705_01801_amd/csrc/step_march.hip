@@ -97,9 +97,12 @@ __device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)off, 0, 0);
 }
 // the 7 populations of the node at byte offset nb, or nothing (all zeros)
+// (kOff + 6 N4 stays below 2^32 because 7 N4 < 2^31, so a disabled base
+// keeps every population's offset out of range)
 __device__ inline void bload7(__amdgpu_buffer_rsrc_t r, uint32_t N4, bool on, uint32_t nb, float v[7]) {
+    const uint32_t base = on ? nb : kOff;
 #pragma unroll
-    for (int l = 0; l < 7; ++l) v[l] = bld(r, on ? nb + (uint32_t)l * N4 : kOff);
+    for (int l = 0; l < 7; ++l) v[l] = bld(r, base + (uint32_t)l * N4);
 }
 
 // value beyond a wall: mirrored, odd for fixed walls
@@ -113,10 +116,11 @@ __device__ inline float bounce(int wall, float damp, float out_l, float own_lb) 
 // [z0, z0 + lz).  fin/fout point at the geometry's own population block.
 template <int TX>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
-                                           float* __restrict__ fout, float (&sS)[2][(kThreads / TX + 2) * (TX + 2)],
-                                           float4 (&sElo)[3][TX + 2], float4 (&sEhi)[3][TX + 2]) {
+                                           float* __restrict__ fout, float (&sS)[2][(kThreads / TX + 2) * (TX + 2) + 1],
+                                           float4 (&sElo)[3][TX + 3], float4 (&sEhi)[3][TX + 3]) {
     constexpr int TY = kThreads / TX;
     constexpr int W = TX + 2;
+    constexpr int kSinkS = (TY + 2) * W;  // LDS slot written by disabled lanes
     const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
     const uint32_t N = g.N;
     const uint32_t plane = (uint32_t)n0 * (uint32_t)n1;
@@ -280,29 +284,20 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             const float4 e_hi = sEhi[es][lx + 1];  // g0/2, g2/2, 0, 0
             const float cM00 = e_lo.x, cM02 = e_lo.y, cM22 = e_lo.z, cM11 = e_lo.w;
             const float hG0 = e_hi.x, hG2 = e_hi.y;
-            float A00p, A00m, A20p, A20m, A22p, A22m, A02p, A02m;
-            if (jx_p >= 0) {
-                const float4 en = sElo[es][lx + 2];
-                const float Sn = L[my_lds + 1];
-                A00p = en.x * Sn;
-                A20p = en.y * Sn;
-            } else {
-                const float sg = ghost(wx_p, S);
-                A00p = cM00 * sg;
-                A20p = cM02 * sg;
-            }
-            if (jx_m >= 0) {
-                const float4 en = sElo[es][lx];
-                const float Sn = L[my_lds - 1];
-                A00m = en.x * Sn;
-                A20m = en.y * Sn;
-            } else {
-                const float sg = ghost(wx_m, S);
-                A00m = cM00 * sg;
-                A20m = cM02 * sg;
-            }
-            const float A11p = cM11 * (jy_p >= 0 ? L[my_lds + W] : ghost(wy_p, S));
-            const float A11m = cM11 * (jy_m >= 0 ? L[my_lds - W] : ghost(wy_m, S));
+            float A22p, A22m, A02p, A02m;
+            // axis-0/1 neighbours: read unconditionally (every index is inside
+            // the LDS arrays), then select the wall rule
+            const float4 enp = sElo[es][lx + 2];
+            const float4 enm = sElo[es][lx];
+            const float Sxp = L[my_lds + 1], Sxm = L[my_lds - 1];
+            const float Syp = L[my_lds + W], Sym = L[my_lds - W];
+            const float gxp = ghost(wx_p, S), gxm = ghost(wx_m, S);
+            const float A00p = jx_p >= 0 ? enp.x * Sxp : cM00 * gxp;
+            const float A20p = jx_p >= 0 ? enp.y * Sxp : cM02 * gxp;
+            const float A00m = jx_m >= 0 ? enm.x * Sxm : cM00 * gxm;
+            const float A20m = jx_m >= 0 ? enm.y * Sxm : cM02 * gxm;
+            const float A11p = cM11 * (jy_p >= 0 ? Syp : ghost(wy_p, S));
+            const float A11m = cM11 * (jy_m >= 0 ? Sym : ghost(wy_m, S));
             if (jz_p >= 0) {
                 const float4 en = sElo[es1][lx + 1];
                 A02p = en.y * Sp;
@@ -358,12 +353,11 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             em = make_float2(cM02, cM22);
 
             if (more) {
-                if (ring_on) sS[sb ^ 1][ring_lds] = sum7(r1);
-                if (e_on) {
-                    sElo[es2][threadIdx.x] = e1[0];
-                    sEhi[es2][threadIdx.x] = e1[1];
-                }
-                if (active) sS[sb ^ 1][my_lds] = Sp;
+                // disabled lanes write the sink slot past the end (never read)
+                sS[sb ^ 1][ring_on ? ring_lds : kSinkS] = sum7(r1);
+                sElo[es2][e_on ? (int)threadIdx.x : TX + 2] = e1[0];
+                sEhi[es2][e_on ? (int)threadIdx.x : TX + 2] = e1[1];
+                sS[sb ^ 1][active ? my_lds : kSinkS] = Sp;
                 Sm = Sc;
                 Sc = Sp;
             }
@@ -386,9 +380,9 @@ template <int TX>
 __global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
-    __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2)];
-    __shared__ float4 sElo[3][TX + 2];
-    __shared__ float4 sEhi[3][TX + 2];
+    __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2) + 1];
+    __shared__ float4 sElo[3][TX + 3];
+    __shared__ float4 sEhi[3][TX + 3];
     if (blockIdx.x == 0) probe_block(g, pr, fin);
     TileGeom tg;
     tg.n0 = g.n0;
@@ -423,9 +417,9 @@ __global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* _
                                                               int64_t tiles_total, BatchProbeArgs bp,
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
-    __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2)];
-    __shared__ float4 sElo[3][TX + 2];
-    __shared__ float4 sEhi[3][TX + 2];
+    __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2) + 1];
+    __shared__ float4 sElo[3][TX + 3];
+    __shared__ float4 sEhi[3][TX + 3];
     for (int h = blockIdx.x; h < n_items; h += gridDim.x) {
         const BatchItem& it = items[h];
         const int64_t t = *(volatile const int64_t*)(bp.tcount + h);
