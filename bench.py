@@ -102,7 +102,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="auto",
-                    help="'auto' (autotune) or TILE_X,CHUNK_Z,BLOCKS to fix the step kernel's launch shape")
+                    help="'auto' (autotune) or TILE_X,TILE_Y,CHUNK_Z,BLOCKS to fix the step kernel's launch shape")
     ap.add_argument("--spectra-horns", type=int, default=64,
                     help="horns in the batched-vs-plain spectra leg (0 skips it)")
     args = ap.parse_args()
@@ -164,8 +164,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w["name"], "nodes": N, "lattice": "D3Q7", "probes": int(len(w["probes"])),
-                   "c": geom["c"], "launch": {"tile_x": tile[0], "chunk_z": tile[1], "blocks": tile[2],
-                                              "graph_block": 32}},
+                   "c": geom["c"], "launch": {"tile_x": tile[0], "tile_y": tile[1], "chunk_z": tile[2],
+                                              "blocks": tile[3], "graph_block": 32}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "copy_ceiling": {"achieved": round(copy_gbs, 1), "unit": "GB/s",

@@ -120,14 +120,14 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max);
 
 /* Launch shape of the 3-D step kernel for this geometry (the per-node
  * arithmetic, and so every result, is the same for every shape; only speed
- * changes).  tile_x: 16, 32 or 64 nodes along axis 0 per workgroup tile (the
- * tile spans 256 / tile_x nodes along axis 1); chunk_z >= 1 planes per
- * tile along axis 2; blocks: persistent grid size, rounded down to a
- * multiple of 8 (0 = one full wave of resident workgroups).  Used by
- * lbw_autotune and by tests.  Errors: LBW_EINVAL for a 2-D geometry or
- * out-of-range values. */
-int lbw_set_step_config(lbw_geometry_t g, int tile_x, int chunk_z, int blocks);
-int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* chunk_z, int* blocks);
+ * changes).  A workgroup owns a tile_x x tile_y tile of (axis 0, axis 1)
+ * columns: tile_x is 16, 32 or 64 and tile_x * tile_y, the workgroup size,
+ * is 256 or 512; chunk_z >= 1 planes per tile along axis 2; blocks:
+ * persistent grid size, rounded down to a multiple of 8 (0 = one full wave
+ * of resident workgroups).  Used by lbw_autotune and by tests.
+ * Errors: LBW_EINVAL for a 2-D geometry or out-of-range values. */
+int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks);
+int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks);
 
 /* Creates a simulation state on caller-owned device buffers.
  *  p0        device, N doubles: initial pressure P; populations start at the
@@ -154,7 +154,8 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
 int lbw_step_n(lbw_state_t s, int64_t n);
 
 /* Picks the fastest launch shape of the 3-D step kernel for this state's
- * geometry by timing candidates (tile_x 16/32/64, chunk_z 4..64, one and two
+ * geometry by timing candidates (tile_x 16/32/64 with workgroups of 256 and
+ * 512 threads, chunk_z 4..64, one and two
  * waves of resident workgroups) for reps launches each with HIP events.  The
  * candidates run real ping-pong steps (each launch reads what the previous
  * one wrote) from the state's current buffer into its other buffer and a
@@ -227,7 +228,8 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
 int lbw_batch_layout(lbw_batch_t b, int64_t* node_offsets, int64_t* probe_offsets);
 
 /* Launch shape shared by all geometries of the batch (as
- * lbw_set_step_config).  The default made by lbw_batch_make is chunk_z 16,
+ * lbw_set_step_config, with 256-thread workgroups: tile_y = 256 / tile_x).
+ * The default made by lbw_batch_make is chunk_z 16,
  * two waves of resident workgroups, and the tile_x with the fewest idle lanes
  * over all geometries (sum of ceil(n0/tile_x) tile_x * ceil(n1/tile_y)
  * tile_y * n2; ties to the wider tile).  lbw_batch_autotune is switched

@@ -92,8 +92,8 @@ def lib():
         L.lbw_geometry_export.argtypes = [vp, i32, vp, ctypes.c_size_t]
         L.lbw_stability_bound.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         ip = ctypes.POINTER(ctypes.c_int)
-        L.lbw_set_step_config.argtypes = [vp, i32, i32, i32]
-        L.lbw_get_step_config.argtypes = [vp, ip, ip, ip]
+        L.lbw_set_step_config.argtypes = [vp, i32, i32, i32, i32]
+        L.lbw_get_step_config.argtypes = [vp, ip, ip, ip, ip]
         L.lbw_init.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), i32, vp, i64, vp, ctypes.POINTER(vp)]
         L.lbw_step_n.argtypes = [vp, i64]
         L.lbw_autotune.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
@@ -199,13 +199,14 @@ class Geometry:
         check(lib().lbw_stability_bound(self.handle, ctypes.byref(v)))
         return v.value
 
-    def set_step_config(self, tile_x: int, chunk_z: int, blocks: int = 0):
-        check(lib().lbw_set_step_config(self.handle, int(tile_x), int(chunk_z), int(blocks)))
+    def set_step_config(self, tile_x: int, tile_y: int, chunk_z: int, blocks: int = 0):
+        check(lib().lbw_set_step_config(self.handle, int(tile_x), int(tile_y), int(chunk_z), int(blocks)))
 
     def step_config(self):
-        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        check(lib().lbw_get_step_config(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
+        """(tile_x, tile_y, chunk_z, blocks) of the 3-D step kernel."""
+        v = [ctypes.c_int() for _ in range(4)]
+        check(lib().lbw_get_step_config(self.handle, *(ctypes.byref(x) for x in v)))
+        return tuple(x.value for x in v)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -54,9 +54,9 @@ namespace {
 
 thread_local std::string g_err;
 
-// tuned launch shapes per grid shape (n0, n1, n2) -> (tile_x, chunk_z, blocks)
+// tuned launch shapes per grid shape (n0, n1, n2) -> (tile_x, tile_y, chunk_z, blocks)
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, std::tuple<int, int, int>> g_tuned;
+std::map<std::tuple<int, int, int>, std::tuple<int, int, int, int>> g_tuned;
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -207,12 +207,12 @@ int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_
     const GeomDev& v = g->dev;
     if (d.dim == 3) {
         const int tx = lbw::march_tx_for(v.n0);
-        g->plan = lbw::make_march_plan(v, tx, 16, cus * lbw::march_blocks_per_cu(tx));
+        g->plan = lbw::make_march_plan(v, tx, 256 / tx, 16, cus * lbw::march_blocks_per_cu(tx, 256 / tx));
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(std::make_tuple(v.n0, v.n1, v.n2));
         if (it != g_tuned.end())
             g->plan = lbw::make_march_plan(v, std::get<0>(it->second), std::get<1>(it->second),
-                                           std::get<2>(it->second));
+                                           std::get<2>(it->second), std::get<3>(it->second));
     }
     *out = g;
     return LBW_OK;
@@ -278,26 +278,29 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max) {
     return LBW_OK;
 }
 
-int lbw_set_step_config(lbw_geometry_t g, int tile_x, int chunk_z, int blocks) {
+int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks) {
     if (!g) return fail(LBW_EINVAL, "geometry is NULL");
     if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
-    if (tile_x != 16 && tile_x != 32 && tile_x != 64) return fail(LBW_EINVAL, "tile_x must be 16, 32 or 64");
+    if (!lbw::march_shape_ok(tile_x, tile_y))
+        return fail(LBW_EINVAL, "tile %d x %d: tile_x must be 16, 32 or 64 and tile_x * tile_y 256 or 512", tile_x,
+                    tile_y);
     if (chunk_z < 1 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 1 and blocks >= 0");
     if (blocks == 0) {
         int dev = 0, cus = 0;
         HIP_TRY(hipGetDevice(&dev), "lbw_set_step_config");
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "lbw_set_step_config");
-        blocks = cus * lbw::march_blocks_per_cu(tile_x);
+        blocks = cus * lbw::march_blocks_per_cu(tile_x, tile_y);
     }
-    g->plan = lbw::make_march_plan(g->dev, tile_x, chunk_z, blocks);
+    g->plan = lbw::make_march_plan(g->dev, tile_x, tile_y, chunk_z, blocks);
     g->plan_version += 1;
     return LBW_OK;
 }
 
-int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* chunk_z, int* blocks) {
+int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks) {
     if (!g) return fail(LBW_EINVAL, "geometry is NULL");
     if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
     if (tile_x) *tile_x = g->plan.tx;
+    if (tile_y) *tile_y = g->plan.ty;
     if (chunk_z) *chunk_z = g->plan.lz;
     if (blocks) *blocks = g->plan.blocks;
     return LBW_OK;
@@ -442,13 +445,15 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     lbw::MarchPlan best = keep;
     float best_ms = 1e30f;
     float* other = s->f[1 - s->cur];
+    for (int nt : {256, 512})
     for (int tx : {16, 32, 64}) {
         if (err != hipSuccess) break;
-        const int bpc = lbw::march_blocks_per_cu(tx);
+        const int ty = nt / tx;
+        const int bpc = lbw::march_blocks_per_cu(tx, ty);
         for (int lz : {4, 8, 16, 32, 64}) {
             if (lz > 2 * g->dev.n2 && lz != 4) continue;
             for (int mult : {1, 2}) {
-                const lbw::MarchPlan p = lbw::make_march_plan(g->dev, tx, lz, mult * cus * bpc);
+                const lbw::MarchPlan p = lbw::make_march_plan(g->dev, tx, ty, lz, mult * cus * bpc);
                 float* bufs[2] = {other, tmp};
                 int w = 0;
                 auto run = [&](int count) {
@@ -480,7 +485,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     if (err != hipSuccess) return hip_fail(err, "lbw_autotune");
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[std::make_tuple(g->dev.n0, g->dev.n1, g->dev.n2)] = std::make_tuple(best.tx, best.lz, best.blocks);
+        g_tuned[std::make_tuple(g->dev.n0, g->dev.n1, g->dev.n2)] = std::make_tuple(best.tx, best.ty, best.lz, best.blocks);
     }
     if (best_us) *best_us = 1e3 * best_ms / reps;
     return LBW_OK;

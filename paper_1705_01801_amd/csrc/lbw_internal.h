@@ -65,15 +65,16 @@ hipError_t launch_step(const GeomDev& g, const ProbeArgs& pr, const float* fin, 
 
 // Launch shape of the z-marching D3Q7 kernel.
 struct MarchPlan {
-    int tx, ty;          // tile extent along axes 0 and 1 (tx * ty = 256)
+    int tx, ty;          // tile extent along axes 0 and 1 (tx * ty = threads per workgroup, 256 or 512)
     int lz;              // planes per chunk along axis 2
     int ntx, nty, nchunks;
     int64_t tiles;       // ntx * nty * nchunks
     int blocks;          // persistent grid size (multiple of 8)
 };
-MarchPlan make_march_plan(const GeomDev& g, int tx, int lz, int blocks);
+MarchPlan make_march_plan(const GeomDev& g, int tx, int ty, int lz, int blocks);
 int march_tx_for(int n0);
-int march_blocks_per_cu(int tx);
+bool march_shape_ok(int tx, int ty);  // tx in {16, 32, 64}, tx * ty in {256, 512}
+int march_blocks_per_cu(int tx, int ty);
 hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
                              float* fout, hipStream_t st);
 

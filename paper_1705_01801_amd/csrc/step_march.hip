@@ -3,9 +3,9 @@
 // Same arithmetic as the per-node description in step.hip (BGK tau = 1/2,
 // corrected equilibrium, Christoffel and metric-gradient forcing, push
 // streaming with wall rules); only the data movement differs:
-//  - a workgroup of 256 threads owns a TX x TY tile of (axis 0, axis 1)
-//    columns (TX = 16, 32 or 64, TY = 256 / TX) and walks a chunk of LZ
-//    planes along axis 2;
+//  - a workgroup of NT = 256 or 512 threads owns a TX x TY tile of (axis 0,
+//    axis 1) columns (TX = 16, 32 or 64, TY = NT / TX) and walks a chunk of
+//    LZ planes along axis 2 (the batch kernel uses NT = 256);
 //  - each thread keeps its own column's populations and S = sum_l f_l of
 //    planes z-1, z, z+1 in registers, so axis-2 neighbours cost no loads;
 //  - S of the tile plus a one-node ring is staged in LDS (two plane slots)
@@ -37,7 +37,7 @@
 namespace lbw {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kBatchThreads = 256;
 constexpr int kXcds = 8;
 
 __device__ inline void load7(const float* __restrict__ f, uint32_t N, uint32_t n, float v[7]) {
@@ -114,11 +114,11 @@ __device__ inline float bounce(int wall, float damp, float out_l, float own_lb) 
 
 // One tile of one geometry: columns [x0, x0 + TX) x [y0, y0 + TY), planes
 // [z0, z0 + lz).  fin/fout point at the geometry's own population block.
-template <int TX>
+template <int TX, int NT>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
-                                           float* __restrict__ fout, float (&sS)[2][(kThreads / TX + 2) * (TX + 2) + 1],
+                                           float* __restrict__ fout, float (&sS)[2][(NT / TX + 2) * (TX + 2) + 1],
                                            float4 (&sElo)[3][TX + 3], float4 (&sEhi)[3][TX + 3]) {
-    constexpr int TY = kThreads / TX;
+    constexpr int TY = NT / TX;
     constexpr int W = TX + 2;
     constexpr int kSinkS = (TY + 2) * W;  // LDS slot written by disabled lanes
     const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
@@ -376,11 +376,11 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
     }
 }
 
-template <int TX>
-__global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
+template <int TX, int NT>
+__global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
-    __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2) + 1];
+    __shared__ float sS[2][(NT / TX + 2) * (TX + 2) + 1];
     __shared__ float4 sElo[3][TX + 3];
     __shared__ float4 sEhi[3][TX + 3];
     if (blockIdx.x == 0) probe_block(g, pr, fin);
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeAr
     const int t_begin = (int)(plan.tiles * xcd / kXcds);
     const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
     for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
-        march_tile<TX>(tg, tile, fin, fout, sS, sElo, sEhi);
+        march_tile<TX, NT>(tg, tile, fin, fout, sS, sElo, sEhi);
 }
 
 // Batch of geometries advanced by one launch: tiles of all geometries form
@@ -413,11 +413,11 @@ __global__ __launch_bounds__(kThreads) void step_march_kernel(GeomDev g, ProbeAr
 // into one contiguous range per XCD.  Block b first records the probes of
 // geometries b, b + gridDim.x, ... (one step counter per geometry).
 template <int TX>
-__global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* __restrict__ items, int n_items,
+__global__ __launch_bounds__(kBatchThreads) void step_batch_kernel(const BatchItem* __restrict__ items, int n_items,
                                                               int64_t tiles_total, BatchProbeArgs bp,
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
-    __shared__ float sS[2][(kThreads / TX + 2) * (TX + 2) + 1];
+    __shared__ float sS[2][(kBatchThreads / TX + 2) * (TX + 2) + 1];
     __shared__ float4 sElo[3][TX + 3];
     __shared__ float4 sEhi[3][TX + 3];
     for (int h = blockIdx.x; h < n_items; h += gridDim.x) {
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* _
         tg.ntx = it.ntx;
         tg.nty = it.nty;
         tg.lz = it.lz;
-        march_tile<TX>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sElo, sEhi);
+        march_tile<TX, kBatchThreads>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sElo, sEhi);
     }
 }
 
@@ -480,51 +480,73 @@ __global__ __launch_bounds__(kThreads) void step_batch_kernel(const BatchItem* _
 
 int march_tx_for(int n0) { return n0 <= 16 ? 16 : (n0 <= 32 ? 32 : 64); }
 
-int march_blocks_per_cu(int tx) {
+bool march_shape_ok(int tx, int ty) {
+    return (tx == 16 || tx == 32 || tx == 64) && (tx * ty == 256 || tx * ty == 512);
+}
+
+namespace {
+template <int TX, int NT>
+int blocks_per_cu_of() {
     int nb = 0;
-    hipError_t e = tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<16>, kThreads, 0)
-                   : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<32>, kThreads, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<64>, kThreads, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<TX, NT>, NT, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
+}
+template <int TX, int NT>
+void launch_of(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin, float* fout,
+               hipStream_t st) {
+    hipLaunchKernelGGL((step_march_kernel<TX, NT>), dim3(plan.blocks), dim3(NT), 0, st, g, pr, plan, fin, fout);
+}
+}  // namespace
+
+int march_blocks_per_cu(int tx, int ty) {
+    const int nt = tx * ty;
+    if (nt == 512) return tx == 16 ? blocks_per_cu_of<16, 512>() : tx == 32 ? blocks_per_cu_of<32, 512>()
+                                                                            : blocks_per_cu_of<64, 512>();
+    return tx == 16 ? blocks_per_cu_of<16, 256>() : tx == 32 ? blocks_per_cu_of<32, 256>() : blocks_per_cu_of<64, 256>();
 }
 
 hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
                              float* fout, hipStream_t st) {
-    if (plan.tx == 16)
-        hipLaunchKernelGGL(step_march_kernel<16>, dim3(plan.blocks), dim3(kThreads), 0, st, g, pr, plan, fin, fout);
-    else if (plan.tx == 32)
-        hipLaunchKernelGGL(step_march_kernel<32>, dim3(plan.blocks), dim3(kThreads), 0, st, g, pr, plan, fin, fout);
-    else
-        hipLaunchKernelGGL(step_march_kernel<64>, dim3(plan.blocks), dim3(kThreads), 0, st, g, pr, plan, fin, fout);
+    if (!march_shape_ok(plan.tx, plan.ty)) return hipErrorInvalidValue;
+    const int nt = plan.tx * plan.ty;
+    if (nt == 512) {
+        if (plan.tx == 16) launch_of<16, 512>(g, pr, plan, fin, fout, st);
+        else if (plan.tx == 32) launch_of<32, 512>(g, pr, plan, fin, fout, st);
+        else launch_of<64, 512>(g, pr, plan, fin, fout, st);
+    } else {
+        if (plan.tx == 16) launch_of<16, 256>(g, pr, plan, fin, fout, st);
+        else if (plan.tx == 32) launch_of<32, 256>(g, pr, plan, fin, fout, st);
+        else launch_of<64, 256>(g, pr, plan, fin, fout, st);
+    }
     return hipGetLastError();
 }
 
 int batch_blocks_per_cu(int tx) {
     int nb = 0;
-    hipError_t e = tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<16>, kThreads, 0)
-                   : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32>, kThreads, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64>, kThreads, 0);
+    hipError_t e = tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<16>, kBatchThreads, 0)
+                   : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32>, kBatchThreads, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64>, kBatchThreads, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int blocks,
                              const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st) {
     if (tx == 16)
-        hipLaunchKernelGGL(step_batch_kernel<16>, dim3(blocks), dim3(kThreads), 0, st, items, n_items, tiles_total,
+        hipLaunchKernelGGL(step_batch_kernel<16>, dim3(blocks), dim3(kBatchThreads), 0, st, items, n_items, tiles_total,
                            bp, fin, fout);
     else if (tx == 32)
-        hipLaunchKernelGGL(step_batch_kernel<32>, dim3(blocks), dim3(kThreads), 0, st, items, n_items, tiles_total,
+        hipLaunchKernelGGL(step_batch_kernel<32>, dim3(blocks), dim3(kBatchThreads), 0, st, items, n_items, tiles_total,
                            bp, fin, fout);
     else
-        hipLaunchKernelGGL(step_batch_kernel<64>, dim3(blocks), dim3(kThreads), 0, st, items, n_items, tiles_total,
+        hipLaunchKernelGGL(step_batch_kernel<64>, dim3(blocks), dim3(kBatchThreads), 0, st, items, n_items, tiles_total,
                            bp, fin, fout);
     return hipGetLastError();
 }
 
-MarchPlan make_march_plan(const GeomDev& g, int tx, int lz, int blocks) {
+MarchPlan make_march_plan(const GeomDev& g, int tx, int ty, int lz, int blocks) {
     MarchPlan p{};
     p.tx = tx;
-    p.ty = kThreads / tx;
+    p.ty = ty;
     p.lz = lz < 1 ? 1 : lz;
     p.ntx = (g.n0 + p.tx - 1) / p.tx;
     p.nty = (g.n1 + p.ty - 1) / p.ty;

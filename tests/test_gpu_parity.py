@@ -263,11 +263,12 @@ def test_launch_shapes_bit_identical():
     o = oracle.Oracle(geom)
     f, tr = o.run(o.init(P0), 60, probes)
     ref = None
-    for tx, lz, blocks in [(64, 16, 0), (32, 1, 8), (32, 5, 16), (64, 37, 24), (64, 64, 8), (32, 7, 0), (16, 16, 0),
-                           (16, 3, 8)]:
-        say("launch shape", tx, lz, blocks)
+    for tx, ty, lz, blocks in [(64, 4, 16, 0), (32, 8, 1, 8), (32, 8, 5, 16), (64, 4, 37, 24), (64, 4, 64, 8),
+                               (32, 8, 7, 0), (16, 16, 16, 0), (16, 16, 3, 8), (64, 8, 16, 0), (32, 16, 5, 8),
+                               (16, 32, 9, 0)]:
+        say("launch shape", tx, ty, lz, blocks)
         g = lbw.Geometry(geom)
-        g.set_step_config(tx, lz, blocks)
+        g.set_step_config(tx, ty, lz, blocks)
         sim = lbw.Simulation(g, P0, probes, t_max=60)
         sim.step(60)
         fg = sim.populations().cpu().numpy()
@@ -276,9 +277,10 @@ def test_launch_shapes_bit_identical():
             assert rel_l2(fg.astype(np.float64), f) <= 1e-5
             assert np.abs(sim.probe() - tr).max() <= 1e-5 * np.abs(tr).max()
         else:
-            assert np.array_equal(fg, ref), (tx, lz, blocks)
-    with pytest.raises(lbw.LbwError):
-        lbw.Geometry(geom).set_step_config(48, 16, 0)
+            assert np.array_equal(fg, ref), (tx, ty, lz, blocks)
+    for bad in [(48, 4, 16, 0), (64, 2, 16, 0), (16, 64, 16, 0), (64, 4, 0, 0)]:
+        with pytest.raises(lbw.LbwError):
+            lbw.Geometry(geom).set_step_config(*bad)
 
 
 def test_graph_blocks_and_autotune_preserve_results():
