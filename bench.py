@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="auto",
                     help="'auto' (autotune) or TILE_X,TILE_Y,CHUNK_Z,BLOCKS to fix the step kernel's launch shape")
+    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 3),
+                    help="3-D workload to time: 1 cylinder 128x128x256 (the benchmark), 2 horn 128x128x512, "
+                         "3 torus 96x256x512")
     ap.add_argument("--spectra-horns", type=int, default=64,
                     help="horns in the batched-vs-plain spectra leg (0 skips it)")
     args = ap.parse_args()
@@ -116,7 +119,7 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    w = W.workload(1)
+    w = W.workload(args.config)
     geom = w["geom"]
     N = W.num_nodes(geom)
     g = lbw.Geometry(geom)
@@ -144,7 +147,7 @@ def main():
     mlups = N * args.steps / (ms / 1e3) / 1e6
     bytes_per_launch = 56.0 * N
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
-    traffic = read_traffic()
+    traffic = read_traffic() if args.config == 1 else None  # counters were taken on the cylinder
     # practical ceiling: a device-to-device copy moving the same bytes
     src = torch.empty(7 * N, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
