@@ -13,6 +13,12 @@
   finite volumes; its own error is of order R'^2.  This pins the horn's
   metric terms (the Mhat^rz gradient force in particular) that no closed
   form of the full problem reaches;
+* torus ring mode: a wave once around the major circle (cos theta) has the
+  lowest eigenvalue of the cross-section problem
+      -d_r(r h d_r psi) - d_phi((h/r) d_phi psi) + (r/h) psi = lam r h psi,
+  h = R + r cos(phi), zero flux at both walls (finite volumes, scipy); this
+  pins the torus metric (G^theta theta = 1/h^2, the sqrt(g) weighting, the
+  phi-dependent forces) that no closed form reaches;
 * the frequency extractor recovers known sinusoids;
 * the zeros the paper prints for the pipe's wall condition (golden file).
 """
@@ -21,6 +27,8 @@ import os
 
 import numpy as np
 import pytest
+import scipy.sparse as sparse
+import scipy.sparse.linalg as sparse_linalg
 from scipy.linalg import eigh_tridiagonal
 from scipy.optimize import brentq, minimize_scalar
 from scipy.special import jv, jvp, yv, yvp
@@ -230,3 +238,62 @@ def test_horn_modes_follow_webster():
     e2 = np.abs(horn_spectrum(a, b, k, (16, 224), "fixed", 16000, 5) / opened - 1.0)
     assert e2[0] < 0.025 and e1[0] / e2[0] > 1.6, (e1, e2)
     assert e2[1:].max() < 7e-3, e2
+
+
+def torus_ring_frequency(R, rmin, rmax, nr=200, nphi=256):
+    """Frequency (wave speed 1) of the cos(theta) mode of a torus of major
+    radius R and minor radii [rmin, rmax]: smallest eigenvalue of the
+    cross-section problem above, finite volumes on nr x nphi cells."""
+    hr, hp = (rmax - rmin) / nr, 2.0 * math.pi / nphi
+    r = rmin + (np.arange(nr) + 0.5) * hr
+    rf = rmin + np.arange(nr + 1) * hr
+    p = (np.arange(nphi) + 0.5) * hp
+    idx = lambda i, j: i * nphi + (j % nphi)
+    rows, cols, vals = [], [], []
+    diag = np.zeros(nr * nphi)
+    for i in range(nr):
+        for j in range(nphi):
+            k = idx(i, j)
+            for ii, rface in ((i + 1, rf[i + 1]), (i - 1, rf[i])):
+                if 0 <= ii < nr:  # no flux through the walls
+                    w = rface * (R + rface * math.cos(p[j])) / hr ** 2
+                    diag[k] += w
+                    rows.append(k), cols.append(idx(ii, j)), vals.append(-w)
+            for jj, pf in ((j + 1, p[j] + hp / 2), (j - 1, p[j] - hp / 2)):
+                w = (R + r[i] * math.cos(pf)) / r[i] / hp ** 2
+                diag[k] += w
+                rows.append(k), cols.append(idx(i, jj)), vals.append(-w)
+            diag[k] += r[i] / (R + r[i] * math.cos(p[j]))
+    A = sparse.csr_matrix((vals, (rows, cols)), shape=(nr * nphi,) * 2) + sparse.diags(diag)
+    rr, pp = np.meshgrid(r, p, indexing="ij")
+    B = sparse.diags((rr * (R + rr * np.cos(pp))).ravel())
+    lam = sparse_linalg.eigsh(A, k=1, M=B, sigma=0, which="LM", return_eigenvectors=False).min()
+    return math.sqrt(lam) / (2.0 * math.pi)
+
+
+def torus_ring_lbm(n, steps):
+    """Oracle on a torus grid whose major-angle links are about one lattice
+    unit long (the scheme's dispersion along an axis grows as Mhat -> -1),
+    started from P0 = cos(theta); lowest spectral peak in physical units."""
+    geom = dict(W.torus(c=0.1), n=n, h_ref=0.95 / n[0])
+    o = oracle.Oracle(geom)
+    tot = np.zeros(o.N)
+    for ax in range(3):
+        m = o.Mhat[ax] + (np.abs(o.Mhat[4]) if ax in (0, 2) else 0.0)
+        tot += np.where(m <= 1.0, 4.0, (1.0 + m) ** 2 / np.maximum(m, 1e-300))
+    geom["c"] = 0.9 * 2.0 / math.sqrt(tot.max())
+    o = oracle.Oracle(geom)
+    nr, nt, nph = n
+    probes = np.array([i0 + nr * (i1 + nt * i2) for i0 in (0, nr // 2) for i1 in (0, nt // 8) for i2 in (0, nph // 2)])
+    _, trace = o.run(o.init(np.cos(W.node_grid(geom)[1])), steps, probes)
+    freq, _ = oracle.modes(trace, 2)
+    return freq[0] / (geom["c"] * geom["h_ref"])
+
+
+def test_torus_ring_mode_converges():
+    R = W.torus()["params"][0]
+    ref = torus_ring_frequency(R, 0.05, 1.0)
+    assert abs(ref * 2.0 * math.pi * R - 1.0) > 0.01  # the cross-section matters at the level checked
+    e1 = torus_ring_lbm((8, 128, 12), 5000) / ref - 1.0
+    e2 = torus_ring_lbm((12, 192, 18), 7500) / ref - 1.0
+    assert abs(e2) < 6e-3 and abs(e1) > 1.5 * abs(e2), (e1, e2)
