@@ -287,6 +287,17 @@ int lbw_mlp_loss_grad(lbw_mlp_t m, const float* x, const float* t, const float* 
 /* One Adam step (bias-corrected) on the last gradient.  Errors: LBW_ESTATE
  * before any lbw_mlp_loss_grad, LBW_EINVAL for bad hyper-parameters. */
 int lbw_mlp_adam_step(lbw_mlp_t m, float lr, float beta1, float beta2, float eps);
+/* steps full-batch training steps (lbw_mlp_loss_grad then lbw_mlp_adam_step)
+ * on the same x, t, w, with the cosine learning rate
+ * lr (1 + cos(pi s / steps)) / 2 + lr_floor at step s = 0 .. steps-1 of this
+ * call, continuing the network's Adam state.  The rate and the bias
+ * corrections are computed on the device from a step counter, in double as
+ * a host would, and one step is captured once into a HIP graph and replayed
+ * (no per-step host work).  loss (device, 1 float, may be NULL) receives the
+ * loss of the last step's forward pass.  Synchronises.  Errors as
+ * lbw_mlp_loss_grad and lbw_mlp_adam_step; steps < 1 is LBW_EINVAL. */
+int lbw_mlp_train(lbw_mlp_t m, const float* x, const float* t, const float* w, int B, float weight_sum, int steps,
+                  double lr, double lr_floor, float beta1, float beta2, float eps, float* loss);
 int lbw_mlp_free(lbw_mlp_t m);
 
 /* Message of the calling thread's last error ("" if none). */

@@ -29,7 +29,7 @@ SYMBOLS = ("lbw_make_geometry", "lbw_free_geometry", "lbw_geometry_export", "lbw
            "lbw_batch_get_step_config", "lbw_batch_autotune", "lbw_batch_set_graph_block", "lbw_batch_step_n",
            "lbw_batch_info", "lbw_batch_probe", "lbw_batch_modes", "lbw_batch_free", "lbw_mlp_create",
            "lbw_mlp_param_count", "lbw_mlp_set_params", "lbw_mlp_get_params", "lbw_mlp_forward", "lbw_mlp_loss_grad",
-           "lbw_mlp_adam_step", "lbw_mlp_free", "lbw_last_error")
+           "lbw_mlp_adam_step", "lbw_mlp_train", "lbw_mlp_free", "lbw_last_error")
 
 
 class GeometryDesc(ctypes.Structure):
@@ -122,6 +122,8 @@ def lib():
         L.lbw_mlp_forward.argtypes = [vp, vp, i32, vp]
         L.lbw_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
         L.lbw_mlp_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        L.lbw_mlp_train.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, i32, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
         L.lbw_mlp_free.argtypes = [vp]
         L.lbw_last_error.restype = ctypes.c_char_p
         for name in SYMBOLS:
@@ -455,6 +457,20 @@ class MLP:
 
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         check(lib().lbw_mlp_adam_step(self.handle, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def train(self, x, t, w=None, steps=1000, lr=1e-3, lr_floor=1e-5, weight_sum=None, beta1=0.9, beta2=0.999,
+              eps=1e-8) -> float:
+        """steps graph-replayed training steps with the cosine learning rate
+        lr (1 + cos(pi s / steps)) / 2 + lr_floor; returns the last loss."""
+        import torch
+        B = int(x.shape[0])
+        if weight_sum is None:
+            weight_sum = float(w.sum().item()) if w is not None else float(t.numel())
+        loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+        check(lib().lbw_mlp_train(self.handle, x.data_ptr(), t.data_ptr(), None if w is None else w.data_ptr(), B,
+                                  float(weight_sum), int(steps), float(lr), float(lr_floor), float(beta1),
+                                  float(beta2), float(eps), loss.data_ptr()))
+        return float(loss.item())
 
     def close(self):
         if getattr(self, "handle", None):

@@ -137,6 +137,38 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Adam step whose learning rate and bias corrections come from a device step
+// counter, so that a captured training step can be replayed unchanged: the
+// step is the (*done + 1)-th Adam step of the network and the s-th of the
+// schedule (s = *done - done0), with the cosine rate
+// lr0 (1 + cos(pi s / total)) / 2 + lr_floor.  Same arithmetic as a host
+// computing lr and the corrections in double and passing them as floats.
+__global__ void adam_sched_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                  float* __restrict__ v, int64_t n, double lr0, double lr_floor, int64_t total,
+                                  int64_t done0, float b1, float b2, float eps, const int64_t* __restrict__ done) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t t = *done;
+    const double sfrac = (double)(t - done0) / (double)total;
+    const float lr = (float)(lr0 * 0.5 * (1.0 + cos(3.14159265358979323846 * sfrac)) + lr_floor);
+    const float c1 = 1.0f - (float)pow((double)b1, (double)(t + 1));
+    const float c2 = 1.0f - (float)pow((double)b2, (double)(t + 1));
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void count_set_kernel(int64_t* c, int64_t value) {
+    if (threadIdx.x == 0) *c = value;
+}
+
+__global__ void count_inc_kernel(int64_t* c) {
+    if (threadIdx.x == 0) *c += 1;
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <int EPI>
@@ -166,19 +198,21 @@ struct lbw_mlp {
     __bf16* dz = nullptr;        // BF16 gradient w.r.t. a pre-activation
     float* partial = nullptr;
     float* loss_dev = nullptr;
+    int64_t* d_steps = nullptr;  // Adam steps taken, on the device (scheduled training)
     int64_t steps = 0;
     bool have_grad = false;
 };
 
 namespace {
 
-hipError_t refresh_bf16(lbw_mlp* M) {
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(nblk(M->P)), dim3(256), 0, M->stream, M->p, M->wb, M->P);
+hipError_t refresh_bf16(lbw_mlp* M, hipStream_t st) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(nblk(M->P)), dim3(256), 0, st, M->p, M->wb, M->P);
     return hipGetLastError();
 }
+hipError_t refresh_bf16(lbw_mlp* M) { return refresh_bf16(M, M->stream); }
 
-hipError_t forward(lbw_mlp* M, const float* x, int B) {
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(nblk((int64_t)B * M->w[0])), dim3(256), 0, M->stream, x,
+hipError_t forward(lbw_mlp* M, const float* x, int B, hipStream_t st) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(nblk((int64_t)B * M->w[0])), dim3(256), 0, st, x,
                        M->act + M->act_off[0], (int64_t)B * M->w[0]);
     hipError_t e = hipGetLastError();
     for (int l = 0; l < M->L && e == hipSuccess; ++l) {
@@ -187,10 +221,40 @@ hipError_t forward(lbw_mlp* M, const float* x, int B) {
         const __bf16* W = M->wb + M->off[l];
         const float* bias = M->p + M->off[l] + (int64_t)N * K;
         if (l + 1 < M->L)
-            e = gemm<kEpiBiasTanhBF16>(X, K, 1, W, 1, K, B, N, K, bias, nullptr, M->act + M->act_off[l + 1], N,
-                                       M->stream);
+            e = gemm<kEpiBiasTanhBF16>(X, K, 1, W, 1, K, B, N, K, bias, nullptr, M->act + M->act_off[l + 1], N, st);
         else
-            e = gemm<kEpiBiasF32>(X, K, 1, W, 1, K, B, N, K, bias, M->yout, nullptr, N, M->stream);
+            e = gemm<kEpiBiasF32>(X, K, 1, W, 1, K, B, N, K, bias, M->yout, nullptr, N, st);
+    }
+    return e;
+}
+hipError_t forward(lbw_mlp* M, const float* x, int B) { return forward(M, x, B, M->stream); }
+
+// Loss, its gradient and the backward pass (after forward), on stream st.
+hipError_t loss_and_backward(lbw_mlp* M, const float* t, const float* w, int B, float inv, hipStream_t st) {
+    const int L = M->L;
+    const int64_t n_out = (int64_t)B * M->w[L];
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(nblk(n_out)), dim3(256), 0, st, M->yout, t, w, n_out, inv, M->dz,
+                       M->partial);
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, st, M->partial, (int)nblk(n_out), inv, M->loss_dev);
+    hipError_t e = hipGetLastError();
+    for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
+        const int K = M->w[l], N = M->w[l + 1];
+        const __bf16* X = M->act + M->act_off[l];
+        float* gW = M->g + M->off[l];
+        float* gb = gW + (int64_t)N * K;
+        // dW[n][k] = sum_b dz[b][n] X[b][k]
+        e = gemm<kEpiF32>(M->dz, 1, N, X, K, 1, N, K, B, nullptr, gW, nullptr, K, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(bias_grad_kernel, dim3(nblk(N)), dim3(256), 0, st, M->dz, B, N, gb);
+        e = hipGetLastError();
+        if (e == hipSuccess && l > 0) {
+            // dY_prev[b][k] = sum_n dz[b][n] W[n][k]
+            e = gemm<kEpiF32>(M->dz, N, 1, M->wb + M->off[l], K, 1, B, K, N, nullptr, M->dy, nullptr, K, st);
+            if (e != hipSuccess) break;
+            hipLaunchKernelGGL(tanh_back_kernel, dim3(nblk((int64_t)B * K)), dim3(256), 0, st, M->dy, X, M->dz,
+                               (int64_t)B * K);
+            e = hipGetLastError();
+        }
     }
     return e;
 }
@@ -233,6 +297,7 @@ int lbw_mlp_create(const int32_t* widths, int n_layers, int max_batch, void* str
     if (e == hipSuccess) e = hipMalloc(&M->dz, sizeof(__bf16) * bw);
     if (e == hipSuccess) e = hipMalloc(&M->partial, sizeof(float) * (nblk(bw) + 1));
     if (e == hipSuccess) e = hipMalloc(&M->loss_dev, sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&M->d_steps, sizeof(int64_t));
     if (e == hipSuccess) e = hipMemsetAsync(M->p, 0, sizeof(float) * P, M->stream);
     if (e == hipSuccess) e = hipMemsetAsync(M->m, 0, sizeof(float) * P, M->stream);
     if (e == hipSuccess) e = hipMemsetAsync(M->v, 0, sizeof(float) * P, M->stream);
@@ -285,33 +350,7 @@ int lbw_mlp_loss_grad(lbw_mlp_t M, const float* x, const float* t, const float* 
     if (B < 1 || B > M->max_batch) return fail(LBW_EINVAL, "batch %d outside [1, %d]", B, M->max_batch);
     if (!(weight_sum > 0.0f)) return fail(LBW_EINVAL, "weight_sum must be > 0");
     HIP_TRY(forward(M, x, B), "lbw_mlp_loss_grad");
-    const int L = M->L;
-    const int64_t n_out = (int64_t)B * M->w[L];
-    const float inv = 1.0f / weight_sum;
-    hipLaunchKernelGGL(loss_grad_kernel, dim3(nblk(n_out)), dim3(256), 0, M->stream, M->yout, t, w, n_out, inv, M->dz,
-                       M->partial);
-    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, M->stream, M->partial, (int)nblk(n_out), inv,
-                       M->loss_dev);
-    HIP_TRY(hipGetLastError(), "lbw_mlp_loss_grad");
-    for (int l = L - 1; l >= 0; --l) {
-        const int K = M->w[l], N = M->w[l + 1];
-        const __bf16* X = M->act + M->act_off[l];
-        float* gW = M->g + M->off[l];
-        float* gb = gW + (int64_t)N * K;
-        // dW[n][k] = sum_b dz[b][n] X[b][k]
-        HIP_TRY(gemm<kEpiF32>(M->dz, 1, N, X, K, 1, N, K, B, nullptr, gW, nullptr, K, M->stream), "mlp dW");
-        hipLaunchKernelGGL(bias_grad_kernel, dim3(nblk(N)), dim3(256), 0, M->stream, M->dz, B, N, gb);
-        HIP_TRY(hipGetLastError(), "mlp db");
-        if (l > 0) {
-            // dY_prev[b][k] = sum_n dz[b][n] W[n][k]
-            HIP_TRY(gemm<kEpiF32>(M->dz, N, 1, M->wb + M->off[l], K, 1, B, K, N, nullptr, M->dy, nullptr, K,
-                                  M->stream),
-                    "mlp dX");
-            hipLaunchKernelGGL(tanh_back_kernel, dim3(nblk((int64_t)B * K)), dim3(256), 0, M->stream, M->dy, X, M->dz,
-                               (int64_t)B * K);
-            HIP_TRY(hipGetLastError(), "mlp tanh backward");
-        }
-    }
+    HIP_TRY(loss_and_backward(M, t, w, B, 1.0f / weight_sum, M->stream), "lbw_mlp_loss_grad");
     if (loss) HIP_TRY(hipMemcpyAsync(loss, M->loss_dev, sizeof(float), hipMemcpyDeviceToDevice, M->stream), "loss");
     if (grad) HIP_TRY(hipMemcpyAsync(grad, M->g, sizeof(float) * M->P, hipMemcpyDeviceToDevice, M->stream), "grad");
     M->have_grad = true;
@@ -333,11 +372,61 @@ int lbw_mlp_adam_step(lbw_mlp_t M, float lr, float beta1, float beta2, float eps
     return LBW_OK;
 }
 
+int lbw_mlp_train(lbw_mlp_t M, const float* x, const float* t, const float* w, int B, float weight_sum, int steps,
+                  double lr, double lr_floor, float beta1, float beta2, float eps, float* loss) {
+    if (!M || !x || !t) return fail(LBW_EINVAL, "NULL argument");
+    if (B < 1 || B > M->max_batch) return fail(LBW_EINVAL, "batch %d outside [1, %d]", B, M->max_batch);
+    if (!(weight_sum > 0.0f)) return fail(LBW_EINVAL, "weight_sum must be > 0");
+    if (steps < 1) return fail(LBW_EINVAL, "steps must be >= 1");
+    if (!(lr > 0.0) || !(lr_floor >= 0.0) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+        !(eps > 0.f))
+        return fail(LBW_EINVAL, "invalid Adam hyper-parameters");
+    // the device counter starts at the network's step count; one training
+    // step (forward, loss, backward, Adam, BF16 refresh, counter) is captured
+    // on a private stream and replayed on the network's stream
+    hipLaunchKernelGGL(count_set_kernel, dim3(1), dim3(64), 0, M->stream, M->d_steps, M->steps);
+    HIP_TRY(hipGetLastError(), "lbw_mlp_train");
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "lbw_mlp_train");
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = forward(M, x, B, cap);
+        if (le == hipSuccess) le = loss_and_backward(M, t, w, B, 1.0f / weight_sum, cap);
+        if (le == hipSuccess) {
+            hipLaunchKernelGGL(adam_sched_kernel, dim3(nblk(M->P)), dim3(256), 0, cap, M->p, M->g, M->m, M->v, M->P,
+                               lr, lr_floor, (int64_t)steps, M->steps, beta1, beta2, eps, M->d_steps);
+            le = hipGetLastError();
+        }
+        if (le == hipSuccess) le = refresh_bf16(M, cap);
+        if (le == hipSuccess) {
+            hipLaunchKernelGGL(count_inc_kernel, dim3(1), dim3(64), 0, cap, M->d_steps);
+            le = hipGetLastError();
+        }
+        e = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    for (int i = 0; i < steps && e == hipSuccess; ++i) e = hipGraphLaunch(exec, M->stream);
+    if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, M->loss_dev, sizeof(float), hipMemcpyDeviceToDevice, M->stream);
+    const hipError_t es = hipStreamSynchronize(M->stream);  // before the graph is destroyed
+    if (e == hipSuccess) e = es;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return hip_fail(e, "lbw_mlp_train");
+    M->steps += steps;
+    M->have_grad = true;
+    return LBW_OK;
+}
+
 int lbw_mlp_free(lbw_mlp_t M) {
     if (!M) return LBW_OK;
     (void)hipStreamSynchronize(M->stream);
     for (void* ptr : {(void*)M->p, (void*)M->g, (void*)M->m, (void*)M->v, (void*)M->wb, (void*)M->act,
-                      (void*)M->yout, (void*)M->dy, (void*)M->dz, (void*)M->partial, (void*)M->loss_dev})
+                      (void*)M->yout, (void*)M->dy, (void*)M->dz, (void*)M->partial, (void*)M->loss_dev,
+                      (void*)M->d_steps})
         (void)hipFree(ptr);
     delete M;
     return LBW_OK;

@@ -156,10 +156,9 @@ class Surrogate:
                 params.append(rng.uniform(-lim, lim, size=self.widths[l] * self.widths[l + 1]))
                 params.append(np.zeros(self.widths[l + 1]))
             net.set_params(np.concatenate(params))
-            for s in range(steps):
-                rate = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps)) + 1e-5
-                net.loss_grad(x, t, w, weight_sum=wsum)
-                net.adam_step(lr=rate)
+            # cosine rate lr (1 + cos(pi s / steps)) / 2 + 1e-5, one captured
+            # training step replayed by the library
+            net.train(x, t, w, steps=steps, lr=lr, lr_floor=1e-5, weight_sum=wsum)
             loss = net.loss_grad(x, t, w, weight_sum=wsum)[0].item()
             losses.append(loss)
             if log:

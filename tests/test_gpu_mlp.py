@@ -108,3 +108,36 @@ def test_mlp_errors():
     with pytest.raises(lbw.LbwError):  # batch above max_batch
         lbw.check(lbw.lib().lbw_mlp_forward(net.handle, x.data_ptr(), 5, y.data_ptr()))
     assert net.forward(np.zeros((5, 3), np.float32)).shape == (5, 2)  # the binding splits large batches
+
+
+@pytest.mark.parametrize("widths,B,steps", [(WIDTHS, 512, 25), ([3, 40, 17, 10], 37, 7)])
+def test_graph_training_matches_step_by_step(widths, B, steps):
+    """lbw_mlp_train (one captured step replayed, schedule on the device)
+    against the same steps issued one call at a time with the rate computed
+    on the host: the same arithmetic, so the parameters agree to float
+    rounding of the schedule."""
+    import math
+    netA, p, x, t, w = setup(7, B, widths)
+    netB, _, _, _, _ = setup(7, B, widths)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    xt = torch.as_tensor(x.astype(np.float32), device=dev)
+    tt = torch.as_tensor(t.astype(np.float32), device=dev)
+    wt = torch.as_tensor(w.astype(np.float32), device=dev)
+    wsum = float(w.sum())
+    say("mlp graph training", widths, B, steps)
+    lossA = netA.train(xt, tt, wt, steps=steps, lr=3e-3, lr_floor=1e-5, weight_sum=wsum)
+    for s in range(steps):
+        lossB = netB.loss_grad(xt, tt, wt, weight_sum=wsum)[0].item()
+        netB.adam_step(lr=3e-3 * 0.5 * (1.0 + math.cos(math.pi * (s / steps))) + 1e-5)
+    pa, pb = netA.get_params(), netB.get_params()
+    assert np.abs(pa - pb).max() <= 1e-5 * np.abs(pb).max(), np.abs(pa - pb).max()
+    assert abs(lossA - lossB) <= 1e-5 * abs(lossB)
+    # training moved the parameters and continues from the same Adam state
+    assert np.abs(pa - p.astype(np.float32)).max() > 1e-4
+    netA.train(xt, tt, wt, steps=3, lr=1e-3, weight_sum=wsum)
+    for s in range(3):
+        netB.loss_grad(xt, tt, wt, weight_sum=wsum)
+        netB.adam_step(lr=1e-3 * 0.5 * (1.0 + math.cos(math.pi * (s / 3))) + 1e-5)
+    assert np.abs(netA.get_params() - netB.get_params()).max() <= 1e-5 * np.abs(pb).max()
+    with pytest.raises(lbw.LbwError):
+        netA.train(xt, tt, wt, steps=0)
