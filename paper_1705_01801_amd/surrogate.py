@@ -135,9 +135,14 @@ class Surrogate:
         self.seed = seed
         self.feat = None
 
-    def fit(self, prof: np.ndarray, freqs: np.ndarray, steps: int = 4000, lr: float = 1e-3, log=None):
+    def fit(self, prof: np.ndarray, freqs: np.ndarray, steps: int = 4000, lr: float = 1e-3, log=None,
+            bootstrap: bool = True):
         """Full-batch Adam on all valid (finite, positive) targets; returns
-        the final training loss of each member."""
+        the final training loss of each member on the whole set.  With
+        bootstrap each member sees its own resample of the training horns
+        (Poisson(1) multiplicities as weights), so members also disagree where
+        the targets jump between neighbouring horns, not only where the data
+        is thin."""
         import torch
         logf = np.where(np.isfinite(freqs) & (freqs > 0), np.log(np.where(freqs > 0, freqs, 1.0)), np.nan)
         self.feat = Features(self.ranges, logf)
@@ -158,7 +163,13 @@ class Surrogate:
             net.set_params(np.concatenate(params))
             # cosine rate lr (1 + cos(pi s / steps)) / 2 + 1e-5, one captured
             # training step replayed by the library
-            net.train(x, t, w, steps=steps, lr=lr, lr_floor=1e-5, weight_sum=wsum)
+            if bootstrap:
+                mult = rng.poisson(1.0, size=len(wn)).astype(np.float32)
+                wb = wn * mult[:, None]
+                net.train(x, t, torch.as_tensor(wb, device=dev), steps=steps, lr=lr, lr_floor=1e-5,
+                          weight_sum=float(wb.sum()))
+            else:
+                net.train(x, t, w, steps=steps, lr=lr, lr_floor=1e-5, weight_sum=wsum)
             loss = net.loss_grad(x, t, w, weight_sum=wsum)[0].item()
             losses.append(loss)
             if log:

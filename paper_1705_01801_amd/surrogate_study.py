@@ -30,6 +30,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--plain", type=int, default=16)
     ap.add_argument("--judge", type=int, default=128)
+    ap.add_argument("--no-bootstrap", action="store_true", help="train every member on the whole training set")
     ap.add_argument("--fallback-sample", type=int, default=256)
     ap.add_argument("--candidates", type=int, default=100000)
     ap.add_argument("--threshold", type=float, default=0.01)
@@ -90,10 +91,10 @@ def main(argv=None):
     sur = S.Surrogate([W.HORN_RANGES[k] for k in ("a", "b", "k")], members=4,
                       widths=(3, args.hidden, args.hidden, args.hidden, K))
     t0 = time.perf_counter()
-    losses = sur.fit(prof, f_train, steps=args.train_steps, log=log)
+    losses = sur.fit(prof, f_train, steps=args.train_steps, log=log, bootstrap=not args.no_bootstrap)
     torch.cuda.synchronize()
     rep["training"] = {"seconds": time.perf_counter() - t0, "final_losses": losses, "widths": sur.widths,
-                       "adam_steps": args.train_steps,
+                       "adam_steps": args.train_steps, "bootstrap": not args.no_bootstrap,
                        "valid_targets": int(np.isfinite(f_train).sum())}
 
     # 4. inference on candidates
@@ -113,19 +114,26 @@ def main(argv=None):
     def simulate(idx):
         ms = S.with_wave_speeds([W.horn_member(cprof[i], cgrid[i]) for i in idx])
         ps = [W.horn_pulse(m["geom"]) for m in ms]
-        f, ts, tm = S.run_batch(ms, ps, steps, K, log=log)
-        return f, ts + tm
+        f, ts, tm, pw, _ = S.run_batch(ms, ps, steps, K, log=log, keep_trace=True)
+        return f, ts + tm, pw
 
     # 5. judge accepted candidates
     acc = np.flatnonzero(~fallback)
     if len(acc):
         jidx = rng.choice(acc, size=min(args.judge, len(acc)), replace=False)
-        f_judge, t_judge = simulate(jidx)
+        f_judge, t_judge, pw_judge = simulate(jidx)
         ok = np.isfinite(f_judge) & np.isfinite(mean[jidx])
         err = np.abs(mean[jidx][ok] / f_judge[ok] - 1.0)
         rep["judge"] = {"sampled": len(jidx), "seconds": t_judge, "modes_compared": int(ok.sum()),
                         "rel_err_median": float(np.median(err)), "rel_err_p95": float(np.quantile(err, 0.95)),
                         "rel_err_max": float(err.max()), "frac_within_1pct": float((err <= 0.01).mean())}
+        # accepted candidates with a mode more than 1 % off: what the surrogate
+        # predicted against the LBM's modes and their spectral powers
+        cand_err = np.where(ok, np.abs(mean[jidx] / np.where(ok, f_judge, 1.0) - 1.0), 0.0).max(axis=1)
+        rep["judge"]["outliers"] = [
+            {"profile": cprof[jidx[i]].tolist(), "grid": [int(v) for v in cgrid[jidx[i]]],
+             "spread": float(spread[jidx[i]]), "predicted": mean[jidx[i]].tolist(), "lbm": f_judge[i].tolist(),
+             "lbm_power": pw_judge[i].tolist()} for i in np.flatnonzero(cand_err > 0.01)]
         log("judge: median %.2e p95 %.2e max %.2e" % (np.median(err), np.quantile(err, 0.95), err.max()))
 
     # 6. fallback cost per spectrum (batched LBM on a sample of the fallback set)
@@ -133,7 +141,7 @@ def main(argv=None):
     per_spec = rep["batched"]["seconds"] / rep["batched"]["horns"]
     if len(fb):
         fidx = rng.choice(fb, size=min(args.fallback_sample, len(fb)), replace=False)
-        _, t_fb = simulate(fidx)
+        _, t_fb, _ = simulate(fidx)
         per_spec = t_fb / len(fidx)
         rep["fallback_sample"] = {"sampled": len(fidx), "seconds": t_fb, "seconds_per_spectrum": per_spec}
     total = t_inf + len(fb) * per_spec
