@@ -141,6 +141,10 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
         const int x = x0 + lx, y = y0 + ly;
         const bool active = lx < wdt && ly < hgt;
         const uint32_t col = (uint32_t)x + (uint32_t)n0 * (uint32_t)y;
+        // the tile holds whole walled axis-0 rows: the axis-0 populations
+        // reach their destinations by a lane shift, so each lane stores its
+        // own node's (aligned stores instead of stores shifted by one float)
+        const bool row_tile = x0 == 0 && wdt == n0 && g.bc_lo[0] != LBW_BC_PERIODIC;
 
         int wx_p = 0, wx_m = 0, wy_p = 0, wy_m = 0;
         const int jx_p = link_coord(x, +1, n0, g.bc_lo[0], g.bc_hi[0], &wx_p);
@@ -331,14 +335,27 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             // push with the wall rules: destination offset and value by select
             const uint32_t nb = col4 + (uint32_t)z * plane4;
             const uint32_t o0 = nb;
-            const uint32_t o1 = jx_p >= 0 ? 1u * N4 + nb + (uint32_t)(jx_p - x) * 4u : 2u * N4 + nb;
-            const uint32_t o2 = jx_m >= 0 ? 2u * N4 + nb + (uint32_t)(jx_m - x) * 4u : 1u * N4 + nb;
+            const uint32_t o1 = row_tile ? 1u * N4 + nb
+                                : jx_p >= 0 ? 1u * N4 + nb + (uint32_t)(jx_p - x) * 4u : 2u * N4 + nb;
+            const uint32_t o2 = row_tile ? 2u * N4 + nb
+                                : jx_m >= 0 ? 2u * N4 + nb + (uint32_t)(jx_m - x) * 4u : 1u * N4 + nb;
             const uint32_t o3 = jy_p >= 0 ? 3u * N4 + nb + (uint32_t)((jy_p - y) * n0) * 4u : 4u * N4 + nb;
             const uint32_t o4 = jy_m >= 0 ? 4u * N4 + nb + (uint32_t)((jy_m - y) * n0) * 4u : 3u * N4 + nb;
             const uint32_t o5 = jz_p >= 0 ? 5u * N4 + col4 + (uint32_t)jz_p * plane4 : 6u * N4 + nb;
             const uint32_t o6 = jz_m >= 0 ? 6u * N4 + col4 + (uint32_t)jz_m * plane4 : 5u * N4 + nb;
-            const float v1 = jx_p >= 0 ? fs[1] : bounce(wx_p, damp, fs[1], fs[2]);
-            const float v2 = jx_m >= 0 ? fs[2] : bounce(wx_m, damp, fs[2], fs[1]);
+            float v1 = jx_p >= 0 ? fs[1] : bounce(wx_p, damp, fs[1], fs[2]);
+            float v2 = jx_m >= 0 ? fs[2] : bounce(wx_m, damp, fs[2], fs[1]);
+            {
+                // whole-row tile: population 1 of this node comes from the
+                // lane on the left (or the wall at x = 0), population 2 from
+                // the lane on the right (or the wall at x = n0 - 1)
+                const float from_left = __shfl_up(fs[1], 1, TX);
+                const float from_right = __shfl_down(fs[2], 1, TX);
+                const float in1 = jx_m >= 0 ? from_left : v2;
+                const float in2 = jx_p >= 0 ? from_right : v1;
+                v1 = row_tile ? in1 : v1;
+                v2 = row_tile ? in2 : v2;
+            }
             const float v3 = jy_p >= 0 ? fs[3] : bounce(wy_p, damp, fs[3], fs[4]);
             const float v4 = jy_m >= 0 ? fs[4] : bounce(wy_m, damp, fs[4], fs[3]);
             const float v5 = jz_p >= 0 ? fs[5] : bounce(wz_p, damp, fs[5], fs[6]);
