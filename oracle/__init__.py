@@ -69,6 +69,9 @@ def _load():
         lib.orc_step.argtypes = [gp, dp, dp, dp, dp, dp]
         lib.orc_run.argtypes = [gp, dp, dp, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                 ctypes.c_int, dp]
+        lib.orc_run_driven.argtypes = [gp, dp, dp, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.c_int, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.c_int, ctypes.c_double, ctypes.c_double]
         lib.orc_invariant.argtypes = [gp, dp]
         lib.orc_invariant.restype = ctypes.c_double
         lib.orc_pressure.argtypes = [gp, dp, dp, dp]
@@ -149,16 +152,29 @@ class Oracle:
         assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (self.Q, self.N)
         return self.run(f, n, [])[0]
 
-    def run(self, f: np.ndarray, nsteps: int, probes):
-        """Advances f in place; returns (f, trace[nsteps, n_probes]) where
-        trace[t] is the pressure at each probe before step t."""
+    def run(self, f: np.ndarray, nsteps: int, probes, sources=None, amplitude: float = 0.0, omega: float = 0.0,
+            t0: int = 0):
+        """Advances f in place from time t0; returns (f, trace[nsteps, n_probes])
+        where trace[s] is the pressure at each probe at time t0 + s, before
+        that step.  With sources (node indices) the pressure
+        amplitude * sin(omega t) is imposed at those nodes at every time t
+        before the probes are read (populations at rest at that pressure)."""
         assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (self.Q, self.N)
         probes = np.ascontiguousarray(probes, dtype=np.int64).reshape(-1)
+        src = np.ascontiguousarray([] if sources is None else sources, dtype=np.int64).reshape(-1)
+        assert src.size == 0 or (src.min() >= 0 and src.max() < self.N)
         trace = np.zeros((max(int(nsteps), 0), probes.size))
         w = self._workbuf()
-        self.lib.orc_run(ctypes.byref(self._g), _ptr(self.Mhat), _ptr(self.Gamh), _ptr(self.sqrtg), _ptr(f),
-                         _ptr(w), int(nsteps), _ptr(probes, ctypes.c_int64), int(probes.size), _ptr(trace))
+        self.lib.orc_run_driven(ctypes.byref(self._g), _ptr(self.Mhat), _ptr(self.Gamh), _ptr(self.sqrtg), _ptr(f),
+                                _ptr(w), int(nsteps), _ptr(probes, ctypes.c_int64), int(probes.size), _ptr(trace),
+                                int(t0), _ptr(src, ctypes.c_int64), int(src.size), float(amplitude), float(omega))
         return f, trace
+
+    @staticmethod
+    def amplitude(trace: np.ndarray, t0: int, t1: int) -> np.ndarray:
+        """Response intensity of a driven run (Sec. IV.A, the pipe sweeps):
+        the largest |P| at each probe over trace rows [t0, t1)."""
+        return np.abs(np.asarray(trace)[t0:t1]).max(axis=0)
 
     def invariant(self, f) -> float:
         return float(self.lib.orc_invariant(ctypes.byref(self._g), _ptr(np.ascontiguousarray(f))))

@@ -405,20 +405,48 @@ static double orc_probe_value(const orc_geom* g, const double* f, const double* 
     return s / sqrtg[node];
 }
 
-/* Runs nsteps steps in place.  Before each step t the pressure at every probe
- * is appended: trace[t * np + p] = P(probe_p, t0 + t).  work holds
- * (Q + 1) * N doubles. */
-int orc_run(const orc_geom* g, const double* Mhat, const double* Gamh, const double* sqrtg, double* f,
-            double* work, int64_t nsteps, const int64_t* probes, int np, double* trace) {
+/* Driven source (Sec. IV.A and IV.C: the pressure imposed at source nodes
+ * as a harmonic function of time).  At time t every source node is put at
+ * rest at the imposed pressure P = amp sin(omega t): f_0 = w_0 sqrt(g) P,
+ * f_l = w sqrt(g) P (the initial-state rule, zero first moment). */
+static void orc_impose(const orc_geom* g, const double* sqrtg, double* f, int64_t t, const int64_t* src, int ns,
+                       double amp, double omega) {
+    int d = g->dim, Q = 2 * d + 1;
+    int64_t N = orc_nodes(g);
+    double c2 = g->c * g->c;
+    double P = amp * sin(omega * (double)t);
+    for (int i = 0; i < ns; ++i) {
+        int64_t n = src[i];
+        for (int l = 0; l < Q; ++l) {
+            double w = (l == 0) ? 1.0 - d * c2 : 0.5 * c2;
+            f[l * N + n] = w * sqrtg[n] * P;
+        }
+    }
+}
+
+/* Runs nsteps steps in place, from time t0.  At each time t = t0 + s the
+ * sources (if any) are imposed, then the pressure at every probe is
+ * appended, trace[s * np + p] = P(probe_p, t), then the step t -> t+1 runs.
+ * work holds (Q + 1) * N doubles. */
+int orc_run_driven(const orc_geom* g, const double* Mhat, const double* Gamh, const double* sqrtg, double* f,
+                   double* work, int64_t nsteps, const int64_t* probes, int np, double* trace, int64_t t0,
+                   const int64_t* src, int ns, double amp, double omega) {
     int Q = 2 * g->dim + 1;
     int64_t N = orc_nodes(g);
     double* fs = work;
     double* S = work + (int64_t)Q * N;
-    for (int64_t t = 0; t < nsteps; ++t) {
-        for (int p = 0; p < np; ++p) trace[t * np + p] = orc_probe_value(g, f, sqrtg, probes[p]);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (ns > 0) orc_impose(g, sqrtg, f, t0 + s, src, ns, amp, omega);
+        for (int p = 0; p < np; ++p) trace[s * np + p] = orc_probe_value(g, f, sqrtg, probes[p]);
         orc_step(g, Mhat, Gamh, f, fs, S);
     }
     return 0;
+}
+
+/* Undriven run: as orc_run_driven with no sources. */
+int orc_run(const orc_geom* g, const double* Mhat, const double* Gamh, const double* sqrtg, double* f,
+            double* work, int64_t nsteps, const int64_t* probes, int np, double* trace) {
+    return orc_run_driven(g, Mhat, Gamh, sqrtg, f, work, nsteps, probes, np, trace, 0, NULL, 0, 0.0, 0.0);
 }
 
 /* Scalar invariant sum_x sqrt(g) P = sum_x sum_l f_l (Sec. III, curvilinear

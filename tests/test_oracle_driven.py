@@ -1,0 +1,132 @@
+"""Pins for the oracle's driven runs (CPU only).
+
+A driven source imposes the pressure C sin(omega t) at chosen nodes at every
+time t, the populations there put at rest at that pressure (Sec. IV.A and
+IV.C, the ring and point sources of the pipe and torus experiments); the
+response intensity is the largest |P| at a probe over a late window of the
+run (the pipe and torus frequency sweeps).  Pins:
+
+* a probe on a source node reads C sin(omega t) exactly, on a curvilinear
+  grid (sqrt(g) != 1), so the imposed populations carry sqrt(g) and sum to
+  sqrt(g) P, and the imposition precedes the probe read at the same t;
+* linearity in C, a zero drive leaves the field at rest, and a run split in
+  two calls (second one from t0) equals one run;
+* the exact periodic steady state of a driven 1-D line: with x(t) the state
+  after the imposition at time t, x(t) = Im(X e^{i omega t}), the linear step
+  A, the projection Pi that clears the source node and the imposed rest
+  populations b, the phasor solves (e^{i omega} I - Pi A) X = C b e^{i omega}.
+  A is built column by column from a separate 1-D implementation of the
+  scheme's step (identity metric, damped half-way bounce-back), and the
+  system is solved in the frequency domain, independent of the oracle's time
+  loop.  The oracle's trace over a late window must follow Im(Z e^{i omega t})
+  at every probe; the residual is the slowly decaying transient that
+  switching the drive on leaves behind (measured <= 3.2e-4 of |Z| after 8000
+  steps for the frequencies below), against a deviation of order omega for a
+  drive applied one step early or late;
+* the intensity rule on the steady sinusoid: within |Z| (1 - omega^2 / 8)
+  (integer-time sampling of the crest) and |Z| plus that residual.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+
+def line_geom(N, c, D):
+    return dict(kind="box", dim=3, n=(1, 1, N), qmin=(0.0, 0.0, 0.0), qmax=(1.0, 1.0, float(N)),
+                bc_lo=("periodic", "periodic", "bounceback"), bc_hi=("periodic", "periodic", "bounceback"),
+                h_ref=1.0, c=c, damp=D, params=())
+
+
+def test_source_node_reads_imposed_pressure():
+    geom = W.closed_cylinder(scale=16)
+    n0, n1, n2 = geom["n"]
+    o = oracle.Oracle(geom)
+    ring = [0 + n0 * (i1 + n1 * 0) for i1 in range(n1)]      # r = r_min, z = 0, all theta
+    point = [3 + n0 * (2 + n1 * 5)]                           # an interior node
+    src = ring + point
+    assert np.ptp(o.sqrtg[src]) > 0.1                         # sqrt(g) differs between them
+    C, w, T = 0.7, 0.05, 120
+    f = o.init(np.zeros(o.N))
+    _, tr = o.run(f, T, src + [point[0] + 1], sources=src, amplitude=C, omega=w)
+    expect = C * np.sin(w * np.arange(T))
+    assert np.abs(tr[:, :len(src)] - expect[:, None]).max() <= 1e-13
+    assert np.abs(tr[T // 2:, -1]).max() > 1e-3              # the drive reaches the neighbour
+
+
+def test_drive_linear_and_time_origin():
+    geom = W.closed_cylinder(scale=16)
+    n0, n1 = geom["n"][0], geom["n"][1]
+    o = oracle.Oracle(geom)
+    src = [1 + n0 * (i1 + n1 * 2) for i1 in range(n1)]
+    probes = [5 + n0 * (3 + n1 * 9), 2 + n0 * (7 + n1 * 14)]
+    runs = {}
+    for C in (0.0, 0.5, 1.0):
+        f = o.init(np.zeros(o.N))
+        runs[C] = o.run(f, 200, probes, sources=src, amplitude=C, omega=0.08)
+    assert not runs[0.0][0].any() and not runs[0.0][1].any()
+    assert np.abs(runs[1.0][1] - 2.0 * runs[0.5][1]).max() <= 1e-12 * np.abs(runs[1.0][1]).max()
+    assert np.abs(runs[1.0][0] - 2.0 * runs[0.5][0]).max() <= 1e-12 * np.abs(runs[1.0][0]).max()
+    f = o.init(np.zeros(o.N))
+    _, t1 = o.run(f, 120, probes, sources=src, amplitude=1.0, omega=0.08)
+    _, t2 = o.run(f, 80, probes, sources=src, amplitude=1.0, omega=0.08, t0=120)
+    assert np.array_equal(f, runs[1.0][0])
+    assert np.array_equal(np.vstack([t1, t2]), runs[1.0][1])
+
+
+def line_step(f, c, D):
+    """One step of the scheme on a 1 x 1 x N box with the identity metric,
+    written for this pin: f[7, N] in the order rest, +x, -x, +y, -y, +z, -z;
+    the x and y links return to the node itself (one periodic node), the z
+    links reflect at half-way walls with damping D."""
+    c2 = c * c
+    S = f.sum(axis=0)
+    out = np.empty_like(f)
+    out[0] = 2.0 * (1.0 - 3.0 * c2) * S - f[0]
+    for p, m in ((1, 2), (3, 4), (5, 6)):
+        K = f[p] - f[m]
+        out[p] = c2 * S + K - f[p]
+        out[m] = c2 * S - K - f[m]
+    g = out.copy()
+    g[5, 1:] = out[5, :-1]
+    g[6, :-1] = out[6, 1:]
+    g[5, 0] = D * out[6, 0]
+    g[6, -1] = D * out[5, -1]
+    return g
+
+
+def steady_phasors(N, c, D, omega, C):
+    """Phasor X[7, N] of the periodic steady state, source at node 0."""
+    n = 7 * N
+    A = np.empty((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        A[:, j] = line_step(e.reshape(7, N), c, D).reshape(-1)
+    keep = np.ones(n)
+    keep[np.arange(7) * N] = 0.0
+    b = np.zeros(n)
+    b[0] = 1.0 - 3.0 * c * c
+    b[np.arange(1, 7) * N] = 0.5 * c * c
+    z = np.exp(1j * omega)
+    return np.linalg.solve(z * np.eye(n) - keep[:, None] * A, C * b * z).reshape(7, N)
+
+
+@pytest.mark.parametrize("omega", [0.013, 0.047, 0.09, 0.15])
+def test_driven_line_reaches_exact_steady_state(omega):
+    N, c, D, C, T, win = 40, 0.5, 0.65, 1.3, 8000, 400
+    o = oracle.Oracle(line_geom(N, c, D))
+    probes = [0, 1, N // 2, N - 1]
+    Z = steady_phasors(N, c, D, omega, C)[:, probes].sum(axis=0)   # sqrt(g) = 1
+    f = o.init(np.zeros(o.N))
+    _, tr = o.run(f, T, probes, sources=[0], amplitude=C, omega=omega)
+    t = np.arange(T - win, T)
+    steady = np.imag(Z[None, :] * np.exp(1j * omega * t)[:, None])
+    resid = np.abs(tr[T - win:] - steady).max(axis=0) / np.abs(Z)
+    assert resid.max() <= 1e-3, resid
+    amp = o.amplitude(tr, T - win, T)
+    assert np.all(amp >= np.abs(Z) * (1.0 - omega * omega / 8.0) - resid * np.abs(Z) - 1e-12)
+    assert np.all(amp <= np.abs(Z) * (1.0 + resid) + 1e-12)
