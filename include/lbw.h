@@ -190,6 +190,25 @@ int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out);
 /* Current step count and the device buffer holding the current populations. */
 int lbw_state_info(lbw_state_t s, int64_t* t, float** f_current);
 
+/* Driven sources (Sec. IV.A pipe ring source, Sec. IV.C torus ring and point
+ * sources: the pressure imposed at chosen nodes as a harmonic function of
+ * time).  From the next queued step on, at every time t (steps since
+ * lbw_init) the populations of each node in nodes[0..n) are put at rest at
+ * the pressure P = amplitude * sin(omega t), f_0 = w_0 sqrt(g) P and
+ * f_l = w sqrt(g) P (the rule of lbw_init), before the probes are read and
+ * the step t -> t+1 is taken; omega is in radians per step.  nodes is host
+ * memory, read during the call.  n = 0 removes the sources.  Waits for the
+ * stream.  Errors: LBW_EINVAL (n < 0, NULL nodes with n > 0, a node outside
+ * the grid, non-finite amplitude or omega), LBW_ENOMEM, LBW_EDEVICE. */
+int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude, double omega);
+
+/* Response intensity of a driven run (the frequency sweeps of Sec. IV.A and
+ * IV.C): out (host, n_probes values) receives the largest |P| of each probe
+ * over recorded rows [t0, t1).  Waits for the stream.  Errors: LBW_EINVAL
+ * (no probes, an empty window or one outside the recorded rows),
+ * LBW_EUNSTABLE (a non-finite value in the window; out is still written). */
+int lbw_amplitude(lbw_state_t s, int64_t t0, int64_t t1, double* out);
+
 /* Pressure P = sum_l f_l / sqrt(g) of the current state into a device buffer
  * of N doubles (queued on the state's stream). */
 int lbw_pressure(lbw_state_t s, double* p_out);
@@ -253,6 +272,21 @@ int lbw_batch_probe(lbw_batch_t b, double* host_dst, int64_t t0, int64_t t1);
  * geometry's probes): freq_out and power_out (may be NULL) receive n * k
  * values, geometry-major.  Synchronises.  Errors as lbw_modes. */
 int lbw_batch_modes(lbw_batch_t b, int k, double* freq_out, double* power_out);
+
+/* Driven sources of a batch (the rule of lbw_set_sources): source i sits at
+ * node nodes[i] of geometry geom[i] with its own amplitude[i] and omega[i],
+ * so one batch can sweep many drive frequencies over copies of a geometry;
+ * t is that geometry's step count.  All arrays are host memory of n
+ * entries, read during the call; n = 0 removes the sources.  Waits for the
+ * stream.  Errors: LBW_EINVAL (n < 0, NULL arrays with n > 0, a geometry
+ * index or node out of range, non-finite amplitude or omega), LBW_ENOMEM,
+ * LBW_EDEVICE. */
+int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* geom, const double* amplitude,
+                          const double* omega, int n);
+
+/* Response intensity of every probe of the batch (P values in global probe
+ * order) over rows [t0, t1); as lbw_amplitude. */
+int lbw_batch_amplitude(lbw_batch_t b, int64_t t0, int64_t t1, double* out);
 
 /* Releases the batch (waits for its stream); caller buffers untouched. */
 int lbw_batch_free(lbw_batch_t b);

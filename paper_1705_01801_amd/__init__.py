@@ -25,9 +25,10 @@ TABLE_PLANES = ("Mhat00", "Mhat11", "Mhat22", "Mhat02", "Gamh0", "Gamh1", "Gamh2
 SYMBOLS = ("lbw_make_geometry", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound",
            "lbw_set_step_config", "lbw_get_step_config", "lbw_init",
            "lbw_step_n", "lbw_autotune", "lbw_set_graph_block", "lbw_probe", "lbw_modes", "lbw_state_info",
-           "lbw_pressure", "lbw_free_state", "lbw_batch_make", "lbw_batch_layout", "lbw_batch_set_step_config",
+           "lbw_pressure", "lbw_free_state", "lbw_set_sources", "lbw_amplitude", "lbw_batch_make", "lbw_batch_layout", "lbw_batch_set_step_config",
            "lbw_batch_get_step_config", "lbw_batch_autotune", "lbw_batch_set_graph_block", "lbw_batch_step_n",
-           "lbw_batch_info", "lbw_batch_probe", "lbw_batch_modes", "lbw_batch_free", "lbw_mlp_create",
+           "lbw_batch_info", "lbw_batch_probe", "lbw_batch_modes", "lbw_batch_set_sources",
+           "lbw_batch_amplitude", "lbw_batch_free", "lbw_mlp_create",
            "lbw_mlp_param_count", "lbw_mlp_set_params", "lbw_mlp_get_params", "lbw_mlp_forward", "lbw_mlp_loss_grad",
            "lbw_mlp_adam_step", "lbw_mlp_train", "lbw_mlp_free", "lbw_last_error")
 
@@ -103,6 +104,8 @@ def lib():
         L.lbw_state_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(vp)]
         L.lbw_pressure.argtypes = [vp, vp]
         L.lbw_free_state.argtypes = [vp]
+        L.lbw_set_sources.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.c_double, ctypes.c_double]
+        L.lbw_amplitude.argtypes = [vp, i64, i64, vp]
         L.lbw_batch_make.argtypes = [ctypes.POINTER(GeometryDesc), i32, vp, vp, vp, ctypes.POINTER(i64),
                                      ctypes.POINTER(ctypes.c_int32), vp, i64, vp, ctypes.POINTER(vp)]
         L.lbw_batch_layout.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -115,6 +118,9 @@ def lib():
         L.lbw_batch_probe.argtypes = [vp, vp, i64, i64]
         L.lbw_batch_modes.argtypes = [vp, i32, vp, vp]
         L.lbw_batch_free.argtypes = [vp]
+        L.lbw_batch_set_sources.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), i32]
+        L.lbw_batch_amplitude.argtypes = [vp, i64, i64, vp]
         L.lbw_mlp_create.argtypes = [ctypes.POINTER(ctypes.c_int32), i32, i32, vp, ctypes.POINTER(vp)]
         L.lbw_mlp_param_count.argtypes = [vp, ctypes.POINTER(i64)]
         L.lbw_mlp_set_params.argtypes = [vp, vp]
@@ -287,6 +293,19 @@ class Simulation:
         check(lib().lbw_modes(self.handle, int(k), freq.ctypes.data, power.ctypes.data))
         return freq, power
 
+    def set_sources(self, nodes, amplitude: float, omega: float):
+        """Drives the pressure amplitude * sin(omega t) at the given nodes
+        from the next step on (an empty list removes the sources)."""
+        nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64).reshape(-1))
+        check(lib().lbw_set_sources(self.handle, nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    int(nodes.size), float(amplitude), float(omega)))
+
+    def amplitude(self, t0: int, t1: int) -> np.ndarray:
+        """Largest |P| of each probe over recorded rows [t0, t1)."""
+        out = np.zeros(self.n_probes)
+        check(lib().lbw_amplitude(self.handle, int(t0), int(t1), out.ctypes.data))
+        return out
+
     def pressure(self):
         import torch
         out = torch.empty(self.geometry.N, dtype=torch.float64, device=self.f[0].device)
@@ -384,6 +403,25 @@ class Batch:
         if out.size == 0:
             return out
         check(lib().lbw_batch_probe(self.handle, out.ctypes.data, int(t0), int(t1)))
+        return out
+
+    def set_sources(self, nodes, geom, amplitude, omega):
+        """Source i drives amplitude[i] * sin(omega[i] t) at node nodes[i]
+        of geometry geom[i] (scalars broadcast); empty lists remove them."""
+        nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64).reshape(-1))
+        n = nodes.size
+        geom = np.ascontiguousarray(np.broadcast_to(np.asarray(geom, dtype=np.int32), (n,)))
+        amp = np.ascontiguousarray(np.broadcast_to(np.asarray(amplitude, dtype=np.float64), (n,)))
+        om = np.ascontiguousarray(np.broadcast_to(np.asarray(omega, dtype=np.float64), (n,)))
+        check(lib().lbw_batch_set_sources(self.handle, nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          geom.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                          amp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n)))
+
+    def amplitude(self, t0: int, t1: int) -> np.ndarray:
+        """Largest |P| of every probe (global order) over rows [t0, t1)."""
+        out = np.zeros(self.P)
+        check(lib().lbw_batch_amplitude(self.handle, int(t0), int(t1), out.ctypes.data))
         return out
 
     def modes(self, k: int):

@@ -44,6 +44,9 @@ struct lbw_state {
     double* mode_out = nullptr;  // device, 2 * mode_k
     int mode_k = 0;
     int64_t* d_scratch_count = nullptr;  // step counter for timing launches
+    lbw::SourceEntry* d_src = nullptr;   // driven sources, imposed before every step
+    int n_src = 0;
+    double* d_amp = nullptr;             // response intensities (n_probes)
     // graph-captured step blocks, one per starting buffer parity
     int graph_block = 32;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -348,6 +351,10 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
 namespace {
 
 hipError_t launch_one(lbw_state* s, const lbw::ProbeArgs& pr, int from, hipStream_t st) {
+    if (s->n_src > 0) {
+        const hipError_t e = lbw::launch_sources(s->d_src, s->n_src, s->d_tcount, s->f[from], st);
+        if (e != hipSuccess) return e;
+    }
     if (s->g->dev.dim == 3)
         return lbw::launch_step_march(s->g->dev, pr, s->g->plan, s->f[from], s->f[1 - from], st);
     return lbw::launch_step(s->g->dev, pr, s->f[from], s->f[1 - from], st);
@@ -546,6 +553,67 @@ int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out) {
     return LBW_OK;
 }
 
+int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude, double omega) {
+    if (!s) return fail(LBW_EINVAL, "state is NULL");
+    if (n < 0 || (n > 0 && !nodes)) return fail(LBW_EINVAL, "invalid source list");
+    if (!std::isfinite(amplitude) || !std::isfinite(omega)) return fail(LBW_EINVAL, "non-finite amplitude or omega");
+    lbw_geometry* g = s->g;
+    for (int i = 0; i < n; ++i)
+        if (nodes[i] < 0 || nodes[i] >= g->N) return fail(LBW_EINVAL, "source %d outside the grid", i);
+    // sqrt(g) per (i0, i2) entry, FP64 table plane 7
+    std::vector<double> sg(n > 0 ? (size_t)g->E : 0);
+    if (n > 0)
+        HIP_TRY(hipMemcpyAsync(sg.data(), g->tab64 + 7 * g->E, sizeof(double) * g->E, hipMemcpyDeviceToHost, s->stream),
+                "lbw_set_sources");
+    HIP_TRY(hipStreamSynchronize(s->stream), "lbw_set_sources");
+    const int d = g->dev.dim;
+    const double c2 = g->dev.c2_64;
+    const int64_t n0 = g->dev.n0, plane = n0 * g->dev.n1;
+    std::vector<lbw::SourceEntry> host((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const int64_t node = nodes[i];
+        const double sq = sg[(size_t)(node % n0 + n0 * (node / plane))];
+        lbw::SourceEntry e{};
+        e.f_off = (uint64_t)node;
+        e.N = (uint32_t)g->N;
+        e.q = g->Q;
+        e.counter = 0;
+        e.a0 = amplitude * (1.0 - d * c2) * sq;
+        e.a1 = amplitude * 0.5 * c2 * sq;
+        e.omega = omega;
+        host[(size_t)i] = e;
+    }
+    drop_graphs(s);
+    (void)hipFree(s->d_src);
+    s->d_src = nullptr;
+    s->n_src = 0;
+    if (n > 0) {
+        HIP_TRY(hipMalloc((void**)&s->d_src, sizeof(lbw::SourceEntry) * n), "lbw_set_sources");
+        HIP_TRY(hipMemcpyAsync(s->d_src, host.data(), sizeof(lbw::SourceEntry) * n, hipMemcpyHostToDevice, s->stream),
+                "lbw_set_sources");
+        HIP_TRY(hipStreamSynchronize(s->stream), "lbw_set_sources");
+        s->n_src = n;
+    }
+    return LBW_OK;
+}
+
+int lbw_amplitude(lbw_state_t s, int64_t t0, int64_t t1, double* out) {
+    if (!s || !out) return fail(LBW_EINVAL, "NULL argument");
+    if (s->n_probes < 1) return fail(LBW_EINVAL, "state has no probes");
+    const int64_t rows = s->t < s->t_max ? s->t : s->t_max;
+    if (t0 < 0 || t1 <= t0 || t1 > rows)
+        return fail(LBW_EINVAL, "rows [%lld, %lld) empty or outside [0, %lld)", (long long)t0, (long long)t1,
+                    (long long)rows);
+    if (!s->d_amp) HIP_TRY(hipMalloc((void**)&s->d_amp, sizeof(double) * s->n_probes), "lbw_amplitude");
+    HIP_TRY(lbw::launch_amplitude(s->trace, s->n_probes, s->n_probes, t0, t1, s->d_amp, s->stream), "lbw_amplitude");
+    HIP_TRY(hipMemcpyAsync(out, s->d_amp, sizeof(double) * s->n_probes, hipMemcpyDeviceToHost, s->stream),
+            "lbw_amplitude");
+    HIP_TRY(hipStreamSynchronize(s->stream), "lbw_amplitude");
+    for (int p = 0; p < s->n_probes; ++p)
+        if (!std::isfinite(out[p])) return fail(LBW_EUNSTABLE, "non-finite value at probe %d", p);
+    return LBW_OK;
+}
+
 int lbw_state_info(lbw_state_t s, int64_t* t, float** f_current) {
     if (!s) return fail(LBW_EINVAL, "state is NULL");
     if (t) *t = s->t;
@@ -566,6 +634,8 @@ int lbw_free_state(lbw_state_t s) {
     (void)hipFree(s->d_scratch_count);
     (void)hipFree(s->d_tcount);
     (void)hipFree(s->d_probes);
+    (void)hipFree(s->d_src);
+    (void)hipFree(s->d_amp);
     (void)hipFree(s->mode_work);
     (void)hipFree(s->mode_out);
     delete s;

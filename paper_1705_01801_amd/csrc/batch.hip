@@ -1,5 +1,6 @@
 // C-ABI for batches of D3Q7 geometries advanced by one launch per step.
 #include <cmath>
+#include <map>
 #include <vector>
 
 #include "host_util.h"
@@ -34,6 +35,9 @@ struct lbw_batch {
     size_t mode_work_bytes = 0;
     double* mode_out = nullptr;
     int mode_k = 0;
+    lbw::SourceEntry* d_src = nullptr;  // driven sources, imposed before every step
+    int n_src = 0;
+    double* d_amp = nullptr;            // response intensities (P)
 };
 
 namespace {
@@ -49,6 +53,8 @@ void release(lbw_batch* b) {
     (void)hipFree(b->d_scratch_count);
     (void)hipFree(b->mode_work);
     (void)hipFree(b->mode_out);
+    (void)hipFree(b->d_src);
+    (void)hipFree(b->d_amp);
     delete b;
 }
 
@@ -111,6 +117,10 @@ lbw::BatchProbeArgs probe_args(lbw_batch* b, bool record) {
 }
 
 hipError_t launch_batch(lbw_batch* b, const lbw::BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st) {
+    if (b->n_src > 0 && bp.tcount == b->d_tcount) {
+        const hipError_t e = lbw::launch_sources(b->d_src, b->n_src, b->d_tcount, const_cast<float*>(fin), st);
+        if (e != hipSuccess) return e;
+    }
     return lbw::launch_step_batch(b->d_items, b->n, b->tiles, b->tx, b->blocks, bp, fin, fout, st);
 }
 
@@ -472,6 +482,79 @@ int lbw_batch_modes(lbw_batch_t b, int k, double* freq_out, double* power_out) {
         HIP_TRY(hipMemcpyAsync(power_out, pw, sizeof(double) * k * b->n, hipMemcpyDeviceToHost, b->stream),
                 "lbw_batch_modes");
     HIP_TRY(hipStreamSynchronize(b->stream), "lbw_batch_modes");
+    return LBW_OK;
+}
+
+int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* geom, const double* amplitude,
+                          const double* omega, int n) {
+    if (!b) return fail(LBW_EINVAL, "batch is NULL");
+    if (n < 0 || (n > 0 && (!nodes || !geom || !amplitude || !omega))) return fail(LBW_EINVAL, "invalid source list");
+    for (int i = 0; i < n; ++i) {
+        if (geom[i] < 0 || geom[i] >= b->n) return fail(LBW_EINVAL, "source %d: geometry out of range", i);
+        const int64_t N = b->node_off[geom[i] + 1] - b->node_off[geom[i]];
+        if (nodes[i] < 0 || nodes[i] >= N) return fail(LBW_EINVAL, "source %d outside its geometry", i);
+        if (!std::isfinite(amplitude[i]) || !std::isfinite(omega[i]))
+            return fail(LBW_EINVAL, "source %d: non-finite amplitude or omega", i);
+    }
+    // sqrt(g) planes (table plane 7) of the geometries that carry sources
+    std::map<int, std::vector<double>> sg;
+    for (int i = 0; i < n; ++i) {
+        const int h = geom[i];
+        if (sg.count(h)) continue;
+        const int64_t E = b->rec_off[h + 1] - b->rec_off[h];
+        std::vector<double>& v = sg[h];
+        v.resize((size_t)E);
+        HIP_TRY(hipMemcpyAsync(v.data(), b->tab64 + b->tab64_off[h] + 7 * E, sizeof(double) * E,
+                               hipMemcpyDeviceToHost, b->stream),
+                "lbw_batch_set_sources");
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream), "lbw_batch_set_sources");
+    std::vector<lbw::SourceEntry> host((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const int h = geom[i];
+        const lbw_geometry_desc& d = b->d[h];
+        const int64_t n0 = d.n[0], plane = n0 * d.n[1];
+        const int64_t N = b->node_off[h + 1] - b->node_off[h];
+        const double sq = sg[h][(size_t)(nodes[i] % n0 + n0 * (nodes[i] / plane))];
+        const double c2 = d.c * d.c;
+        lbw::SourceEntry e{};
+        e.f_off = (uint64_t)(7 * b->node_off[h] + nodes[i]);
+        e.N = (uint32_t)N;
+        e.q = 7;
+        e.counter = h;
+        e.a0 = amplitude[i] * (1.0 - 3.0 * c2) * sq;
+        e.a1 = amplitude[i] * 0.5 * c2 * sq;
+        e.omega = omega[i];
+        host[(size_t)i] = e;
+    }
+    drop_graphs(b);
+    (void)hipFree(b->d_src);
+    b->d_src = nullptr;
+    b->n_src = 0;
+    if (n > 0) {
+        HIP_TRY(hipMalloc((void**)&b->d_src, sizeof(lbw::SourceEntry) * n), "lbw_batch_set_sources");
+        HIP_TRY(hipMemcpyAsync(b->d_src, host.data(), sizeof(lbw::SourceEntry) * n, hipMemcpyHostToDevice, b->stream),
+                "lbw_batch_set_sources");
+        HIP_TRY(hipStreamSynchronize(b->stream), "lbw_batch_set_sources");
+        b->n_src = n;
+    }
+    return LBW_OK;
+}
+
+int lbw_batch_amplitude(lbw_batch_t b, int64_t t0, int64_t t1, double* out) {
+    if (!b || !out) return fail(LBW_EINVAL, "NULL argument");
+    if (b->P < 1) return fail(LBW_EINVAL, "batch has no probes");
+    const int64_t rows = b->t < b->t_max ? b->t : b->t_max;
+    if (t0 < 0 || t1 <= t0 || t1 > rows)
+        return fail(LBW_EINVAL, "rows [%lld, %lld) empty or outside [0, %lld)", (long long)t0, (long long)t1,
+                    (long long)rows);
+    if (!b->d_amp) HIP_TRY(hipMalloc((void**)&b->d_amp, sizeof(double) * b->P), "lbw_batch_amplitude");
+    HIP_TRY(lbw::launch_amplitude(b->trace, b->P, b->P, t0, t1, b->d_amp, b->stream), "lbw_batch_amplitude");
+    HIP_TRY(hipMemcpyAsync(out, b->d_amp, sizeof(double) * b->P, hipMemcpyDeviceToHost, b->stream),
+            "lbw_batch_amplitude");
+    HIP_TRY(hipStreamSynchronize(b->stream), "lbw_batch_amplitude");
+    for (int64_t p = 0; p < b->P; ++p)
+        if (!std::isfinite(out[p])) return fail(LBW_EUNSTABLE, "non-finite value at probe %lld", (long long)p);
     return LBW_OK;
 }
 

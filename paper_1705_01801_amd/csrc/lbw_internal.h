@@ -106,6 +106,23 @@ int batch_blocks_per_cu(int tx);
 hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int blocks,
                              const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st);
 
+// One driven node (Sec. IV.A/IV.C sources): its populations sit at
+// f[f_off + l N], l < q; a0 = amplitude w_0 sqrt(g), a1 = amplitude w sqrt(g);
+// the time is counters[counter].
+struct SourceEntry {
+    uint64_t f_off;
+    uint32_t N;
+    int32_t q;
+    int32_t counter;
+    int32_t pad;
+    double a0, a1, omega;
+};
+// Imposes every source at its current time (before the step that reads f).
+hipError_t launch_sources(const SourceEntry* src, int n, const int64_t* counters, float* f, hipStream_t st);
+// out[c] = max over rows [t0, t1) of |trace[t * stride + c]|, c < cols (NaN if any is NaN).
+hipError_t launch_amplitude(const double* trace, int64_t stride, int64_t cols, int64_t t0, int64_t t1, double* out,
+                            hipStream_t st);
+
 // Spectra of probe groups (consecutive trace columns, one group per
 // geometry): fills freq/power (device, groups * k each) from trace rows
 // [0, T) of row length `stride`.  Synchronises the stream per chunk.

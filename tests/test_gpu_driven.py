@@ -1,0 +1,140 @@
+"""GPU: driven sources and response intensity against the FP64 oracle.
+
+Sources impose amplitude * sin(omega t) at chosen nodes before every step
+(Sec. IV.A and IV.C ring and point sources); the intensity is the largest
+|P| per probe over a late window (the frequency sweeps).  The HIP path
+keeps populations in FP32, so fields and traces are compared with the field
+tolerance of the undriven parity tests (relative L2 1e-5); a probe on a
+source node must read the imposed value to FP32 rounding; a batch of copies
+driven at different frequencies must match each copy driven alone bit for
+bit (same per-node arithmetic, same source kernel), and graph replay must
+match step-by-step launches.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1705_01801_amd as lbw
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cyl():
+    geom = W.closed_cylinder(scale=16, c=0.35)      # 8 x 8 x 16, sqrt(g) = r varies
+    n0, n1 = geom["n"][0], geom["n"][1]
+    ring = [0 + n0 * (i1 + n1 * 0) for i1 in range(n1)]
+    src = ring + [5 + n0 * (3 + n1 * 7)]
+    probes = [ring[2], src[-1], 4 + n0 * (6 + n1 * 12), 7 + n0 * (1 + n1 * 15)]
+    return dict(geom, damp=0.65), src, probes
+
+
+@pytest.mark.parametrize("case", ["cylinder", "polar2d"])
+def test_driven_run_matches_oracle(case):
+    if case == "cylinder":
+        geom, src, probes = cyl()
+    else:
+        geom = dict(W.polar_disk(scale=4), damp=0.65)  # 16 x 16, D2Q5 kernel
+        n0 = geom["n"][0]
+        src = [0 + n0 * i1 for i1 in range(geom["n"][1])]
+        probes = [src[3], 9 + n0 * 4, 14 + n0 * 11]
+    C, w, T = 0.8, 0.07, 300
+    say("driven", case, W.shape_of(geom), "sources", len(src), "steps", T)
+    o = oracle.Oracle(geom)
+    f = o.init(np.zeros(o.N))
+    _, tr_o = o.run(f, T, probes, sources=src, amplitude=C, omega=w)
+    sim = lbw.Simulation(lbw.Geometry(geom), np.zeros(o.N), probes, t_max=T)
+    sim.set_sources(src, C, w)
+    sim.step(T)                                       # graph blocks of 32 plus single launches
+    fg = sim.populations().double().cpu().numpy()
+    assert rel_l2(fg, f) <= 1e-5
+    tr = sim.probe()
+    assert np.abs(tr - tr_o).max() <= 1e-5 * np.abs(tr_o).max()
+    # the source probe reads the imposed pressure (FP32 populations)
+    assert np.abs(tr[:, 0] - C * np.sin(w * np.arange(T))).max() <= 2e-6 * C
+    a = sim.amplitude(T - 100, T)
+    assert np.abs(a - o.amplitude(tr_o, T - 100, T)).max() <= 1e-5 * a.max()
+    assert np.array_equal(a, np.abs(tr[T - 100:]).max(axis=0))
+
+
+def test_sources_graph_replay_and_removal():
+    geom, src, probes = cyl()
+    T = 150
+    out = []
+    for block in (0, 16):
+        sim = lbw.Simulation(lbw.Geometry(geom), np.zeros(W.num_nodes(geom)), probes, t_max=2 * T)
+        sim.set_graph_block(block)
+        sim.set_sources(src, 1.0, 0.11)
+        sim.step(T)
+        sim.set_sources([], 0.0, 0.0)                 # then free ringing
+        sim.step(T)
+        out.append((sim.populations().cpu().numpy(), sim.probe()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    o = oracle.Oracle(geom)
+    f = o.init(np.zeros(o.N))
+    _, t1 = o.run(f, T, probes, sources=src, amplitude=1.0, omega=0.11)
+    _, t2 = o.run(f, T, probes, t0=T)
+    ref = np.vstack([t1, t2])
+    assert np.abs(out[0][1] - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_batch_sweep_matches_single_runs():
+    geom, src, probes = cyl()
+    omegas = [0.02, 0.05, 0.09, 0.13]
+    T = 200
+    n = len(omegas) + 1                               # the last copy is not driven
+    N = W.num_nodes(geom)
+    say("driven batch of", n)
+    b = lbw.Batch([geom] * n, [np.zeros(N)] * n, [probes] * n, t_max=T)
+    b.set_graph_block(16)
+    nodes = np.concatenate([src] * len(omegas))
+    which = np.repeat(np.arange(len(omegas)), len(src))
+    b.set_sources(nodes, which, 0.6, np.repeat(omegas, len(src)))
+    b.step(T)
+    trace = b.probe()
+    amp = b.amplitude(T // 2, T)
+    for h in range(n):
+        sim = lbw.Simulation(lbw.Geometry(geom), np.zeros(N), probes, t_max=T)
+        if h < len(omegas):
+            sim.set_sources(src, 0.6, omegas[h])
+        sim.step(T)
+        assert np.array_equal(b.populations(h).cpu().numpy(), sim.populations().cpu().numpy()), h
+        cols = slice(int(b.probe_offsets[h]), int(b.probe_offsets[h + 1]))
+        assert np.array_equal(trace[:, cols], sim.probe()), h
+        assert np.array_equal(amp[cols], np.abs(sim.probe()[T // 2:]).max(axis=0)), h
+    assert not trace[:, -len(probes):].any()          # the undriven copy stays at rest
+
+
+def test_source_errors():
+    geom, src, probes = cyl()
+    N = W.num_nodes(geom)
+    sim = lbw.Simulation(lbw.Geometry(geom), np.zeros(N), probes, t_max=10)
+    with pytest.raises(lbw.LbwError):
+        sim.set_sources([N], 1.0, 0.1)
+    with pytest.raises(lbw.LbwError):
+        sim.set_sources([-1], 1.0, 0.1)
+    with pytest.raises(lbw.LbwError):
+        sim.set_sources([0], float("nan"), 0.1)
+    with pytest.raises(lbw.LbwError):
+        sim.amplitude(0, 1)                          # nothing recorded yet
+    sim.step(4)
+    with pytest.raises(lbw.LbwError):
+        sim.amplitude(2, 2)
+    with pytest.raises(lbw.LbwError):
+        sim.amplitude(0, 5)
+    b = lbw.Batch([geom] * 2, [np.zeros(N)] * 2, [probes] * 2, t_max=10)
+    with pytest.raises(lbw.LbwError):
+        b.set_sources([0], [2], 1.0, 0.1)
+    with pytest.raises(lbw.LbwError):
+        b.set_sources([N], [1], 1.0, 0.1)
