@@ -1,0 +1,168 @@
+"""Frequency sweep of the driven pipe (the ring-source experiment of
+Sec. IV.A): every drive frequency is one copy of the pipe in one batch, all
+advanced together; the response intensity at a probe is plotted against the
+drive frequency and its peaks are compared with the pipe's resonances.
+
+    python -m paper_1705_01801_amd.sweep_study --out gpurun_out/sweep.json
+
+Closed form used for the comparison: axisymmetric modes of the annulus
+r in [1, 25] with reflecting (zero normal derivative) walls have radial
+wavenumbers zeta_j (zeta_0 = 0 and the roots of
+J_1(zeta a) Y_1(zeta b) - J_1(zeta b) Y_1(zeta a)); a pipe closed at z = 0 and
+open at z = L has axial wavenumbers (2n + 1) pi / (2L), one closed at both
+ends n pi / L; omega = c sqrt(zeta_j^2 + k_z^2).  Every numerical step of the
+sweep runs in the HIP library; this script only sets it up and reads back
+the intensities.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+import workloads as W
+
+from . import Batch, Simulation, Geometry
+
+
+def radial_wavenumbers(a: float, b: float, kmax: float) -> list:
+    from scipy.optimize import brentq
+    from scipy.special import j1, y1
+
+    def f(z):
+        return j1(z * a) * y1(z * b) - j1(z * b) * y1(z * a)
+
+    roots = [0.0]
+    zs = np.linspace(1e-4, kmax, 4000)
+    v = f(zs)
+    for i in range(len(zs) - 1):
+        if np.sign(v[i]) != np.sign(v[i + 1]):
+            roots.append(brentq(f, zs[i], zs[i + 1]))
+    return roots
+
+
+def resonances(c: float, L: float, a: float, b: float, wmax: float, closed_open: bool) -> list:
+    out = []
+    for zeta in radial_wavenumbers(a, b, wmax / c):
+        for n in range(0, 200):
+            kz = (2 * n + 1) * math.pi / (2 * L) if closed_open else n * math.pi / L
+            w = c * math.hypot(zeta, kz)
+            if w > wmax:
+                break
+            if w > 0:
+                out.append(w)
+    return sorted(out)
+
+
+def peaks(omega: np.ndarray, amp: np.ndarray, rel: float = 0.02) -> list:
+    """Local maxima above rel * max, refined by a parabola through the three
+    samples around each."""
+    out = []
+    top = amp.max()
+    for i in range(1, len(amp) - 1):
+        if amp[i] > amp[i - 1] and amp[i] >= amp[i + 1] and amp[i] > rel * top:
+            y0, y1, y2 = amp[i - 1], amp[i], amp[i + 1]
+            d = 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)
+            out.append(float(omega[i] + d * (omega[1] - omega[0])))
+    return out
+
+
+def match(expected: list, found: list, tol: float):
+    """Nearest found peak per expected resonance within tol (absolute)."""
+    rows = []
+    for w in expected:
+        if not found:
+            break
+        j = int(np.argmin([abs(p - w) for p in found]))
+        if abs(found[j] - w) <= tol:
+            rows.append((w, found[j], found[j] / w - 1))
+    return rows
+
+
+def main():
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--points", type=int, default=119)
+    ap.add_argument("--steps", type=int, default=W.PIPE_STEPS)
+    ap.add_argument("--plain", type=int, default=4, help="sweep points also run one at a time")
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    torch.cuda.set_device(0)
+    omegas = W.sweep_omegas(args.points)
+    ends = ("fixed", "free")
+    geoms = [W.driven_pipe(e) for e in ends for _ in omegas]
+    N = W.num_nodes(geoms[0])
+    ring, probes = W.pipe_ring(geoms[0]), W.pipe_probes(geoms[0])
+    T = int(args.steps)
+    b = Batch(geoms, [np.zeros(N)] * len(geoms), [probes] * len(geoms), t_max=T)
+    nodes = np.concatenate([ring] * len(geoms))
+    which = np.repeat(np.arange(len(geoms)), len(ring))
+    om = np.repeat(np.tile(omegas, len(ends)), len(ring))
+    b.set_sources(nodes, which, 1.0, om)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(T)
+    torch.cuda.synchronize()
+    t_step = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    amp = b.amplitude(T // 2, T).reshape(len(ends), len(omegas), len(probes))
+    t_amp = time.perf_counter() - t1
+    rep = {"workload": "driven pipe 20x5x100 (r, theta, z), ring source, c %.2f, damping %.2f" % (W.PIPE_C, W.PIPE_DAMP),
+           "points": len(geoms), "omegas": [float(omegas[0]), float(omegas[-1]), len(omegas)], "steps": T,
+           "nodes": int(N * len(geoms)),
+           "batched": {"seconds": t_step + t_amp, "step_seconds": t_step,
+                       "points_per_s": len(geoms) / (t_step + t_amp),
+                       "glups": N * len(geoms) * T / t_step / 1e9}}
+    # a few points one at a time (same graph-replayed single-geometry path)
+    if args.plain > 0:
+        idx = np.linspace(0, len(omegas) - 1, args.plain).astype(int)
+        same = True
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in idx:
+            sim = Simulation(Geometry(geoms[i]), np.zeros(N), probes, t_max=T)
+            sim.set_sources(ring, 1.0, float(omegas[i]))
+            sim.step(T)
+            a = sim.amplitude(T // 2, T)
+            same = same and bool(np.array_equal(a, amp[0, i]))
+            sim.close()
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        rep["plain"] = {"points": len(idx), "seconds": tp, "points_per_s": len(idx) / tp,
+                        "identical_to_batched": same}
+        rep["batched_vs_plain"] = rep["batched"]["points_per_s"] / rep["plain"]["points_per_s"]
+    geom = geoms[0]
+    a_in, b_out = geom["qmin"][0], geom["qmax"][0]
+    L = geom["qmax"][2]
+    # compared: the plane-wave band below the first radial cutoff, where the
+    # resonances are pi c / L apart and a peak within 0.4 of that spacing is
+    # unambiguous; above it both families interleave
+    cutoff = W.PIPE_C * radial_wavenumbers(a_in, b_out, 1.0)[1]
+    wmax = min(float(omegas[-1]), cutoff)
+    tol = 0.4 * math.pi * W.PIPE_C / L
+    rep["compared_band"] = [float(omegas[0]), wmax]
+    rep["response"] = {}
+    for e, end in enumerate(ends):
+        found = peaks(omegas, amp[e, :, 0])
+        res = {"peaks": found}
+        for label, co in (("closed_open", True), ("closed_closed", False)):
+            exp = resonances(W.PIPE_C, L, a_in, b_out, wmax, co)
+            m = match(exp, found, tol)
+            res[label] = {"expected": exp, "matched": len(m),
+                          "rms_rel": float(np.sqrt(np.mean([r[2] ** 2 for r in m]))) if m else None,
+                          "max_rel": float(max(abs(r[2]) for r in m)) if m else None,
+                          "pairs": [[r[0], r[1]] for r in m]}
+        res["intensity_probe0"] = amp[e, :, 0].tolist()
+        rep["response"][end] = res
+    line = json.dumps(rep)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -138,3 +138,28 @@ def test_source_errors():
         b.set_sources([0], [2], 1.0, 0.1)
     with pytest.raises(lbw.LbwError):
         b.set_sources([N], [1], 1.0, 0.1)
+
+
+def test_pipe_sweep_point_full_size():
+    """One point of the pipe sweep at its full size and length (8400 steps),
+    batched with two other drive frequencies, against the oracle.  FP32
+    rounding (6e-8 per step) accumulates at most linearly over the run:
+    tolerance 8400 x 6e-8 ~ 5e-4 relative."""
+    geom = W.driven_pipe("fixed")
+    ring, probes = W.pipe_ring(geom), W.pipe_probes(geom)
+    N, T = W.num_nodes(geom), W.PIPE_STEPS
+    omegas = [0.004, 0.00785, 0.0123]
+    say("pipe sweep point, batch of", len(omegas), "steps", T)
+    b = lbw.Batch([geom] * 3, [np.zeros(N)] * 3, [probes] * 3, t_max=T)
+    b.set_sources(np.concatenate([ring] * 3), np.repeat(np.arange(3), len(ring)), 1.0,
+                  np.repeat(omegas, len(ring)))
+    b.step(T)
+    amp = b.amplitude(T // 2, T).reshape(3, len(probes))
+    tr = b.probe()[:, len(probes):2 * len(probes)]
+    o = oracle.Oracle(geom)
+    f = o.init(np.zeros(o.N))
+    _, tr_o = o.run(f, T, probes, sources=ring, amplitude=1.0, omega=omegas[1])
+    assert np.abs(tr - tr_o).max() <= 5e-4 * np.abs(tr_o).max()
+    a_o = o.amplitude(tr_o, T // 2, T)
+    assert np.abs(amp[1] - a_o).max() <= 5e-4 * a_o.max()
+    assert rel_l2(b.populations(1).double().cpu().numpy(), f) <= 5e-4

@@ -360,3 +360,42 @@ def candidates(n: int = 100000):
     with."""
     rng = np.random.default_rng(SEED_BASE + 4 + 104729)
     return horn_profiles(n, rng), horn_grids(n, rng)
+
+
+# ---------------------------------------------------------------------------
+# driven pipe (frequency sweep of the pipe experiment, Sec. IV.A)
+# ---------------------------------------------------------------------------
+
+PIPE_C = 0.1            # lattice wave speed of the sweep
+PIPE_DAMP = 0.65        # damping of the reflecting walls
+PIPE_STEPS = 8400       # steps per sweep point (steady oscillation)
+
+
+def driven_pipe(open_end: str = "fixed") -> dict:
+    """Pipe of the ring-source sweep: (r, theta, z) with 20 x 5 x 100 cells,
+    r in [1, 25], z in [0, 100] (one lattice unit per axial cell), reflecting
+    walls with damping 0.65 at r = 1, r = 25 and the closed end z = 0; the
+    open end z = 100 is a fixed (P = 0) wall or, as in the paper, a free
+    (copy) wall.  The paper's free wall at r = 1 is replaced by a reflecting
+    one: with the free rule the axisymmetric field of this grid grows."""
+    return dict(kind="cylinder", dim=3, n=(20, 5, 100), qmin=(1.0, 0.0, 0.0), qmax=(25.0, TWO_PI, 100.0),
+                bc_lo=("bounceback", "periodic", "bounceback"), bc_hi=("bounceback", "periodic", open_end),
+                h_ref=1.0, c=PIPE_C, damp=PIPE_DAMP, params=())
+
+
+def pipe_ring(geom) -> np.ndarray:
+    """Source nodes: the ring at the inner radius in the closed-end plane."""
+    n0, n1 = geom["n"][0], geom["n"][1]
+    return np.array([n0 * i1 for i1 in range(n1)], dtype=np.int64)
+
+
+def pipe_probes(geom) -> np.ndarray:
+    """Probes: r = 2.8, z = 10.5 (the paper's r = 3, z = z_max / 10) and the
+    pipe's mid-length at the same radius."""
+    n0, n1 = geom["n"][0], geom["n"][1]
+    return np.array([1 + n0 * n1 * 10, 1 + n0 * n1 * 50], dtype=np.int64)
+
+
+def sweep_omegas(n: int = 119, lo: float = 0.0005, hi: float = 0.03) -> np.ndarray:
+    """Drive frequencies of the sweep, radians per step."""
+    return np.linspace(lo, hi, n)
