@@ -94,6 +94,22 @@ def spectra_leg(n_horns, n_plain=4):
                     "paper_1705_01801_amd.surrogate_study), which trains the surrogate first"}
 
 
+def sweep_leg(points):
+    """Driven-pipe frequency sweep (ring source, Sec. IV.A): sweep points per
+    second with every drive frequency a copy in one batch, against two
+    points run one at a time; 8400 steps per point."""
+    from paper_1705_01801_amd import sweep_study
+    log("bench: sweep leg, %d drive frequencies batched" % points)
+    r = sweep_study.run(points=points, plain=2, ends=("fixed",))
+    m = r["response"]["fixed"]["closed_open"]
+    return {"unit": "sweep points/s", "batched": round(r["batched"]["points_per_s"], 2),
+            "plain": round(r["plain"]["points_per_s"], 3), "batched_vs_plain": round(r["batched_vs_plain"], 1),
+            "points": r["points"], "steps": r["steps"], "nodes": r["nodes"], "glups": round(r["batched"]["glups"], 2),
+            "identical_to_plain": r["plain"]["identical_to_batched"],
+            "closed_open_peaks_matched": m["matched"], "closed_open_rms_rel": m["rms_rel"],
+            "workload": r["workload"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +124,8 @@ def main():
                          "3 torus 96x256x512")
     ap.add_argument("--spectra-horns", type=int, default=64,
                     help="horns in the batched-vs-plain spectra leg (0 skips it)")
+    ap.add_argument("--sweep-points", type=int, default=119,
+                    help="drive frequencies in the driven-pipe sweep leg (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this build", file=sys.stderr)
@@ -176,6 +194,8 @@ def main():
     }
     if args.spectra_horns > 0:
         out["spectra"] = spectra_leg(args.spectra_horns)
+    if args.sweep_points > 0:
+        out["sweep"] = sweep_leg(args.sweep_points)
     if not args.no_cpu_baseline:
         log("bench: oracle baseline, %d steps" % args.cpu_steps)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

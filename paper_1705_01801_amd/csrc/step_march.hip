@@ -114,7 +114,7 @@ __device__ inline float bounce(int wall, float damp, float out_l, float own_lb) 
 
 // One tile of one geometry: columns [x0, x0 + TX) x [y0, y0 + TY), planes
 // [z0, z0 + lz).  fin/fout point at the geometry's own population block.
-template <int TX, int NT>
+template <int TX, int NT, bool ROW>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
                                            float* __restrict__ fout, float (&sS)[2][(NT / TX + 2) * (TX + 2) + 1],
                                            float4 (&sElo)[3][TX + 3], float4 (&sEhi)[3][TX + 3]) {
@@ -143,8 +143,9 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
         const uint32_t col = (uint32_t)x + (uint32_t)n0 * (uint32_t)y;
         // the tile holds whole walled axis-0 rows: the axis-0 populations
         // reach their destinations by a lane shift, so each lane stores its
-        // own node's (aligned stores instead of stores shifted by one float)
-        const bool row_tile = x0 == 0 && wdt == n0 && g.bc_lo[0] != LBW_BC_PERIODIC;
+        // own node's (aligned stores instead of stores shifted by one float);
+        // ROW = false compiles the shift out (grids wider than a tile)
+        const bool row_tile = ROW && x0 == 0 && wdt == n0 && g.bc_lo[0] != LBW_BC_PERIODIC;
 
         int wx_p = 0, wx_m = 0, wy_p = 0, wy_m = 0;
         const int jx_p = link_coord(x, +1, n0, g.bc_lo[0], g.bc_hi[0], &wx_p);
@@ -345,7 +346,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             const uint32_t o6 = jz_m >= 0 ? 6u * N4 + col4 + (uint32_t)jz_m * plane4 : 5u * N4 + nb;
             float v1 = jx_p >= 0 ? fs[1] : bounce(wx_p, damp, fs[1], fs[2]);
             float v2 = jx_m >= 0 ? fs[2] : bounce(wx_m, damp, fs[2], fs[1]);
-            {
+            if constexpr (ROW) {
                 // whole-row tile: population 1 of this node comes from the
                 // lane on the left (or the wall at x = 0), population 2 from
                 // the lane on the right (or the wall at x = n0 - 1)
@@ -393,7 +394,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
     }
 }
 
-template <int TX, int NT>
+template <int TX, int NT, bool ROW>
 __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
     const int t_begin = (int)(plan.tiles * xcd / kXcds);
     const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
     for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
-        march_tile<TX, NT>(tg, tile, fin, fout, sS, sElo, sEhi);
+        march_tile<TX, NT, ROW>(tg, tile, fin, fout, sS, sElo, sEhi);
 }
 
 // Batch of geometries advanced by one launch: tiles of all geometries form
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(kBatchThreads) void step_batch_kernel(const BatchIt
         tg.ntx = it.ntx;
         tg.nty = it.nty;
         tg.lz = it.lz;
-        march_tile<TX, kBatchThreads>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sElo, sEhi);
+        march_tile<TX, kBatchThreads, true>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sElo, sEhi);
     }
 }
 
@@ -505,13 +506,19 @@ namespace {
 template <int TX, int NT>
 int blocks_per_cu_of() {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<TX, NT>, NT, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<TX, NT, false>, NT, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 template <int TX, int NT>
 void launch_of(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin, float* fout,
                hipStream_t st) {
-    hipLaunchKernelGGL((step_march_kernel<TX, NT>), dim3(plan.blocks), dim3(NT), 0, st, g, pr, plan, fin, fout);
+    // whole walled rows fit one tile: the variant with the axis-0 lane shift
+    if (g.n0 <= TX && g.bc_lo[0] != LBW_BC_PERIODIC)
+        hipLaunchKernelGGL((step_march_kernel<TX, NT, true>), dim3(plan.blocks), dim3(NT), 0, st, g, pr, plan, fin,
+                           fout);
+    else
+        hipLaunchKernelGGL((step_march_kernel<TX, NT, false>), dim3(plan.blocks), dim3(NT), 0, st, g, pr, plan, fin,
+                           fout);
 }
 }  // namespace
 

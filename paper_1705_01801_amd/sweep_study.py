@@ -82,21 +82,15 @@ def match(expected: list, found: list, tol: float):
     return rows
 
 
-def main():
+def run(points: int = 119, steps: int = W.PIPE_STEPS, plain: int = 4, ends=("fixed", "free")) -> dict:
+    """The sweep: one batch with a copy of the pipe per (open end, drive
+    frequency); returns the measurements and the peak comparison."""
     import torch
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--points", type=int, default=119)
-    ap.add_argument("--steps", type=int, default=W.PIPE_STEPS)
-    ap.add_argument("--plain", type=int, default=4, help="sweep points also run one at a time")
-    ap.add_argument("--out", default=None)
-    args = ap.parse_args()
-    torch.cuda.set_device(0)
-    omegas = W.sweep_omegas(args.points)
-    ends = ("fixed", "free")
+    omegas = W.sweep_omegas(points)
     geoms = [W.driven_pipe(e) for e in ends for _ in omegas]
     N = W.num_nodes(geoms[0])
     ring, probes = W.pipe_ring(geoms[0]), W.pipe_probes(geoms[0])
-    T = int(args.steps)
+    T = int(steps)
     b = Batch(geoms, [np.zeros(N)] * len(geoms), [probes] * len(geoms), t_max=T)
     nodes = np.concatenate([ring] * len(geoms))
     which = np.repeat(np.arange(len(geoms)), len(ring))
@@ -117,8 +111,8 @@ def main():
                        "points_per_s": len(geoms) / (t_step + t_amp),
                        "glups": N * len(geoms) * T / t_step / 1e9}}
     # a few points one at a time (same graph-replayed single-geometry path)
-    if args.plain > 0:
-        idx = np.linspace(0, len(omegas) - 1, args.plain).astype(int)
+    if plain > 0:
+        idx = np.linspace(0, len(omegas) - 1, plain).astype(int)
         same = True
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -157,6 +151,20 @@ def main():
                           "pairs": [[r[0], r[1]] for r in m]}
         res["intensity_probe0"] = amp[e, :, 0].tolist()
         rep["response"][end] = res
+    b.close()
+    return rep
+
+
+def main():
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--points", type=int, default=119)
+    ap.add_argument("--steps", type=int, default=W.PIPE_STEPS)
+    ap.add_argument("--plain", type=int, default=4, help="sweep points also run one at a time")
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    torch.cuda.set_device(0)
+    rep = run(args.points, args.steps, args.plain)
     line = json.dumps(rep)
     print(line, flush=True)
     if args.out:
