@@ -163,3 +163,21 @@ def test_pipe_sweep_point_full_size():
     a_o = o.amplitude(tr_o, T // 2, T)
     assert np.abs(amp[1] - a_o).max() <= 5e-4 * a_o.max()
     assert rel_l2(b.populations(1).double().cpu().numpy(), f) <= 5e-4
+
+
+def test_radial_wave_matches_oracle():
+    """The radial wave of the oracle pin (polar grid 199 x 4, ring drive,
+    400 steps) through the 2-D kernel."""
+    import math
+    n0, nth = 199, 4
+    geom = dict(kind="polar2d", dim=2, n=(n0, nth), qmin=(1.0, 0.0), qmax=(1.0 + n0, 2 * math.pi),
+                bc_lo=("bounceback", "periodic"), bc_hi=("bounceback", "periodic"), h_ref=1.0, c=0.5, damp=1.0,
+                params=())
+    src = [n0 * i for i in range(nth)]
+    o = oracle.Oracle(geom)
+    f = o.init(np.zeros(o.N))
+    o.run(f, 400, [], sources=src, amplitude=1.0, omega=0.075)
+    sim = lbw.Simulation(lbw.Geometry(geom), np.zeros(o.N), [5, 50], t_max=400)
+    sim.set_sources(src, 1.0, 0.075)
+    sim.step(400)
+    assert rel_l2(sim.populations().double().cpu().numpy(), f) <= 1e-5

@@ -24,7 +24,11 @@ run (the pipe and torus frequency sweeps).  Pins:
   steps for the frequencies below), against a deviation of order omega for a
   drive applied one step early or late;
 * the intensity rule on the steady sinusoid: within |Z| (1 - omega^2 / 8)
-  (integer-time sampling of the crest) and |Z| plus that residual.
+  (integer-time sampling of the crest) and |Z| plus that residual;
+* the radial wave from a driven ring on the polar grid has the radial
+  profile of the outgoing cylindrical wave H0(2)(k r) (closed form, one
+  fitted complex amplitude), which pins the curvature force of the radial
+  operator under a drive.
 """
 import math
 
@@ -130,3 +134,36 @@ def test_driven_line_reaches_exact_steady_state(omega):
     amp = o.amplitude(tr, T - win, T)
     assert np.all(amp >= np.abs(Z) * (1.0 - omega * omega / 8.0) - resid * np.abs(Z) - 1e-12)
     assert np.all(amp <= np.abs(Z) * (1.0 + resid) + 1e-12)
+
+
+def test_radial_wave_follows_outgoing_hankel_profile():
+    """Radial wave from a driven ring (Sec. IV.A, the cylindrical wave from the
+    axis): on the polar grid the field behind the front must have the radial
+    profile of the outgoing solution Im[alpha H0(2)(k r) e^{i omega t}], with k
+    from the lattice dispersion sin(omega/2) = c sin(k h/2) along r
+    (Mhat^rr = 0) and one complex alpha fitted: how strongly a driven node
+    couples to the field is a property of the lattice, not of the continuum.
+    The residual is the switch-on transient (0.3 % here, shrinking with the run
+    length); the Christoffel force with the wrong sign (reading A5) gives 71 %."""
+    from scipy.special import hankel2
+    h, c, nth = 1.0, 0.5, 4
+    n0 = 199
+    geom = dict(kind="polar2d", dim=2, n=(n0, nth), qmin=(1.0, 0.0), qmax=(1.0 + n0 * h, 2 * math.pi),
+                bc_lo=("bounceback", "periodic"), bc_hi=("bounceback", "periodic"), h_ref=h, c=c, damp=1.0,
+                params=())
+    o = oracle.Oracle(geom)
+    w, T = 0.075, 400
+    f = o.init(np.zeros(o.N))
+    o.run(f, T, [], sources=[n0 * i for i in range(nth)], amplitude=1.0, omega=w)
+    P = o.pressure(f).reshape(nth, n0)
+    assert np.abs(P - P[0]).max() <= 1e-12 * np.abs(P).max()   # stays axisymmetric
+    r = 1.0 + (np.arange(n0) + 0.5) * h
+    k = 2.0 * math.asin(math.sin(w / 2.0) / c) / h
+    E = hankel2(0, k * r) / hankel2(0, k * r[0]) * np.exp(1j * w * T)
+    sel = (r >= 5.0) & (r <= 60.0)                            # front near r = 190
+    A = np.stack([np.imag(E[sel]), np.real(E[sel])], axis=1)
+    coef, *_ = np.linalg.lstsq(A, P[0, sel], rcond=None)
+    fit = A @ coef
+    resid = np.sqrt(np.mean((P[0, sel] - fit) ** 2) / np.mean(fit ** 2))
+    assert resid <= 0.01, resid
+    assert 0.1 < math.hypot(*coef) < 1.0
