@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbw_oracle.c")
 _LIB = os.path.join(_HERE, "liblbw_oracle.so")
 
-KINDS = {"box": 0, "polar2d": 1, "cylinder": 2, "horn": 3, "torus": 4, "bessel_horn": 5}
+KINDS = {"box": 0, "polar2d": 1, "cylinder": 2, "horn": 3, "torus": 4, "bessel_horn": 5, "general": 6}
 BCS = {"periodic": 0, "bounceback": 1, "free": 2, "fixed": 3}
 
 
@@ -64,6 +64,7 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         gp = ctypes.POINTER(_Geom)
         lib.orc_coeffs.argtypes = [gp, dp, dp, dp]
+        lib.orc_coeffs_given.argtypes = [gp, dp, dp, dp, dp]
         lib.orc_maps.argtypes = [gp, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)]
         lib.orc_init.argtypes = [gp, dp, dp, dp]
         lib.orc_step.argtypes = [gp, dp, dp, dp, dp, dp]
@@ -124,7 +125,13 @@ class Oracle:
         self.sqrtg = np.zeros(self.N)
         self.Mhat = np.zeros((6, self.N))
         self.Gamh = np.zeros((3, self.N))
-        self.lib.orc_coeffs(ctypes.byref(self._g), _ptr(self.sqrtg), _ptr(self.Mhat), _ptr(self.Gamh))
+        if geom["kind"] == "general":
+            # a geometry given by its metric: per-node sqrt(g), G^{ij}, Gamma^i
+            given = np.ascontiguousarray(geom["coeffs"], dtype=np.float64).reshape(10, self.N)
+            self.lib.orc_coeffs_given(ctypes.byref(self._g), _ptr(given), _ptr(self.sqrtg), _ptr(self.Mhat),
+                                      _ptr(self.Gamh))
+        else:
+            self.lib.orc_coeffs(ctypes.byref(self._g), _ptr(self.sqrtg), _ptr(self.Mhat), _ptr(self.Gamh))
         self._work = None
 
     # -- index maps ---------------------------------------------------------

@@ -250,6 +250,32 @@ int orc_coeffs(const orc_geom* g, double* sqrtg, double* Mhat, double* Gamh) {
     return 0;
 }
 
+/* The same lattice-unit coefficients from given per-node metric data (a
+ * geometry described only by its metric, Sec. III: the scheme needs sqrt(g),
+ * the inverse metric and the contracted Christoffel symbols).  given holds
+ * 10 planes of N values in the coordinates' own units: sqrt(g), G00, G11,
+ * G22, G01, G02, G12, Gc0, Gc1, Gc2. */
+int orc_coeffs_given(const orc_geom* g, const double* given, double* sqrtg, double* Mhat, double* Gamh) {
+    int d = g->dim;
+    int64_t N = orc_nodes(g);
+    double h[3] = {1.0, 1.0, 1.0};
+    for (int a = 0; a < d; ++a) h[a] = orc_h(g, a);
+    double href = g->href;
+    static const int ci[6] = {0, 1, 2, 0, 0, 1};
+    static const int cj[6] = {0, 1, 2, 1, 2, 2};
+    for (int64_t n = 0; n < N; ++n) {
+        sqrtg[n] = given[n];
+        for (int m = 0; m < 6; ++m) {
+            int i = ci[m], j = cj[m];
+            double v = 0.0;
+            if (i < d && j < d) v = href * href * given[(1 + m) * N + n] / (h[i] * h[j]) - (i == j ? 1.0 : 0.0);
+            Mhat[m * N + n] = v;
+        }
+        for (int i = 0; i < 3; ++i) Gamh[i * N + n] = i < d ? href * href * given[(7 + i) * N + n] / h[i] : 0.0;
+    }
+    return 0;
+}
+
 /* ---------------------------------------------------------------------------
  * Lattice topology.
  * ------------------------------------------------------------------------- */

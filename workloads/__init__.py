@@ -399,3 +399,71 @@ def pipe_probes(geom) -> np.ndarray:
 def sweep_omegas(n: int = 119, lo: float = 0.0005, hi: float = 0.03) -> np.ndarray:
     """Drive frequencies of the sweep, radians per step."""
     return np.linspace(lo, hi, n)
+
+
+# ---------------------------------------------------------------------------
+# general (non-separable) metric: a stretched, sheared and bumped duct
+# ---------------------------------------------------------------------------
+# For a geometry outside the built-in coordinate systems the metric is the
+# input (the method needs only sqrt(g), the inverse metric and the contracted
+# Christoffel symbols per node).  This synthetic duct, q in [0, L]^3 with the
+# embedding
+#     X1 = q0 (1 + alpha q2 / L)
+#     X2 = q1 + beta q0 q2 / L
+#     X3 = q2 + gamma L sin(pi q0 / L) sin(pi q1 / L),
+# has every metric component non-zero and varying along all three axes.
+
+GENERAL_PLANES = ("sqrtg", "G00", "G11", "G22", "G01", "G02", "G12", "Gam0", "Gam1", "Gam2")
+
+
+def duct_embedding(q, L=1.0, alpha=0.3, beta=0.2, gamma=0.04):
+    """Jacobian J[a, i] = dX_a/dq_i and Hessian H[a, j, k] = d2X_a/dq_j dq_k
+    at points q (3, ...)."""
+    q0, q1, q2 = q
+    s0, c0 = np.sin(np.pi * q0 / L), np.cos(np.pi * q0 / L)
+    s1, c1 = np.sin(np.pi * q1 / L), np.cos(np.pi * q1 / L)
+    k = np.pi / L
+    z = np.zeros_like(q0)
+    one = np.ones_like(q0)
+    J = np.array([[1.0 + alpha * q2 / L, z, alpha * q0 / L],
+                  [beta * q2 / L, one, beta * q0 / L],
+                  [gamma * L * k * c0 * s1, gamma * L * k * s0 * c1, one]])
+    H = np.zeros((3, 3, 3) + q0.shape)
+    H[0, 0, 2] = H[0, 2, 0] = alpha / L
+    H[1, 0, 2] = H[1, 2, 0] = beta / L
+    H[2, 0, 0] = -gamma * L * k * k * s0 * s1
+    H[2, 1, 1] = -gamma * L * k * k * s0 * s1
+    H[2, 0, 1] = H[2, 1, 0] = gamma * L * k * k * c0 * c1
+    return J, H
+
+
+def general_coefficients(geom) -> np.ndarray:
+    """Per-node inputs of a general geometry, planes GENERAL_PLANES x N in
+    the coordinates' own units (see general_at)."""
+    return general_at(np.array(node_grid(geom)), **geom.get("embedding", {}))
+
+
+def general_at(q, **embedding) -> np.ndarray:
+    """sqrt(g), G^{ij} = (g^{-1})^{ij} (00, 11, 22, 01, 02, 12) and
+    Gamma^i = Gamma^i_jk G^{jk} of the duct at points q (3, M), from the
+    embedding's Jacobian J and Hessian H: g = J^T J,
+    Gamma^i_jk = G^{il} (J_l . H_jk)."""
+    J, H = duct_embedding(q, **embedding)
+    g = np.einsum("ai...,aj...->ij...", J, J)
+    gm = np.moveaxis(g, (0, 1), (-2, -1))
+    G = np.moveaxis(np.linalg.inv(gm), (-2, -1), (0, 1))
+    sqrtg = np.sqrt(np.linalg.det(gm))
+    first = np.einsum("al...,ajk...->ljk...", J, H)
+    gam = np.einsum("il...,ljk...->ijk...", G, first)
+    Gc = np.einsum("ijk...,jk...->i...", gam, G)
+    planes = [sqrtg, G[0, 0], G[1, 1], G[2, 2], G[0, 1], G[0, 2], G[1, 2], Gc[0], Gc[1], Gc[2]]
+    return np.stack([np.asarray(p, dtype=np.float64).reshape(-1) for p in planes])
+
+
+def general_duct(n=(64, 64, 64), c: float | None = None, **embedding) -> dict:
+    """The duct on a lattice of n nodes, q in [0, 1]^3, reflecting walls on
+    every face (closed: sum sqrt(g) P is conserved); h_ref = 1 / n0."""
+    geom = dict(kind="general", dim=3, n=tuple(n), qmin=(0.0, 0.0, 0.0), qmax=(1.0, 1.0, 1.0),
+                bc_lo=("bounceback",) * 3, bc_hi=("bounceback",) * 3, h_ref=1.0 / n[0],
+                c=0.3 if c is None else c, damp=1.0, params=(), embedding=dict(embedding))
+    return geom
