@@ -119,9 +119,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="auto",
                     help="'auto' (autotune) or TILE_X,TILE_Y,CHUNK_Z,BLOCKS to fix the step kernel's launch shape")
-    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 3),
+    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 3, 4),
                     help="3-D workload to time: 1 cylinder 128x128x256 (the benchmark), 2 horn 128x128x512, "
-                         "3 torus 96x256x512")
+                         "3 torus 96x256x512, 4 duct 128x128x128 given by its metric (per-node kernel)")
     ap.add_argument("--spectra-horns", type=int, default=64,
                     help="horns in the batched-vs-plain spectra leg (0 skips it)")
     ap.add_argument("--sweep-points", type=int, default=119,
@@ -137,17 +137,20 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    w = W.workload(args.config)
+    w = W.general_workload() if args.config == 4 else W.workload(args.config)
     geom = w["geom"]
     N = W.num_nodes(geom)
     g = lbw.Geometry(geom)
     sim = lbw.Simulation(g, w["P0"], w["probes"], t_max=args.warmup + args.steps)
-    if args.launch == "auto":
+    general = args.config == 4          # per-node kernel: no launch shapes to tune
+    if general:
+        tuned_us = float("nan")
+    elif args.launch == "auto":
         tuned_us = sim.autotune(reps=20)
     else:
         sim.geometry.set_step_config(*(int(v) for v in args.launch.split(",")))
         tuned_us = float("nan")
-    tile = g.step_config()
+    tile = (256, 1, 1, 0) if general else g.step_config()
     log("bench: %s, %d nodes, warmup %d, steps %d, launch shape %s (tuner %.2f us)" % (w["name"], N, args.warmup,
                                                                                    args.steps, tile, tuned_us))
     sim.step(args.warmup)
@@ -163,7 +166,9 @@ def main():
     sim.probe(0, min(sim.t, sim.t_max))  # raises on a non-finite trace
     ms_per_step = ms / args.steps
     mlups = N * args.steps / (ms / 1e3) / 1e6
-    bytes_per_launch = 56.0 * N
+    # algorithmic bytes per node update: 7 populations read and written, plus
+    # 9 float coefficients read per node for a geometry given by its metric
+    bytes_per_launch = (92.0 if general else 56.0) * N
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
     traffic = read_traffic() if args.config == 1 else None  # counters were taken on the cylinder
     # practical ceiling: a device-to-device copy moving the same bytes
@@ -178,7 +183,7 @@ def main():
         dst.copy_(src)
     c1.record(stream)
     torch.cuda.synchronize()
-    copy_gbs = bytes_per_launch / (c0.elapsed_time(c1) / 50 / 1e3) / 1e9
+    copy_gbs = 56.0 * N / (c0.elapsed_time(c1) / 50 / 1e3) / 1e9
     del src, dst
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,

@@ -51,8 +51,11 @@ extern "C" {
  *  LBW_TORUS       (rho, theta major, phi minor), Sec. IV.C; params = {R}
  *  LBW_BESSEL_HORN as LBW_HORN with s(z) = (Zmax - z)^(-lambda), the Bessel
  *                  horn of Sec. IV.B; params = {lambda, Zmax}
+ *  LBW_GENERAL     any 3-D coordinates, given by their metric per node
+ *                  (lbw_make_geometry_general); params unused
  */
-enum { LBW_BOX = 0, LBW_POLAR2D = 1, LBW_CYLINDER = 2, LBW_HORN = 3, LBW_TORUS = 4, LBW_BESSEL_HORN = 5 };
+enum { LBW_BOX = 0, LBW_POLAR2D = 1, LBW_CYLINDER = 2, LBW_HORN = 3, LBW_TORUS = 4, LBW_BESSEL_HORN = 5,
+       LBW_GENERAL = 6 };
 
 /* Wall codes per face.  Walls sit half a link outside the end nodes.
  *  PERIODIC    both faces of the axis must be periodic
@@ -97,12 +100,30 @@ typedef struct lbw_state* lbw_state_t;
  * D3Q7); LBW_ENOMEM; LBW_EDEVICE. */
 int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_t* out);
 
+/* A 3-D geometry given by its metric (Sec. III: the scheme needs only
+ * sqrt(g), the inverse metric and the contracted Christoffel symbols, so any
+ * coordinate system runs by supplying them).  desc->kind is LBW_GENERAL and
+ * dim 3; desc->params is unused.  metric (host, read during the call) holds
+ * 10 planes of N doubles, node n = i0 + n0 (i1 + n1 i2), in the coordinates'
+ * own units: sqrt(g), G^00, G^11, G^22, G^01, G^02, G^12 (G = g^{-1}), and
+ * Gamma^0, Gamma^1, Gamma^2 (Gamma^i = Gamma^i_jk G^jk).  They are converted
+ * to lattice units as in lbw_make_geometry and kept per node; such a
+ * geometry is stepped by a per-node kernel that reads 36 coefficient bytes
+ * per node, takes no step configuration or autotuning, and cannot join a
+ * batch.  Waits for the stream.  Errors: as lbw_make_geometry, plus
+ * LBW_EINVAL for another kind, NULL metric, a non-finite value or
+ * sqrt(g) <= 0. */
+int lbw_make_geometry_general(const lbw_geometry_desc* desc, const double* metric, void* stream,
+                              lbw_geometry_t* out);
+
 /* Releases a geometry (waits for its stream first).  NULL is accepted. */
 int lbw_free_geometry(lbw_geometry_t g);
 
 /* Exported views, for checking the device tables (synchronises):
  *  LBW_EXPORT_TABLE_F64  8 planes of n0*n2 doubles, entry e = i0 + n0*i2:
- *                        Mhat00, Mhat11, Mhat22, Mhat02, Gamh0, Gamh1, Gamh2, sqrtg
+ *                        Mhat00, Mhat11, Mhat22, Mhat02, Gamh0, Gamh1, Gamh2, sqrtg;
+ *                        for LBW_GENERAL 10 planes of N doubles (per node):
+ *                        Mhat00, 11, 22, 01, 02, 12, Gamh0, 1, 2, sqrtg
  *  LBW_EXPORT_MASK_U8    N bytes; bit (l-1) set when the link n -> n + xi_l
  *                        crosses a wall
  *  LBW_EXPORT_PULL_I32   Q*N int32; entry l*N + n is the node population l
@@ -114,7 +135,8 @@ int lbw_geometry_export(lbw_geometry_t g, int what, void* host_dst, size_t bytes
 
 /* Frozen-coefficient stability bound of the tau = 1/2 step on this geometry:
  * c_max = 2 / sqrt(max_nodes sum_d B_d), B_d = 4 if m_d <= 1 else
- * (1 + m_d)^2 / m_d, m_d = Mhat^dd (+ |Mhat^02| on axes 0 and 2).
+ * (1 + m_d)^2 / m_d, m_d = Mhat^dd (+ |Mhat^02| on axes 0 and 2; for
+ * LBW_GENERAL + the |Mhat^de| of both off-diagonal components of axis d).
  * Synchronises.  Errors: LBW_EINVAL for NULL arguments. */
 int lbw_stability_bound(lbw_geometry_t g, double* c_max);
 
@@ -125,7 +147,8 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max);
  * is 256 or 512; chunk_z >= 1 planes per tile along axis 2; blocks:
  * persistent grid size, rounded down to a multiple of 8 (0 = one full wave
  * of resident workgroups).  Used by lbw_autotune and by tests.
- * Errors: LBW_EINVAL for a 2-D geometry or out-of-range values. */
+ * Errors: LBW_EINVAL for a 2-D or LBW_GENERAL geometry or out-of-range
+ * values. */
 int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks);
 int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks);
 
@@ -164,7 +187,8 @@ int lbw_step_n(lbw_state_t s, int64_t n);
  * unchanged.  The choice is stored in the geometry and in a per-process
  * cache keyed by the grid shape, which later geometries of that shape start
  * from.  Synchronises.  best_us (may be NULL) receives the best time per
- * step in microseconds.  Errors: LBW_EINVAL (2-D geometry, reps < 1). */
+ * step in microseconds.  Errors: LBW_EINVAL (2-D or LBW_GENERAL geometry,
+ * reps < 1). */
 int lbw_autotune(lbw_state_t s, int reps, double* best_us);
 
 /* Number of steps lbw_step_n captures into one HIP graph and replays

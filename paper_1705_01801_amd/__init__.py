@@ -16,13 +16,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbw.so")
 
-KINDS = {"box": 0, "polar2d": 1, "cylinder": 2, "horn": 3, "torus": 4, "bessel_horn": 5}
+KINDS = {"box": 0, "polar2d": 1, "cylinder": 2, "horn": 3, "torus": 4, "bessel_horn": 5, "general": 6}
 BCS = {"periodic": 0, "bounceback": 1, "free": 2, "fixed": 3}
 EXPORT_TABLE_F64, EXPORT_MASK_U8, EXPORT_PULL_I32 = 0, 1, 2
 TABLE_PLANES = ("Mhat00", "Mhat11", "Mhat22", "Mhat02", "Gamh0", "Gamh1", "Gamh2", "sqrtg")
 
 # every symbol include/lbw.h declares
-SYMBOLS = ("lbw_make_geometry", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound",
+SYMBOLS = ("lbw_make_geometry", "lbw_make_geometry_general", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound",
            "lbw_set_step_config", "lbw_get_step_config", "lbw_init",
            "lbw_step_n", "lbw_autotune", "lbw_set_graph_block", "lbw_probe", "lbw_modes", "lbw_state_info",
            "lbw_pressure", "lbw_free_state", "lbw_set_sources", "lbw_amplitude", "lbw_batch_make", "lbw_batch_layout", "lbw_batch_set_step_config",
@@ -93,6 +93,7 @@ def lib():
         L.lbw_geometry_export.argtypes = [vp, i32, vp, ctypes.c_size_t]
         L.lbw_stability_bound.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         ip = ctypes.POINTER(ctypes.c_int)
+        L.lbw_make_geometry_general.argtypes = [ctypes.POINTER(GeometryDesc), vp, vp, ctypes.POINTER(vp)]
         L.lbw_set_step_config.argtypes = [vp, i32, i32, i32, i32]
         L.lbw_get_step_config.argtypes = [vp, ip, ip, ip, ip]
         L.lbw_init.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), i32, vp, i64, vp, ctypes.POINTER(vp)]
@@ -183,15 +184,23 @@ class Geometry:
         self.Q = 2 * self.dim + 1
         self.shape = tuple(int(v) for v in geom["n"][: self.dim])
         self.N = int(np.prod(self.shape))
-        self.E = self.shape[0] * (self.shape[2] if self.dim == 3 else 1)
+        self.general = geom["kind"] == "general"
+        self.E = self.N if self.general else self.shape[0] * (self.shape[2] if self.dim == 3 else 1)
         self._desc = to_desc(geom)
         self._stream = stream
         h = ctypes.c_void_p()
-        check(lib().lbw_make_geometry(ctypes.byref(self._desc), _stream_ptr(stream), ctypes.byref(h)))
+        if self.general:
+            # a geometry given by its metric: 10 planes of N doubles (sqrt(g),
+            # G^{ij} 00 11 22 01 02 12, Gamma^i 0 1 2)
+            metric = np.ascontiguousarray(geom["coeffs"], dtype=np.float64).reshape(10, self.N)
+            check(lib().lbw_make_geometry_general(ctypes.byref(self._desc), metric.ctypes.data, _stream_ptr(stream),
+                                                  ctypes.byref(h)))
+        else:
+            check(lib().lbw_make_geometry(ctypes.byref(self._desc), _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
 
     def table(self) -> np.ndarray:
-        out = np.zeros((8, self.E))
+        out = np.zeros((10 if self.general else 8, self.E))
         check(lib().lbw_geometry_export(self.handle, EXPORT_TABLE_F64, out.ctypes.data, out.nbytes))
         return out
 

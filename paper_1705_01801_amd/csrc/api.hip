@@ -19,7 +19,8 @@ struct lbw_geometry {
     lbw_geometry_desc d;
     int Q = 0;
     int64_t N = 0;
-    int64_t E = 0;  // table entries n0 * n2
+    int64_t E = 0;  // table entries n0 * n2 (a geometry given by its metric: N)
+    bool general = false;  // given by its metric: per-node tables, general step kernel
     double* tab64 = nullptr;
     float* tab32 = nullptr;
     hipStream_t stream = nullptr;
@@ -47,6 +48,7 @@ struct lbw_state {
     lbw::SourceEntry* d_src = nullptr;   // driven sources, imposed before every step
     int n_src = 0;
     double* d_amp = nullptr;             // response intensities (n_probes)
+    float* d_S = nullptr;                // S of the current step (general geometries)
     // graph-captured step blocks, one per starting buffer parity
     int graph_block = 32;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -123,7 +125,7 @@ GeomDev make_geomdev(const lbw_geometry_desc& d, const float* tab32, const doubl
 
 int validate_desc(const lbw_geometry_desc* d) {
     if (!d) return fail(LBW_EINVAL, "descriptor is NULL");
-    if (d->kind < LBW_BOX || d->kind > LBW_BESSEL_HORN) return fail(LBW_EINVAL, "unknown kind %d", d->kind);
+    if (d->kind < LBW_BOX || d->kind > LBW_GENERAL) return fail(LBW_EINVAL, "unknown kind %d", d->kind);
     if (d->dim != 2 && d->dim != 3) return fail(LBW_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
     if (d->kind == LBW_POLAR2D && d->dim != 2) return fail(LBW_EINVAL, "polar2d needs dim 2");
     if (d->kind != LBW_POLAR2D && d->kind != LBW_BOX && d->dim != 3) return fail(LBW_EINVAL, "kind needs dim 3");
@@ -188,6 +190,8 @@ int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_
     *out = nullptr;
     int rc = lbw::validate_desc(desc);
     if (rc) return rc;
+    if (desc->kind == LBW_GENERAL)
+        return fail(LBW_EINVAL, "a geometry given by its metric is made with lbw_make_geometry_general");
     lbw_geometry* g = new lbw_geometry();
     g->d = lbw::normalised(*desc);
     const lbw_geometry_desc& d = g->d;
@@ -221,6 +225,68 @@ int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_
     return LBW_OK;
 }
 
+int lbw_make_geometry_general(const lbw_geometry_desc* desc, const double* metric, void* stream,
+                              lbw_geometry_t* out) {
+    if (!out) return fail(LBW_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = lbw::validate_desc(desc);
+    if (rc) return rc;
+    if (desc->kind != LBW_GENERAL || desc->dim != 3) return fail(LBW_EINVAL, "kind must be LBW_GENERAL with dim 3");
+    if (!metric) return fail(LBW_EINVAL, "metric is NULL");
+    const lbw_geometry_desc d = lbw::normalised(*desc);
+    const int64_t N = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    for (int64_t i = 0; i < lbw::kGenF64 * N; ++i)
+        if (!std::isfinite(metric[i])) return fail(LBW_EINVAL, "non-finite metric value (plane %lld)", (long long)(i / N));
+    for (int64_t n = 0; n < N; ++n)
+        if (!(metric[n] > 0.0)) return fail(LBW_EINVAL, "sqrt(g) must be > 0 (node %lld)", (long long)n);
+    // lattice units (Sec. III): Mhat^{ij} = h_ref^2 G^{ij} / (h_i h_j) - delta^{ij},
+    // Gamh^i = h_ref^2 Gamma^i / h_i; FP32 planes c^2 Mhat and c^2 Gamh / 2
+    double h[3];
+    for (int a = 0; a < 3; ++a) h[a] = (d.qmax[a] - d.qmin[a]) / d.n[a];
+    static const int ci[6] = {0, 1, 2, 0, 0, 1};
+    static const int cj[6] = {0, 1, 2, 1, 2, 2};
+    const double hr2 = d.h_ref * d.h_ref, c2 = d.c * d.c;
+    std::vector<double> t64((size_t)lbw::kGenF64 * N);
+    std::vector<float> t32((size_t)lbw::kGenF32 * N);
+    for (int64_t n = 0; n < N; ++n) {
+        for (int m = 0; m < 6; ++m) {
+            const double v = hr2 * metric[(1 + m) * N + n] / (h[ci[m]] * h[cj[m]]) - (ci[m] == cj[m] ? 1.0 : 0.0);
+            t64[m * N + n] = v;
+            t32[m * N + n] = (float)(c2 * v);
+        }
+        for (int a = 0; a < 3; ++a) {
+            const double v = hr2 * metric[(7 + a) * N + n] / h[a];
+            t64[(6 + a) * N + n] = v;
+            t32[(6 + a) * N + n] = (float)(0.5 * c2 * v);
+        }
+        t64[9 * N + n] = metric[n];
+    }
+    lbw_geometry* g = new lbw_geometry();
+    g->d = d;
+    g->Q = 7;
+    g->N = N;
+    g->E = N;
+    g->general = true;
+    g->stream = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&g->tab64, sizeof(double) * t64.size());
+    if (e == hipSuccess) e = hipMalloc(&g->tab32, sizeof(float) * t32.size());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->tab64, t64.data(), sizeof(double) * t64.size(), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->tab32, t32.data(), sizeof(float) * t32.size(), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);  // host tables go out of scope
+    if (e != hipSuccess) {
+        (void)hipFree(g->tab64);
+        (void)hipFree(g->tab32);
+        delete g;
+        return hip_fail(e, "lbw_make_geometry_general");
+    }
+    g->dev = lbw::make_geomdev(d, g->tab32, g->tab64 + 9 * N);
+    g->dev.sg_node = 1;
+    *out = g;
+    return LBW_OK;
+}
+
 int lbw_free_geometry(lbw_geometry_t g) {
     if (!g) return LBW_OK;
     (void)hipStreamSynchronize(g->stream);
@@ -234,7 +300,7 @@ int lbw_geometry_export(lbw_geometry_t g, int what, void* host_dst, size_t bytes
     if (!g || !host_dst) return fail(LBW_EINVAL, "NULL argument");
     size_t need = 0;
     switch (what) {
-    case LBW_EXPORT_TABLE_F64: need = sizeof(double) * lbw::kTabF64 * g->E; break;
+    case LBW_EXPORT_TABLE_F64: need = sizeof(double) * (g->general ? lbw::kGenF64 : lbw::kTabF64) * g->E; break;
     case LBW_EXPORT_MASK_U8: need = (size_t)g->N; break;
     case LBW_EXPORT_PULL_I32: need = sizeof(int32_t) * g->Q * g->N; break;
     default: return fail(LBW_EINVAL, "unknown export %d", what);
@@ -262,7 +328,7 @@ int lbw_geometry_export(lbw_geometry_t g, int what, void* host_dst, size_t bytes
 
 int lbw_stability_bound(lbw_geometry_t g, double* c_max) {
     if (!g || !c_max) return fail(LBW_EINVAL, "NULL argument");
-    std::vector<double> t((size_t)lbw::kTabF64 * g->E);
+    std::vector<double> t((size_t)(g->general ? lbw::kGenF64 : lbw::kTabF64) * g->E);
     HIP_TRY(hipMemcpyAsync(t.data(), g->tab64, sizeof(double) * t.size(), hipMemcpyDeviceToHost, g->stream),
             "stability bound");
     HIP_TRY(hipStreamSynchronize(g->stream), "stability bound");
@@ -272,7 +338,14 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max) {
         double tot = 0.0;
         for (int a = 0; a < g->d.dim; ++a) {
             double m = t[a * E + e];
-            if (g->d.dim == 3 && a != 1) m += std::fabs(t[3 * E + e]);
+            if (g->general) {
+                // off-diagonal planes 01 (3), 02 (4), 12 (5) touching axis a
+                m += a == 0 ? std::fabs(t[3 * E + e]) + std::fabs(t[4 * E + e])
+                     : a == 1 ? std::fabs(t[3 * E + e]) + std::fabs(t[5 * E + e])
+                              : std::fabs(t[4 * E + e]) + std::fabs(t[5 * E + e]);
+            } else if (g->d.dim == 3 && a != 1) {
+                m += std::fabs(t[3 * E + e]);
+            }
             tot += m <= 1.0 ? 4.0 : (1.0 + m) * (1.0 + m) / m;
         }
         worst = std::fmax(worst, tot);
@@ -283,7 +356,8 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max) {
 
 int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks) {
     if (!g) return fail(LBW_EINVAL, "geometry is NULL");
-    if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
+    if (g->dev.dim != 3 || g->general)
+        return fail(LBW_EINVAL, "step configuration applies to built-in 3-D geometries");
     if (!lbw::march_shape_ok(tile_x, tile_y))
         return fail(LBW_EINVAL, "tile %d x %d: tile_x must be 16, 32 or 64 and tile_x * tile_y 256 or 512", tile_x,
                     tile_y);
@@ -301,7 +375,8 @@ int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, i
 
 int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks) {
     if (!g) return fail(LBW_EINVAL, "geometry is NULL");
-    if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
+    if (g->dev.dim != 3 || g->general)
+        return fail(LBW_EINVAL, "step configuration applies to built-in 3-D geometries");
     if (tile_x) *tile_x = g->plan.tx;
     if (tile_y) *tile_y = g->plan.ty;
     if (chunk_z) *chunk_z = g->plan.lz;
@@ -329,6 +404,7 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
     s->stream = (hipStream_t)stream;
     hipError_t e = hipMalloc(&s->d_tcount, sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc(&s->d_scratch_count, sizeof(int64_t));
+    if (e == hipSuccess && g->general) e = hipMalloc(&s->d_S, sizeof(float) * g->N);
     if (e == hipSuccess && n_probes > 0) e = hipMalloc(&s->d_probes, sizeof(int64_t) * n_probes);
     if (e == hipSuccess && n_probes > 0)
         e = hipMemcpyAsync(s->d_probes, probes, sizeof(int64_t) * n_probes, hipMemcpyHostToDevice, s->stream);
@@ -341,6 +417,7 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
         (void)hipFree(s->d_tcount);
         (void)hipFree(s->d_scratch_count);
         (void)hipFree(s->d_probes);
+        (void)hipFree(s->d_S);
         delete s;
         return hip_fail(e, "lbw_init");
     }
@@ -355,6 +432,7 @@ hipError_t launch_one(lbw_state* s, const lbw::ProbeArgs& pr, int from, hipStrea
         const hipError_t e = lbw::launch_sources(s->d_src, s->n_src, s->d_tcount, s->f[from], st);
         if (e != hipSuccess) return e;
     }
+    if (s->g->general) return lbw::launch_step_general(s->g->dev, pr, s->f[from], s->d_S, s->f[1 - from], st);
     if (s->g->dev.dim == 3)
         return lbw::launch_step_march(s->g->dev, pr, s->g->plan, s->f[from], s->f[1 - from], st);
     return lbw::launch_step(s->g->dev, pr, s->f[from], s->f[1 - from], st);
@@ -433,7 +511,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     if (!s) return fail(LBW_EINVAL, "state is NULL");
     if (reps < 1) return fail(LBW_EINVAL, "reps must be >= 1");
     lbw_geometry* g = s->g;
-    if (g->dev.dim != 3) return fail(LBW_EINVAL, "autotune applies to 3-D geometries");
+    if (g->dev.dim != 3 || g->general) return fail(LBW_EINVAL, "autotune applies to built-in 3-D geometries");
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev), "lbw_autotune");
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "lbw_autotune");
@@ -560,10 +638,11 @@ int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude
     lbw_geometry* g = s->g;
     for (int i = 0; i < n; ++i)
         if (nodes[i] < 0 || nodes[i] >= g->N) return fail(LBW_EINVAL, "source %d outside the grid", i);
-    // sqrt(g) per (i0, i2) entry, FP64 table plane 7
+    // sqrt(g) per (i0, i2) entry (FP64 table plane 7) or per node (plane 9)
     std::vector<double> sg(n > 0 ? (size_t)g->E : 0);
     if (n > 0)
-        HIP_TRY(hipMemcpyAsync(sg.data(), g->tab64 + 7 * g->E, sizeof(double) * g->E, hipMemcpyDeviceToHost, s->stream),
+        HIP_TRY(hipMemcpyAsync(sg.data(), g->tab64 + (g->general ? 9 : 7) * g->E, sizeof(double) * g->E,
+                               hipMemcpyDeviceToHost, s->stream),
                 "lbw_set_sources");
     HIP_TRY(hipStreamSynchronize(s->stream), "lbw_set_sources");
     const int d = g->dev.dim;
@@ -572,7 +651,7 @@ int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude
     std::vector<lbw::SourceEntry> host((size_t)n);
     for (int i = 0; i < n; ++i) {
         const int64_t node = nodes[i];
-        const double sq = sg[(size_t)(node % n0 + n0 * (node / plane))];
+        const double sq = sg[(size_t)(g->general ? node : node % n0 + n0 * (node / plane))];
         lbw::SourceEntry e{};
         e.f_off = (uint64_t)node;
         e.N = (uint32_t)g->N;
@@ -636,6 +715,7 @@ int lbw_free_state(lbw_state_t s) {
     (void)hipFree(s->d_probes);
     (void)hipFree(s->d_src);
     (void)hipFree(s->d_amp);
+    (void)hipFree(s->d_S);
     (void)hipFree(s->mode_work);
     (void)hipFree(s->mode_out);
     delete s;

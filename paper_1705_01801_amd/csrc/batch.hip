@@ -214,9 +214,9 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
             delete b;
             return fail(rc, "geometry %d: %s", h, lbw_last_error());
         }
-        if (descs[h].dim != 3) {
+        if (descs[h].dim != 3 || descs[h].kind == LBW_GENERAL) {
             delete b;
-            return fail(LBW_EINVAL, "geometry %d: batches hold 3-D geometries", h);
+            return fail(LBW_EINVAL, "geometry %d: batches hold built-in 3-D geometries", h);
         }
         if (n_probes[h] < 0) {
             delete b;

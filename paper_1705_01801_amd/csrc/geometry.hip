@@ -147,9 +147,7 @@ __global__ void init_kernel(GeomDev g, double c2, const double* __restrict__ p0,
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
     const int Q = 2 * g.dim + 1;
-    const int i0 = (int)(n % g.n0);
-    const int i2 = (int)(n / ((int64_t)g.n0 * g.n1));
-    const double sg = g.sqrtg[i0 + g.n0 * i2];
+    const double sg = g.sqrtg[sg_index(g, n)];
     const double w0 = 1.0 - g.dim * c2, w = 0.5 * c2;
     f[n] = (float)(w0 * sg * p0[n]);
     for (int l = 1; l < Q; ++l) f[l * g.N + n] = (float)(w * sg * p0[n]);
@@ -159,11 +157,9 @@ __global__ void pressure_kernel(GeomDev g, const float* __restrict__ f, double* 
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
     const int Q = 2 * g.dim + 1;
-    const int i0 = (int)(n % g.n0);
-    const int i2 = (int)(n / ((int64_t)g.n0 * g.n1));
     double s = 0.0;
     for (int l = 0; l < Q; ++l) s += (double)f[l * g.N + n];
-    p[n] = s / g.sqrtg[i0 + g.n0 * i2];
+    p[n] = s / g.sqrtg[sg_index(g, n)];
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }

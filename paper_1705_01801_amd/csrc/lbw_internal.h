@@ -27,9 +27,22 @@ struct GeomDev {
     float two_w0;     // 2 (1 - dim c^2)
     float damp;       // bounce-back damping
     double c2_64;     // c^2 in double (initial state)
-    const float* tab;     // kTabF32 floats per entry
-    const double* sqrtg;  // one double per entry
+    const float* tab;     // kTabF32 floats per entry (general geometries: kGenF32 planes of N floats)
+    const double* sqrtg;  // one double per entry (general geometries: per node)
+    int sg_node;          // 1: sqrt(g) and coefficients are per node (a geometry given by its metric)
 };
+
+// General geometries (given by their metric): FP32 planes of N values used
+// by the general step kernel, c^2 Mhat 00, 11, 22, 01, 02, 12 and
+// c^2 Gamh / 2 for axes 0, 1, 2; FP64 export planes Mhat (same 6), Gamh (3),
+// sqrt(g).
+constexpr int kGenF32 = 9;
+constexpr int kGenF64 = 10;
+
+// Index of node n's sqrt(g): per (i0, i2) entry, or per node.
+__host__ __device__ inline int64_t sg_index(const GeomDev& g, int64_t n) {
+    return g.sg_node ? n : n % g.n0 + (int64_t)g.n0 * (n / ((int64_t)g.n0 * g.n1));
+}
 
 // Neighbour coordinate one link along an axis; -1 when the link crosses a
 // wall, whose code is then stored in *wall.
@@ -62,6 +75,10 @@ struct ProbeArgs {
     int64_t* tcount;       // device step counter
 };
 hipError_t launch_step(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* fout, hipStream_t st);
+// One step of a geometry given by its metric (3-D): S pass (with the probes)
+// into S (N floats), then collide and push.
+hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* S, float* fout,
+                               hipStream_t st);
 
 // Launch shape of the z-marching D3Q7 kernel.
 struct MarchPlan {

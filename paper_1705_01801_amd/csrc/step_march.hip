@@ -66,9 +66,7 @@ __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* 
             const int64_t node = pr.nodes[p];
             double s = 0.0;
             for (int l = 0; l < 7; ++l) s += (double)fin[l * g.N + node];
-            const int i0 = (int)(node % g.n0);
-            const int i2 = (int)(node / ((int64_t)g.n0 * g.n1));
-            pr.trace[t * pr.n + p] = s / g.sqrtg[i0 + g.n0 * i2];
+            pr.trace[t * pr.n + p] = s / g.sqrtg[sg_index(g, node)];
         }
     }
     __syncthreads();

@@ -467,3 +467,18 @@ def general_duct(n=(64, 64, 64), c: float | None = None, **embedding) -> dict:
                 bc_lo=("bounceback",) * 3, bc_hi=("bounceback",) * 3, h_ref=1.0 / n[0],
                 c=0.3 if c is None else c, damp=1.0, params=(), embedding=dict(embedding))
     return geom
+
+
+def general_workload(scale: int = 1) -> dict:
+    """The duct at 128^3 nodes (coarser with scale), a Gaussian pulse in
+    coordinate space (centre (0.4, 0.55, 0.3), width 0.08) and 16 seeded
+    probes; step count as the cylinder's."""
+    n = _scaled((128, 128, 128), scale)
+    geom = general_duct(n=n)
+    geom["coeffs"] = general_coefficients(geom)
+    q = node_grid(geom)
+    P0 = np.exp(-((q[0] - 0.4) ** 2 + (q[1] - 0.55) ** 2 + (q[2] - 0.3) ** 2) / (2 * 0.08 ** 2))
+    rng = np.random.default_rng(SEED_BASE + 5)
+    probes = rng.integers(0, num_nodes(geom), size=16)
+    return dict(index=4, name="general_duct_d3q7_%dx%dx%d" % n, geom=geom, P0=P0,
+                probes=np.asarray(probes, dtype=np.int64), steps=STEPS[1], scale=scale)
