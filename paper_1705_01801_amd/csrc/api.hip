@@ -48,7 +48,6 @@ struct lbw_state {
     lbw::SourceEntry* d_src = nullptr;   // driven sources, imposed before every step
     int n_src = 0;
     double* d_amp = nullptr;             // response intensities (n_probes)
-    float* d_S = nullptr;                // S of the current step (general geometries)
     // graph-captured step blocks, one per starting buffer parity
     int graph_block = 32;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -404,7 +403,6 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
     s->stream = (hipStream_t)stream;
     hipError_t e = hipMalloc(&s->d_tcount, sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc(&s->d_scratch_count, sizeof(int64_t));
-    if (e == hipSuccess && g->general) e = hipMalloc(&s->d_S, sizeof(float) * g->N);
     if (e == hipSuccess && n_probes > 0) e = hipMalloc(&s->d_probes, sizeof(int64_t) * n_probes);
     if (e == hipSuccess && n_probes > 0)
         e = hipMemcpyAsync(s->d_probes, probes, sizeof(int64_t) * n_probes, hipMemcpyHostToDevice, s->stream);
@@ -417,7 +415,6 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
         (void)hipFree(s->d_tcount);
         (void)hipFree(s->d_scratch_count);
         (void)hipFree(s->d_probes);
-        (void)hipFree(s->d_S);
         delete s;
         return hip_fail(e, "lbw_init");
     }
@@ -432,7 +429,7 @@ hipError_t launch_one(lbw_state* s, const lbw::ProbeArgs& pr, int from, hipStrea
         const hipError_t e = lbw::launch_sources(s->d_src, s->n_src, s->d_tcount, s->f[from], st);
         if (e != hipSuccess) return e;
     }
-    if (s->g->general) return lbw::launch_step_general(s->g->dev, pr, s->f[from], s->d_S, s->f[1 - from], st);
+    if (s->g->general) return lbw::launch_step_general(s->g->dev, pr, s->f[from], s->f[1 - from], st);
     if (s->g->dev.dim == 3)
         return lbw::launch_step_march(s->g->dev, pr, s->g->plan, s->f[from], s->f[1 - from], st);
     return lbw::launch_step(s->g->dev, pr, s->f[from], s->f[1 - from], st);
@@ -715,7 +712,6 @@ int lbw_free_state(lbw_state_t s) {
     (void)hipFree(s->d_probes);
     (void)hipFree(s->d_src);
     (void)hipFree(s->d_amp);
-    (void)hipFree(s->d_S);
     (void)hipFree(s->mode_work);
     (void)hipFree(s->mode_out);
     delete s;

@@ -75,9 +75,9 @@ struct ProbeArgs {
     int64_t* tcount;       // device step counter
 };
 hipError_t launch_step(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* fout, hipStream_t st);
-// One step of a geometry given by its metric (3-D): S pass (with the probes)
-// into S (N floats), then collide and push.
-hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* S, float* fout,
+// One step of a geometry given by its metric (3-D, per-node coefficients),
+// z-marching tiles; probes recorded as in the other step kernels.
+hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* fout,
                                hipStream_t st);
 
 // Launch shape of the z-marching D3Q7 kernel.

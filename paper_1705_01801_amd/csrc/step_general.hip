@@ -3,35 +3,87 @@
 // Christoffel symbols, so any coordinate system runs by supplying them per
 // node).  Same arithmetic as the per-node description in step.hip (BGK
 // tau = 1/2, corrected equilibrium, Christoffel and metric-gradient forcing,
-// push streaming with the wall rules), here with all six metric components,
-// each varying along every axis, in two passes:
-//  - general_s_kernel: S = sum_l f_l into a buffer of N floats; workgroup 0
-//    first records the probes of time t and advances the step counter;
-//  - general_step_kernel: one thread per node (axis 0 fastest), momentum
-//    with the metric-gradient term from S and the coefficients of the six
-//    axis neighbours, collision, push.
+// push streaming with the wall rules), with all six metric components, each
+// varying along every axis.
+//
 // Coefficients are FP32 planes of N values: c^2 Mhat 00, 11, 22, 01, 02, 12
-// and c^2 Gamh / 2 per axis.  For axis d the metric-gradient term needs
-// A^{de} = c^2 Mhat^{de} S at the neighbours along e, i.e. at x +- e_0 the
-// components (d0), at x +- e_1 (d1), at x +- e_2 (d2); beyond a wall the
-// node's own A is mirrored, odd for fixed walls.
+// and c^2 Gamh / 2 per axis.  For axis d the metric-gradient term is
+// (1/4) sum_e [A^{de}(x + e_e) - A^{de}(x - e_e)], A^{de} = c^2 Mhat^{de} S:
+// the axis-0 neighbours contribute A^{00}, A^{10}, A^{20}, the axis-1
+// neighbours A^{01}, A^{11}, A^{21}, the axis-2 neighbours A^{02}, A^{12},
+// A^{22}; beyond a wall the node's own A is mirrored (odd for fixed walls).
+//
+// Data movement (as the z-marching kernel of the built-in geometries): a
+// workgroup of 256 threads owns a TX x TY tile of (axis 0, axis 1) columns
+// and walks a chunk of planes along axis 2.  A thread keeps its column's
+// populations, coefficients and the axis-2 products A^{d2} of planes z-1, z
+// and z+1 in registers (plane z+1 is loaded while plane z is computed); the
+// five products the axis-0 and axis-1 neighbours need (A^{00}, A^{11},
+// A^{01}, A^{02}, A^{12}) are staged in LDS for the tile and a one-node ring
+// (two plane slots, one barrier per plane), the ring nodes' populations and
+// coefficients loaded by the first 2 TX + 2 TY threads.  Workgroup 0 records
+// the probes of time t before any population is written and advances the
+// step counter.
 #include "lbw_internal.h"
 
 namespace lbw {
 namespace {
 
-constexpr int kBS = 256;
+constexpr int kGT = 256;  // threads per workgroup
 
-// component plane of Mhat^{de}
-__device__ constexpr int mplane(int d, int e) {
-    return d == e ? d : ((d + e == 1) ? 3 : ((d + e == 2) ? 4 : 5));
-}
+__device__ inline float mirror(int wall, float own) { return wall == LBW_BC_FIXED ? -own : own; }
 
 __device__ inline float bounce_rule(int wall, float damp, float out_l, float own_opposite) {
     return wall == LBW_BC_BOUNCEBACK ? damp * out_l : (wall == LBW_BC_FREE ? own_opposite : -out_l);
 }
 
-__global__ void general_s_kernel(GeomDev g, ProbeArgs pr, const float* __restrict__ fin, float* __restrict__ S) {
+struct GenPlan {
+    int ntx, nty, lz;
+};
+
+// one node's populations, coefficients, S and the six products c^2 Mhat^m S
+struct Node {
+    float f[7];
+    float t[9];
+    float S;
+    float a[6];
+};
+
+__device__ inline void load_node(const float* __restrict__ fin, const float* __restrict__ T, int64_t N, int64_t n,
+                                 Node& v) {
+    float s = 0.f;
+#pragma unroll
+    for (int l = 0; l < 7; ++l) {
+        v.f[l] = fin[l * N + n];
+        s += v.f[l];
+    }
+#pragma unroll
+    for (int m = 0; m < 9; ++m) v.t[m] = T[m * N + n];
+    v.S = s;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) v.a[m] = v.t[m] * s;
+}
+
+__device__ inline void zero_node(Node& v) {
+#pragma unroll
+    for (int l = 0; l < 7; ++l) v.f[l] = 0.f;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) v.t[m] = 0.f;
+    v.S = 0.f;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) v.a[m] = 0.f;
+}
+
+template <int TX>
+__global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs pr, GenPlan plan,
+                                                            const float* __restrict__ fin,
+                                                            float* __restrict__ fout) {
+    constexpr int TY = kGT / TX;
+    constexpr int W = TX + 2;
+    constexpr int SLOTS = (TY + 2) * W;
+    // LDS products per slot: 0 A^{00}, 1 A^{11}, 2 A^{01}, 3 A^{02}, 4 A^{12}
+    __shared__ float sA[2][5][SLOTS];
+
     if (blockIdx.x == 0) {
         const int64_t t = *(volatile const int64_t*)pr.tcount;
         __syncthreads();
@@ -46,81 +98,190 @@ __global__ void general_s_kernel(GeomDev g, ProbeArgs pr, const float* __restric
         __syncthreads();
         if (threadIdx.x == 0) *(volatile int64_t*)pr.tcount = t + 1;
     }
-    const int64_t n = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (n >= g.N) return;
-    float s = 0.f;
-    for (int l = 0; l < 7; ++l) s += fin[l * g.N + n];
-    S[n] = s;
-}
 
-__global__ void general_step_kernel(GeomDev g, const float* __restrict__ fin, const float* __restrict__ S,
-                                    float* __restrict__ fout) {
-    const int64_t n = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (n >= g.N) return;
-    const int64_t N = g.N;
     const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
-    const int64_t plane = (int64_t)n0 * n1;
-    const int x = (int)(n % n0), y = (int)((n / n0) % n1), z = (int)(n / plane);
+    const int64_t N = g.N, plane = (int64_t)n0 * n1;
     const float* __restrict__ T = g.tab;
-    // axis neighbours: node index, or the node itself beyond a wall (then
-    // the wall code is in w[a][side] and the neighbour is not read)
-    int w[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    int j[3][2];
-    j[0][0] = link_coord(x, +1, n0, g.bc_lo[0], g.bc_hi[0], &w[0][0]);
-    j[0][1] = link_coord(x, -1, n0, g.bc_lo[0], g.bc_hi[0], &w[0][1]);
-    j[1][0] = link_coord(y, +1, n1, g.bc_lo[1], g.bc_hi[1], &w[1][0]);
-    j[1][1] = link_coord(y, -1, n1, g.bc_lo[1], g.bc_hi[1], &w[1][1]);
-    j[2][0] = link_coord(z, +1, n2, g.bc_lo[2], g.bc_hi[2], &w[2][0]);
-    j[2][1] = link_coord(z, -1, n2, g.bc_lo[2], g.bc_hi[2], &w[2][1]);
-    const int own[3] = {x, y, z};
-    const int64_t stride[3] = {1, n0, plane};
-    int64_t nb[3][2];
-    for (int a = 0; a < 3; ++a)
-        for (int s = 0; s < 2; ++s) nb[a][s] = j[a][s] >= 0 ? n + (int64_t)(j[a][s] - own[a]) * stride[a] : n;
-    float f[7];
-    for (int l = 0; l < 7; ++l) f[l] = fin[l * N + n];
-    const float Sc = S[n];
-    float K[3];
-    for (int d = 0; d < 3; ++d) {
-        float div = 0.f;
-        for (int e = 0; e < 3; ++e) {
-            const int m = mplane(d, e);
-            const float ahere = T[m * N + n] * Sc;
-            float side[2];
-            for (int s = 0; s < 2; ++s)
-                side[s] = j[e][s] >= 0 ? T[m * N + nb[e][s]] * S[nb[e][s]]
-                                       : (w[e][s] == LBW_BC_FIXED ? -ahere : ahere);
-            div += side[0] - side[1];
+    const int b = blockIdx.x;
+    const int tx = b % plan.ntx, ty = (b / plan.ntx) % plan.nty, ch = b / (plan.ntx * plan.nty);
+    const int x0 = tx * TX, y0 = ty * TY, z0 = ch * plan.lz;
+    const int z1 = min(z0 + plan.lz, n2);
+    const int wdt = min(TX, n0 - x0), hgt = min(TY, n1 - y0);
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool active = lx < wdt && ly < hgt;
+    const int64_t col = (int64_t)x + (int64_t)n0 * y;
+    const int my = (ly + 1) * W + lx + 1;
+
+    int wx_p = 0, wx_m = 0, wy_p = 0, wy_m = 0;
+    const int jx_p = link_coord(x, +1, n0, g.bc_lo[0], g.bc_hi[0], &wx_p);
+    const int jx_m = link_coord(x, -1, n0, g.bc_lo[0], g.bc_hi[0], &wx_m);
+    const int jy_p = link_coord(y, +1, n1, g.bc_lo[1], g.bc_hi[1], &wy_p);
+    const int jy_m = link_coord(y, -1, n1, g.bc_lo[1], g.bc_hi[1], &wy_m);
+
+    // ring node of this thread (slot and wrapped column), if any: rows
+    // y0 - 1 and y0 + hgt over the tile's columns, columns x0 - 1 and
+    // x0 + wdt over its rows, each placed next to the tile's last active
+    // column/row so that a node's neighbour slot is always slot +- 1 / +- W
+    int ring_slot = -1;
+    int64_t ring_col = 0;
+    {
+        const int r = threadIdx.x;
+        int rx = 0, ry = 0, sx = 0, sy = 0;
+        bool have = false;
+        if (r < wdt) {
+            rx = x0 + r; ry = y0 - 1; sx = r + 1; sy = 0; have = true;
+        } else if (r >= TX && r < TX + wdt) {
+            rx = x0 + (r - TX); ry = y0 + hgt; sx = r - TX + 1; sy = hgt + 1; have = true;
+        } else if (r >= 2 * TX && r < 2 * TX + hgt) {
+            rx = x0 - 1; ry = y0 + (r - 2 * TX); sx = 0; sy = r - 2 * TX + 1; have = true;
+        } else if (r >= 2 * TX + TY && r < 2 * TX + TY + hgt) {
+            rx = x0 + wdt; ry = y0 + (r - 2 * TX - TY); sx = wdt + 1; sy = r - 2 * TX - TY + 1; have = true;
         }
-        K[d] = (f[1 + 2 * d] - f[2 + 2 * d]) - T[(6 + d) * N + n] * Sc - 0.25f * div;
+        if (have) {
+            int w = 0;
+            const int gx = rx < 0 || rx >= n0
+                               ? link_coord(rx < 0 ? 0 : n0 - 1, rx < 0 ? -1 : 1, n0, g.bc_lo[0], g.bc_hi[0], &w)
+                               : rx;
+            const int gy = ry < 0 || ry >= n1
+                               ? link_coord(ry < 0 ? 0 : n1 - 1, ry < 0 ? -1 : 1, n1, g.bc_lo[1], g.bc_hi[1], &w)
+                               : ry;
+            if (gx >= 0 && gy >= 0) {
+                ring_slot = sy * W + sx;
+                ring_col = (int64_t)gx + (int64_t)n0 * gy;
+            }
+        }
     }
-    const float cs = g.c2 * Sc;
-    float fs[7];
-    fs[0] = g.two_w0 * Sc - f[0];
-    for (int d = 0; d < 3; ++d) {
-        fs[1 + 2 * d] = cs + K[d] - f[1 + 2 * d];
-        fs[2 + 2 * d] = cs - K[d] - f[2 + 2 * d];
+
+    // planes z0 - 1 (products only), z0 and z0 + 1
+    Node cur, nxt;
+    float azm[3] = {0.f, 0.f, 0.f};  // A^{02}, A^{12}, A^{22} at z - 1
+    {
+        int w = 0;
+        const int zm0 = link_coord(z0, -1, n2, g.bc_lo[2], g.bc_hi[2], &w);
+        if (active && zm0 >= 0) {
+            Node v;
+            load_node(fin, T, N, col + (int64_t)zm0 * plane, v);
+            azm[0] = v.a[4];
+            azm[1] = v.a[5];
+            azm[2] = v.a[2];
+        }
+        if (active) load_node(fin, T, N, col + (int64_t)z0 * plane, cur);
+        else zero_node(cur);
+        const int zp0 = link_coord(z0, +1, n2, g.bc_lo[2], g.bc_hi[2], &w);
+        if (active && zp0 >= 0) load_node(fin, T, N, col + (int64_t)zp0 * plane, nxt);
+        else zero_node(nxt);
     }
-    fout[n] = fs[0];
-    for (int d = 0; d < 3; ++d) {
-        const int lp = 1 + 2 * d, lm = 2 + 2 * d;
-        // +e_d population: to the neighbour, or reflected into -e_d here
-        if (j[d][0] >= 0) fout[lp * N + nb[d][0]] = fs[lp];
-        else fout[lm * N + n] = bounce_rule(w[d][0], g.damp, fs[lp], fs[lm]);
-        if (j[d][1] >= 0) fout[lm * N + nb[d][1]] = fs[lm];
-        else fout[lp * N + n] = bounce_rule(w[d][1], g.damp, fs[lm], fs[lp]);
+
+    int buf = 0;
+    for (int z = z0; z < z1; ++z, buf ^= 1) {
+        int wz_p = 0, wz_m = 0;
+        const int jz_p = link_coord(z, +1, n2, g.bc_lo[2], g.bc_hi[2], &wz_p);
+        const int jz_m = link_coord(z, -1, n2, g.bc_lo[2], g.bc_hi[2], &wz_m);
+        // stage this plane's products for the axis-0/1 neighbours
+        if (active) {
+            sA[buf][0][my] = cur.a[0];
+            sA[buf][1][my] = cur.a[1];
+            sA[buf][2][my] = cur.a[3];
+            sA[buf][3][my] = cur.a[4];
+            sA[buf][4][my] = cur.a[5];
+        }
+        if (ring_slot >= 0) {
+            const int64_t rn = ring_col + (int64_t)z * plane;
+            float s = 0.f;
+#pragma unroll
+            for (int l = 0; l < 7; ++l) s += fin[l * N + rn];
+            sA[buf][0][ring_slot] = T[0 * N + rn] * s;
+            sA[buf][1][ring_slot] = T[1 * N + rn] * s;
+            sA[buf][2][ring_slot] = T[3 * N + rn] * s;
+            sA[buf][3][ring_slot] = T[4 * N + rn] * s;
+            sA[buf][4][ring_slot] = T[5 * N + rn] * s;
+        }
+        __syncthreads();
+        if (active) {
+            const float* L0 = sA[buf][0];
+            const float* L1 = sA[buf][1];
+            const float* L2 = sA[buf][2];
+            const float* L3 = sA[buf][3];
+            const float* L4 = sA[buf][4];
+            // axis 0 neighbours: A^{00}, A^{10} = A^{01}, A^{20} = A^{02}
+            const float x00p = jx_p >= 0 ? L0[my + 1] : mirror(wx_p, cur.a[0]);
+            const float x00m = jx_m >= 0 ? L0[my - 1] : mirror(wx_m, cur.a[0]);
+            const float x10p = jx_p >= 0 ? L2[my + 1] : mirror(wx_p, cur.a[3]);
+            const float x10m = jx_m >= 0 ? L2[my - 1] : mirror(wx_m, cur.a[3]);
+            const float x20p = jx_p >= 0 ? L3[my + 1] : mirror(wx_p, cur.a[4]);
+            const float x20m = jx_m >= 0 ? L3[my - 1] : mirror(wx_m, cur.a[4]);
+            // axis 1 neighbours: A^{01}, A^{11}, A^{21} = A^{12}
+            const float y01p = jy_p >= 0 ? L2[my + W] : mirror(wy_p, cur.a[3]);
+            const float y01m = jy_m >= 0 ? L2[my - W] : mirror(wy_m, cur.a[3]);
+            const float y11p = jy_p >= 0 ? L1[my + W] : mirror(wy_p, cur.a[1]);
+            const float y11m = jy_m >= 0 ? L1[my - W] : mirror(wy_m, cur.a[1]);
+            const float y21p = jy_p >= 0 ? L4[my + W] : mirror(wy_p, cur.a[5]);
+            const float y21m = jy_m >= 0 ? L4[my - W] : mirror(wy_m, cur.a[5]);
+            // axis 2 neighbours (registers): A^{02}, A^{12}, A^{22}
+            const float z02p = jz_p >= 0 ? nxt.a[4] : mirror(wz_p, cur.a[4]);
+            const float z02m = jz_m >= 0 ? azm[0] : mirror(wz_m, cur.a[4]);
+            const float z12p = jz_p >= 0 ? nxt.a[5] : mirror(wz_p, cur.a[5]);
+            const float z12m = jz_m >= 0 ? azm[1] : mirror(wz_m, cur.a[5]);
+            const float z22p = jz_p >= 0 ? nxt.a[2] : mirror(wz_p, cur.a[2]);
+            const float z22m = jz_m >= 0 ? azm[2] : mirror(wz_m, cur.a[2]);
+            const float S = cur.S;
+            const float K0 = (cur.f[1] - cur.f[2]) - cur.t[6] * S -
+                             0.25f * (((x00p - x00m) + (y01p - y01m)) + (z02p - z02m));
+            const float K1 = (cur.f[3] - cur.f[4]) - cur.t[7] * S -
+                             0.25f * (((x10p - x10m) + (y11p - y11m)) + (z12p - z12m));
+            const float K2 = (cur.f[5] - cur.f[6]) - cur.t[8] * S -
+                             0.25f * (((x20p - x20m) + (y21p - y21m)) + (z22p - z22m));
+            const float cs = g.c2 * S;
+            const float fs0 = g.two_w0 * S - cur.f[0];
+            const float fs1 = cs + K0 - cur.f[1], fs2 = cs - K0 - cur.f[2];
+            const float fs3 = cs + K1 - cur.f[3], fs4 = cs - K1 - cur.f[4];
+            const float fs5 = cs + K2 - cur.f[5], fs6 = cs - K2 - cur.f[6];
+            const int64_t n = col + (int64_t)z * plane;
+            fout[n] = fs0;
+            if (jx_p >= 0) fout[1 * N + n + (jx_p - x)] = fs1;
+            else fout[2 * N + n] = bounce_rule(wx_p, g.damp, fs1, fs2);
+            if (jx_m >= 0) fout[2 * N + n + (jx_m - x)] = fs2;
+            else fout[1 * N + n] = bounce_rule(wx_m, g.damp, fs2, fs1);
+            if (jy_p >= 0) fout[3 * N + n + (int64_t)(jy_p - y) * n0] = fs3;
+            else fout[4 * N + n] = bounce_rule(wy_p, g.damp, fs3, fs4);
+            if (jy_m >= 0) fout[4 * N + n + (int64_t)(jy_m - y) * n0] = fs4;
+            else fout[3 * N + n] = bounce_rule(wy_m, g.damp, fs4, fs3);
+            if (jz_p >= 0) fout[5 * N + col + (int64_t)jz_p * plane] = fs5;
+            else fout[6 * N + n] = bounce_rule(wz_p, g.damp, fs5, fs6);
+            if (jz_m >= 0) fout[6 * N + col + (int64_t)jz_m * plane] = fs6;
+            else fout[5 * N + n] = bounce_rule(wz_m, g.damp, fs6, fs5);
+        }
+        // advance one plane: z becomes z - 1, z + 1 becomes z, load z + 2
+        azm[0] = cur.a[4];
+        azm[1] = cur.a[5];
+        azm[2] = cur.a[2];
+        cur = nxt;
+        if (z + 1 < z1) {
+            int w = 0;
+            const int zq = jz_p >= 0 ? link_coord(jz_p, +1, n2, g.bc_lo[2], g.bc_hi[2], &w) : -1;
+            if (active && zq >= 0) load_node(fin, T, N, col + (int64_t)zq * plane, nxt);
+            else zero_node(nxt);
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* S, float* fout,
+hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* fout,
                                hipStream_t st) {
-    const unsigned blocks = (unsigned)((g.N + kBS - 1) / kBS);
-    hipLaunchKernelGGL(general_s_kernel, dim3(blocks), dim3(kBS), 0, st, g, pr, fin, S);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(general_step_kernel, dim3(blocks), dim3(kBS), 0, st, g, fin, S, fout);
+    const bool wide = g.n0 > 32;
+    const int tx = wide ? 64 : 32, ty = kGT / tx;
+    GenPlan plan;
+    plan.ntx = (g.n0 + tx - 1) / tx;
+    plan.nty = (g.n1 + ty - 1) / ty;
+    plan.lz = 16;
+    const int64_t tiles = (int64_t)plan.ntx * plan.nty * ((g.n2 + plan.lz - 1) / plan.lz);
+    if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (wide)
+        hipLaunchKernelGGL(general_march_kernel<64>, dim3((unsigned)tiles), dim3(kGT), 0, st, g, pr, plan, fin, fout);
+    else
+        hipLaunchKernelGGL(general_march_kernel<32>, dim3((unsigned)tiles), dim3(kGT), 0, st, g, pr, plan, fin, fout);
     return hipGetLastError();
 }
 

@@ -27,16 +27,22 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def duct(n=(12, 10, 16)):
+def duct(n=(12, 10, 16), periodic1=False):
     geom = W.general_duct(n=n)
+    if periodic1:  # axis 1 periodic (the lattice problem is valid for any metric)
+        geom["bc_lo"] = ("bounceback", "periodic", "bounceback")
+        geom["bc_hi"] = ("bounceback", "periodic", "fixed")
     return dict(geom, coeffs=W.general_coefficients(geom))
 
 
-@pytest.mark.parametrize("n", [(12, 10, 16), (33, 7, 20)])
-def test_general_duct_matches_oracle(n):
-    geom = duct(n)
+# tile widths 32 and 64, several axis-0 tiles and partial axis-1 tiles,
+# a periodic axis (ring nodes wrap) and a fixed wall
+@pytest.mark.parametrize("n,periodic1", [((12, 10, 16), False), ((33, 7, 20), False), ((70, 9, 12), False),
+                                         ((20, 12, 17), True)])
+def test_general_duct_matches_oracle(n, periodic1):
+    geom = duct(n, periodic1)
     N = W.num_nodes(geom)
-    say("general duct", n)
+    say("general duct", n, "periodic axis 1" if periodic1 else "")
     o = oracle.Oracle(geom)
     g = lbw.Geometry(geom)
     t = g.table()
