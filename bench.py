@@ -150,8 +150,7 @@ def main():
     else:
         sim.geometry.set_step_config(*(int(v) for v in args.launch.split(",")))
         tuned_us = float("nan")
-    # the general kernel's fixed shape: 64 x 4 (or 32 x 8) tiles, 16 planes, a workgroup per tile
-    tile = ((64, 4) if geom["n"][0] > 32 else (32, 8)) + (16, 0) if general else g.step_config()
+    tile = g.step_config()  # the general kernel: its default shape, one workgroup per tile
     log("bench: %s, %d nodes, warmup %d, steps %d, launch shape %s (tuner %.2f us)" % (w["name"], N, args.warmup,
                                                                                    args.steps, tile, tuned_us))
     sim.step(args.warmup)

@@ -109,8 +109,8 @@ int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_
  * Gamma^0, Gamma^1, Gamma^2 (Gamma^i = Gamma^i_jk G^jk).  They are converted
  * to lattice units as in lbw_make_geometry and kept per node; such a
  * geometry is stepped by a per-node kernel that reads 36 coefficient bytes
- * per node, takes no step configuration or autotuning, and cannot join a
- * batch.  Waits for the stream.  Errors: as lbw_make_geometry, plus
+ * per node, takes the shapes of lbw_set_step_config listed there but no
+ * autotuning, and cannot join a batch.  Waits for the stream.  Errors: as lbw_make_geometry, plus
  * LBW_EINVAL for another kind, NULL metric, a non-finite value or
  * sqrt(g) <= 0. */
 int lbw_make_geometry_general(const lbw_geometry_desc* desc, const double* metric, void* stream,
@@ -147,8 +147,10 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max);
  * is 256 or 512; chunk_z >= 1 planes per tile along axis 2; blocks:
  * persistent grid size, rounded down to a multiple of 8 (0 = one full wave
  * of resident workgroups).  Used by lbw_autotune and by tests.
- * Errors: LBW_EINVAL for a 2-D or LBW_GENERAL geometry or out-of-range
- * values. */
+ * A geometry given by its metric (LBW_GENERAL) has its own kernel: tile
+ * 32 x 8 or 64 x 4, any chunk_z, blocks 0 (one workgroup per tile; default
+ * 64 x 4 when n0 > 32, else 32 x 8, chunk 16).
+ * Errors: LBW_EINVAL for a 2-D geometry or out-of-range values. */
 int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks);
 int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks);
 

@@ -282,6 +282,11 @@ int lbw_make_geometry_general(const lbw_geometry_desc* desc, const double* metri
     }
     g->dev = lbw::make_geomdev(d, g->tab32, g->tab64 + 9 * N);
     g->dev.sg_node = 1;
+    {
+        const int tx = g->dev.n0 > 32 ? 64 : 32;
+        g->plan = lbw::make_march_plan(g->dev, tx, 256 / tx, 16, 8);
+        g->plan.blocks = (int)g->plan.tiles;
+    }
     *out = g;
     return LBW_OK;
 }
@@ -355,8 +360,16 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max) {
 
 int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks) {
     if (!g) return fail(LBW_EINVAL, "geometry is NULL");
-    if (g->dev.dim != 3 || g->general)
-        return fail(LBW_EINVAL, "step configuration applies to built-in 3-D geometries");
+    if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
+    if (g->general) {
+        // general kernel: 256-thread tiles 32 x 8 or 64 x 4, one workgroup per tile
+        if (!((tile_x == 32 && tile_y == 8) || (tile_x == 64 && tile_y == 4)) || chunk_z < 1 || blocks != 0)
+            return fail(LBW_EINVAL, "geometry given by its metric: tile 32 x 8 or 64 x 4, chunk_z >= 1, blocks 0");
+        g->plan = lbw::make_march_plan(g->dev, tile_x, tile_y, chunk_z, 8);
+        g->plan.blocks = (int)g->plan.tiles;
+        g->plan_version += 1;
+        return LBW_OK;
+    }
     if (!lbw::march_shape_ok(tile_x, tile_y))
         return fail(LBW_EINVAL, "tile %d x %d: tile_x must be 16, 32 or 64 and tile_x * tile_y 256 or 512", tile_x,
                     tile_y);
@@ -374,8 +387,7 @@ int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, i
 
 int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks) {
     if (!g) return fail(LBW_EINVAL, "geometry is NULL");
-    if (g->dev.dim != 3 || g->general)
-        return fail(LBW_EINVAL, "step configuration applies to built-in 3-D geometries");
+    if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
     if (tile_x) *tile_x = g->plan.tx;
     if (tile_y) *tile_y = g->plan.ty;
     if (chunk_z) *chunk_z = g->plan.lz;
@@ -429,7 +441,8 @@ hipError_t launch_one(lbw_state* s, const lbw::ProbeArgs& pr, int from, hipStrea
         const hipError_t e = lbw::launch_sources(s->d_src, s->n_src, s->d_tcount, s->f[from], st);
         if (e != hipSuccess) return e;
     }
-    if (s->g->general) return lbw::launch_step_general(s->g->dev, pr, s->f[from], s->f[1 - from], st);
+    if (s->g->general)
+        return lbw::launch_step_general(s->g->dev, pr, s->g->plan, s->f[from], s->f[1 - from], st);
     if (s->g->dev.dim == 3)
         return lbw::launch_step_march(s->g->dev, pr, s->g->plan, s->f[from], s->f[1 - from], st);
     return lbw::launch_step(s->g->dev, pr, s->f[from], s->f[1 - from], st);

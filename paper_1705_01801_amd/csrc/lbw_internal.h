@@ -76,9 +76,11 @@ struct ProbeArgs {
 };
 hipError_t launch_step(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* fout, hipStream_t st);
 // One step of a geometry given by its metric (3-D, per-node coefficients),
-// z-marching tiles; probes recorded as in the other step kernels.
-hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* fout,
-                               hipStream_t st);
+// z-marching tiles (plan.tx x plan.ty = 256 threads, plan.lz planes, one
+// workgroup per tile); probes recorded as in the other step kernels.
+struct MarchPlan;
+hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
+                               float* fout, hipStream_t st);
 
 // Launch shape of the z-marching D3Q7 kernel.
 struct MarchPlan {

@@ -17,11 +17,11 @@
 // workgroup of 256 threads owns a TX x TY tile of (axis 0, axis 1) columns
 // and walks a chunk of planes along axis 2.  A thread keeps its column's
 // populations, coefficients and the axis-2 products A^{d2} of planes z-1, z
-// and z+1 in registers (plane z+1 is loaded while plane z is computed); the
+// and z+1 in registers (plane z+2 is loaded while plane z is computed); the
 // five products the axis-0 and axis-1 neighbours need (A^{00}, A^{11},
 // A^{01}, A^{02}, A^{12}) are staged in LDS for the tile and a one-node ring
 // (two plane slots, one barrier per plane), the ring nodes' populations and
-// coefficients loaded by the first 2 TX + 2 TY threads.  Workgroup 0 records
+// coefficients loaded one plane ahead by the first 2 TX + 2 TY threads.  Workgroup 0 records
 // the probes of time t before any population is written and advances the
 // step counter.
 #include "lbw_internal.h"
@@ -172,12 +172,34 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
         if (active && zp0 >= 0) load_node(fin, T, N, col + (int64_t)zp0 * plane, nxt);
         else zero_node(nxt);
     }
+    // ring node of plane z: populations and the five coefficient planes the
+    // neighbours' products use (loaded one plane ahead)
+    float rf[7], rt[5];
+    auto load_ring = [&](int zz) {
+        const int64_t rn = ring_col + (int64_t)zz * plane;
+#pragma unroll
+        for (int l = 0; l < 7; ++l) rf[l] = fin[l * N + rn];
+        rt[0] = T[0 * N + rn];
+        rt[1] = T[1 * N + rn];
+        rt[2] = T[3 * N + rn];
+        rt[3] = T[4 * N + rn];
+        rt[4] = T[5 * N + rn];
+    };
+    if (ring_slot >= 0) load_ring(z0);
+    Node nn;  // plane z + 2
 
     int buf = 0;
     for (int z = z0; z < z1; ++z, buf ^= 1) {
         int wz_p = 0, wz_m = 0;
         const int jz_p = link_coord(z, +1, n2, g.bc_lo[2], g.bc_hi[2], &wz_p);
         const int jz_m = link_coord(z, -1, n2, g.bc_lo[2], g.bc_hi[2], &wz_m);
+        // plane z + 2 of the own column, consumed one plane later
+        if (z + 1 < z1) {
+            int w = 0;
+            const int zq = jz_p >= 0 ? link_coord(jz_p, +1, n2, g.bc_lo[2], g.bc_hi[2], &w) : -1;
+            if (active && zq >= 0) load_node(fin, T, N, col + (int64_t)zq * plane, nn);
+            else zero_node(nn);
+        }
         // stage this plane's products for the axis-0/1 neighbours
         if (active) {
             sA[buf][0][my] = cur.a[0];
@@ -187,15 +209,12 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
             sA[buf][4][my] = cur.a[5];
         }
         if (ring_slot >= 0) {
-            const int64_t rn = ring_col + (int64_t)z * plane;
             float s = 0.f;
 #pragma unroll
-            for (int l = 0; l < 7; ++l) s += fin[l * N + rn];
-            sA[buf][0][ring_slot] = T[0 * N + rn] * s;
-            sA[buf][1][ring_slot] = T[1 * N + rn] * s;
-            sA[buf][2][ring_slot] = T[3 * N + rn] * s;
-            sA[buf][3][ring_slot] = T[4 * N + rn] * s;
-            sA[buf][4][ring_slot] = T[5 * N + rn] * s;
+            for (int l = 0; l < 7; ++l) s += rf[l];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sA[buf][k][ring_slot] = rt[k] * s;
+            if (z + 1 < z1) load_ring(z + 1);
         }
         __syncthreads();
         if (active) {
@@ -257,28 +276,22 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
         azm[1] = cur.a[5];
         azm[2] = cur.a[2];
         cur = nxt;
-        if (z + 1 < z1) {
-            int w = 0;
-            const int zq = jz_p >= 0 ? link_coord(jz_p, +1, n2, g.bc_lo[2], g.bc_hi[2], &w) : -1;
-            if (active && zq >= 0) load_node(fin, T, N, col + (int64_t)zq * plane, nxt);
-            else zero_node(nxt);
-        }
+        nxt = nn;
     }
 }
 
 }  // namespace
 
-hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* fout,
-                               hipStream_t st) {
-    const bool wide = g.n0 > 32;
-    const int tx = wide ? 64 : 32, ty = kGT / tx;
+hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& mp, const float* fin,
+                               float* fout, hipStream_t st) {
+    if (!((mp.tx == 32 && mp.ty == 8) || (mp.tx == 64 && mp.ty == 4)) || mp.lz < 1) return hipErrorInvalidValue;
     GenPlan plan;
-    plan.ntx = (g.n0 + tx - 1) / tx;
-    plan.nty = (g.n1 + ty - 1) / ty;
-    plan.lz = 16;
+    plan.ntx = (g.n0 + mp.tx - 1) / mp.tx;
+    plan.nty = (g.n1 + mp.ty - 1) / mp.ty;
+    plan.lz = mp.lz;
     const int64_t tiles = (int64_t)plan.ntx * plan.nty * ((g.n2 + plan.lz - 1) / plan.lz);
     if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (wide)
+    if (mp.tx == 64)
         hipLaunchKernelGGL(general_march_kernel<64>, dim3((unsigned)tiles), dim3(kGT), 0, st, g, pr, plan, fin, fout);
     else
         hipLaunchKernelGGL(general_march_kernel<32>, dim3((unsigned)tiles), dim3(kGT), 0, st, g, pr, plan, fin, fout);

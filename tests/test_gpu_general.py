@@ -36,15 +36,19 @@ def duct(n=(12, 10, 16), periodic1=False):
 
 
 # tile widths 32 and 64, several axis-0 tiles and partial axis-1 tiles,
-# a periodic axis (ring nodes wrap) and a fixed wall
-@pytest.mark.parametrize("n,periodic1", [((12, 10, 16), False), ((33, 7, 20), False), ((70, 9, 12), False),
-                                         ((20, 12, 17), True)])
-def test_general_duct_matches_oracle(n, periodic1):
+# a periodic axis (ring nodes wrap), a fixed wall, chunks of 1 to 32 planes
+@pytest.mark.parametrize("n,periodic1,shape", [((12, 10, 16), False, None), ((33, 7, 20), False, None),
+                                               ((70, 9, 12), False, (64, 4, 5)), ((20, 12, 17), True, None),
+                                               ((40, 11, 9), False, (32, 8, 1)), ((40, 11, 9), True, (64, 4, 32))])
+def test_general_duct_matches_oracle(n, periodic1, shape):
     geom = duct(n, periodic1)
     N = W.num_nodes(geom)
-    say("general duct", n, "periodic axis 1" if periodic1 else "")
+    say("general duct", n, "periodic axis 1" if periodic1 else "", shape)
     o = oracle.Oracle(geom)
     g = lbw.Geometry(geom)
+    if shape:
+        g.set_step_config(*shape)
+        assert g.step_config()[:3] == shape
     t = g.table()
     assert np.abs(t[0:6] - o.Mhat).max() <= 1e-13 * max(1.0, np.abs(o.Mhat).max())
     assert np.abs(t[6:9] - o.Gamh).max() <= 1e-13 * max(1.0, np.abs(o.Gamh).max())
@@ -129,7 +133,9 @@ def test_general_rejections():
         lbw.Geometry(dict(geom, coeffs=bad))
     g = lbw.Geometry(geom)
     with pytest.raises(lbw.LbwError):
-        g.set_step_config(32, 8, 16)
+        g.set_step_config(16, 16, 16)
+    with pytest.raises(lbw.LbwError):
+        g.set_step_config(32, 8, 16, 64)
     sim = lbw.Simulation(g, np.zeros(N))
     with pytest.raises(lbw.LbwError):
         sim.autotune(reps=2)
