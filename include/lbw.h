@@ -110,9 +110,10 @@ int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_
  * to lattice units as in lbw_make_geometry and kept per node; such a
  * geometry is stepped by a per-node kernel that reads 36 coefficient bytes
  * per node, takes the shapes of lbw_set_step_config listed there but no
- * autotuning, and cannot join a batch.  Waits for the stream.  Errors: as lbw_make_geometry, plus
- * LBW_EINVAL for another kind, NULL metric, a non-finite value or
- * sqrt(g) <= 0. */
+ * autotuning, and cannot join a batch.  Waits for the stream.  Errors: as
+ * lbw_make_geometry, plus LBW_EINVAL for another kind, NULL metric, a
+ * non-finite value, sqrt(g) <= 0, or 36 N >= 2^31 bytes of coefficients
+ * (at most 59,652,323 nodes). */
 int lbw_make_geometry_general(const lbw_geometry_desc* desc, const double* metric, void* stream,
                               lbw_geometry_t* out);
 

@@ -234,6 +234,10 @@ int lbw_make_geometry_general(const lbw_geometry_desc* desc, const double* metri
     if (!metric) return fail(LBW_EINVAL, "metric is NULL");
     const lbw_geometry_desc d = lbw::normalised(*desc);
     const int64_t N = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    // the kernel addresses the nine coefficient planes with 32-bit byte offsets
+    if (4LL * lbw::kGenF32 * N > 2147483647LL)
+        return fail(LBW_EINVAL, "too many nodes (%lld) for per-node coefficients: 36 N bytes must stay below 2^31",
+                    (long long)N);
     for (int64_t i = 0; i < lbw::kGenF64 * N; ++i)
         if (!std::isfinite(metric[i])) return fail(LBW_EINVAL, "non-finite metric value (plane %lld)", (long long)(i / N));
     for (int64_t n = 0; n < N; ++n)

@@ -30,6 +30,18 @@ namespace lbw {
 namespace {
 
 constexpr int kGT = 256;  // threads per workgroup
+constexpr int kXcd = 8;   // tiles are dealt to XCDs in contiguous ranges
+
+// Buffer loads with 32-bit byte offsets: an offset of kOff lies beyond every
+// buffer (the library keeps 4 Q N and 36 N below 2^31), so a disabled lane
+// reads 0 without a branch around the load.
+constexpr uint32_t kOff = 0x80000000u;
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
 
 __device__ inline float mirror(int wall, float own) { return wall == LBW_BC_FIXED ? -own : own; }
 
@@ -38,7 +50,7 @@ __device__ inline float bounce_rule(int wall, float damp, float out_l, float own
 }
 
 struct GenPlan {
-    int ntx, nty, lz;
+    int ntx, nty, nch, lz;
 };
 
 // one node's populations, coefficients, S and the six products c^2 Mhat^m S
@@ -49,29 +61,21 @@ struct Node {
     float a[6];
 };
 
-__device__ inline void load_node(const float* __restrict__ fin, const float* __restrict__ T, int64_t N, int64_t n,
-                                 Node& v) {
+// node at byte offset nb (4 n), or all zeros when off
+__device__ inline void load_node(__amdgpu_buffer_rsrc_t rf, __amdgpu_buffer_rsrc_t rt, uint32_t N4, bool on,
+                                 uint32_t nb, Node& v) {
+    const uint32_t base = on ? nb : kOff;
     float s = 0.f;
 #pragma unroll
     for (int l = 0; l < 7; ++l) {
-        v.f[l] = fin[l * N + n];
+        v.f[l] = bld(rf, base + (uint32_t)l * N4);
         s += v.f[l];
     }
 #pragma unroll
-    for (int m = 0; m < 9; ++m) v.t[m] = T[m * N + n];
+    for (int m = 0; m < 9; ++m) v.t[m] = bld(rt, base + (uint32_t)m * N4);
     v.S = s;
 #pragma unroll
     for (int m = 0; m < 6; ++m) v.a[m] = v.t[m] * s;
-}
-
-__device__ inline void zero_node(Node& v) {
-#pragma unroll
-    for (int l = 0; l < 7; ++l) v.f[l] = 0.f;
-#pragma unroll
-    for (int m = 0; m < 9; ++m) v.t[m] = 0.f;
-    v.S = 0.f;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) v.a[m] = 0.f;
 }
 
 template <int TX>
@@ -82,7 +86,7 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
     constexpr int W = TX + 2;
     constexpr int SLOTS = (TY + 2) * W;
     // LDS products per slot: 0 A^{00}, 1 A^{11}, 2 A^{01}, 3 A^{02}, 4 A^{12}
-    __shared__ float sA[2][5][SLOTS];
+    __shared__ float sA[2][5][SLOTS + 1];  // + a sink slot
 
     if (blockIdx.x == 0) {
         const int64_t t = *(volatile const int64_t*)pr.tcount;
@@ -102,7 +106,13 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
     const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
     const int64_t N = g.N, plane = (int64_t)n0 * n1;
     const float* __restrict__ T = g.tab;
-    const int b = blockIdx.x;
+    // XCD-contiguous tiles: block b runs on XCD b mod 8 and takes tile
+    // (b mod 8) per + b / 8 of that XCD's range, so tiles sharing ring nodes
+    // and chunk-boundary planes share an L2; blocks past the last tile exit
+    // (block 0, which records the probes, always has tile 0)
+    const int per = (int)(((int64_t)plan.ntx * plan.nty * plan.nch + kXcd - 1) / kXcd);
+    const int b = (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
+    if (b >= plan.ntx * plan.nty * plan.nch) return;
     const int tx = b % plan.ntx, ty = (b / plan.ntx) % plan.nty, ch = b / (plan.ntx * plan.nty);
     const int x0 = tx * TX, y0 = ty * TY, z0 = ch * plan.lz;
     const int z1 = min(z0 + plan.lz, n2);
@@ -112,6 +122,9 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
     const bool active = lx < wdt && ly < hgt;
     const int64_t col = (int64_t)x + (int64_t)n0 * y;
     const int my = (ly + 1) * W + lx + 1;
+    const uint32_t N4 = (uint32_t)N * 4u, plane4 = (uint32_t)plane * 4u, col4 = (uint32_t)col * 4u;
+    const __amdgpu_buffer_rsrc_t rf = rsrc(fin, 7u * N4);
+    const __amdgpu_buffer_rsrc_t rt = rsrc(T, 9u * N4);
 
     int wx_p = 0, wx_m = 0, wy_p = 0, wy_m = 0;
     const int jx_p = link_coord(x, +1, n0, g.bc_lo[0], g.bc_hi[0], &wx_p);
@@ -159,33 +172,30 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
     {
         int w = 0;
         const int zm0 = link_coord(z0, -1, n2, g.bc_lo[2], g.bc_hi[2], &w);
-        if (active && zm0 >= 0) {
-            Node v;
-            load_node(fin, T, N, col + (int64_t)zm0 * plane, v);
-            azm[0] = v.a[4];
-            azm[1] = v.a[5];
-            azm[2] = v.a[2];
-        }
-        if (active) load_node(fin, T, N, col + (int64_t)z0 * plane, cur);
-        else zero_node(cur);
+        Node v;
+        load_node(rf, rt, N4, active && zm0 >= 0, col4 + (uint32_t)zm0 * plane4, v);
+        azm[0] = v.a[4];
+        azm[1] = v.a[5];
+        azm[2] = v.a[2];
+        load_node(rf, rt, N4, active, col4 + (uint32_t)z0 * plane4, cur);
         const int zp0 = link_coord(z0, +1, n2, g.bc_lo[2], g.bc_hi[2], &w);
-        if (active && zp0 >= 0) load_node(fin, T, N, col + (int64_t)zp0 * plane, nxt);
-        else zero_node(nxt);
+        load_node(rf, rt, N4, active && zp0 >= 0, col4 + (uint32_t)zp0 * plane4, nxt);
     }
     // ring node of plane z: populations and the five coefficient planes the
     // neighbours' products use (loaded one plane ahead)
-    float rf[7], rt[5];
+    float rfv[7], rtv[5];
+    const uint32_t ring4 = (uint32_t)ring_col * 4u;
     auto load_ring = [&](int zz) {
-        const int64_t rn = ring_col + (int64_t)zz * plane;
+        const uint32_t base = ring_slot >= 0 ? ring4 + (uint32_t)zz * plane4 : kOff;
 #pragma unroll
-        for (int l = 0; l < 7; ++l) rf[l] = fin[l * N + rn];
-        rt[0] = T[0 * N + rn];
-        rt[1] = T[1 * N + rn];
-        rt[2] = T[3 * N + rn];
-        rt[3] = T[4 * N + rn];
-        rt[4] = T[5 * N + rn];
+        for (int l = 0; l < 7; ++l) rfv[l] = bld(rf, base + (uint32_t)l * N4);
+        rtv[0] = bld(rt, base + 0u * N4);
+        rtv[1] = bld(rt, base + 1u * N4);
+        rtv[2] = bld(rt, base + 3u * N4);
+        rtv[3] = bld(rt, base + 4u * N4);
+        rtv[4] = bld(rt, base + 5u * N4);
     };
-    if (ring_slot >= 0) load_ring(z0);
+    load_ring(z0);
     Node nn;  // plane z + 2
 
     int buf = 0;
@@ -194,11 +204,10 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
         const int jz_p = link_coord(z, +1, n2, g.bc_lo[2], g.bc_hi[2], &wz_p);
         const int jz_m = link_coord(z, -1, n2, g.bc_lo[2], g.bc_hi[2], &wz_m);
         // plane z + 2 of the own column, consumed one plane later
-        if (z + 1 < z1) {
+        {
             int w = 0;
-            const int zq = jz_p >= 0 ? link_coord(jz_p, +1, n2, g.bc_lo[2], g.bc_hi[2], &w) : -1;
-            if (active && zq >= 0) load_node(fin, T, N, col + (int64_t)zq * plane, nn);
-            else zero_node(nn);
+            const int zq = z + 1 < z1 && jz_p >= 0 ? link_coord(jz_p, +1, n2, g.bc_lo[2], g.bc_hi[2], &w) : -1;
+            load_node(rf, rt, N4, active && zq >= 0, col4 + (uint32_t)zq * plane4, nn);
         }
         // stage this plane's products for the axis-0/1 neighbours
         if (active) {
@@ -208,13 +217,14 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
             sA[buf][3][my] = cur.a[4];
             sA[buf][4][my] = cur.a[5];
         }
-        if (ring_slot >= 0) {
+        {
             float s = 0.f;
 #pragma unroll
-            for (int l = 0; l < 7; ++l) s += rf[l];
+            for (int l = 0; l < 7; ++l) s += rfv[l];
+            // lanes without a ring node write a sink slot past the tile
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sA[buf][k][ring_slot] = rt[k] * s;
-            if (z + 1 < z1) load_ring(z + 1);
+            for (int k = 0; k < 5; ++k) sA[buf][k][ring_slot >= 0 ? ring_slot : SLOTS] = rtv[k] * s;
+            load_ring(z + 1 < z1 ? z + 1 : z);
         }
         __syncthreads();
         if (active) {
@@ -288,13 +298,15 @@ hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const Marc
     GenPlan plan;
     plan.ntx = (g.n0 + mp.tx - 1) / mp.tx;
     plan.nty = (g.n1 + mp.ty - 1) / mp.ty;
+    plan.nch = (g.n2 + mp.lz - 1) / mp.lz;
     plan.lz = mp.lz;
-    const int64_t tiles = (int64_t)plan.ntx * plan.nty * ((g.n2 + plan.lz - 1) / plan.lz);
-    if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int64_t tiles = (int64_t)plan.ntx * plan.nty * plan.nch;
+    if (tiles > 0x7fffffffLL - 8) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((tiles + kXcd - 1) / kXcd * kXcd);
     if (mp.tx == 64)
-        hipLaunchKernelGGL(general_march_kernel<64>, dim3((unsigned)tiles), dim3(kGT), 0, st, g, pr, plan, fin, fout);
+        hipLaunchKernelGGL(general_march_kernel<64>, dim3(blocks), dim3(kGT), 0, st, g, pr, plan, fin, fout);
     else
-        hipLaunchKernelGGL(general_march_kernel<32>, dim3((unsigned)tiles), dim3(kGT), 0, st, g, pr, plan, fin, fout);
+        hipLaunchKernelGGL(general_march_kernel<32>, dim3(blocks), dim3(kGT), 0, st, g, pr, plan, fin, fout);
     return hipGetLastError();
 }
 
