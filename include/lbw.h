@@ -149,8 +149,8 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max);
  * persistent grid size, rounded down to a multiple of 8 (0 = one full wave
  * of resident workgroups).  Used by lbw_autotune and by tests.
  * A geometry given by its metric (LBW_GENERAL) has its own kernel: tile
- * 32 x 8 or 64 x 4, any chunk_z, blocks 0 (one workgroup per tile; default
- * 64 x 4 when n0 > 32, else 32 x 8, chunk 16).
+ * 32 x 8, 64 x 4 or 64 x 8, any chunk_z, blocks 0 (one workgroup per tile;
+ * default 64 x 8 when n0 > 32, else 32 x 8, chunk 16).
  * Errors: LBW_EINVAL for a 2-D geometry or out-of-range values. */
 int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks);
 int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks);

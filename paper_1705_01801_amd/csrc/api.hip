@@ -287,8 +287,8 @@ int lbw_make_geometry_general(const lbw_geometry_desc* desc, const double* metri
     g->dev = lbw::make_geomdev(d, g->tab32, g->tab64 + 9 * N);
     g->dev.sg_node = 1;
     {
-        const int tx = g->dev.n0 > 32 ? 64 : 32;
-        g->plan = lbw::make_march_plan(g->dev, tx, 256 / tx, 16, 8);
+        const int tx = g->dev.n0 > 32 ? 64 : 32;  // 64 x 8 or 32 x 8 tiles, 16 planes
+        g->plan = lbw::make_march_plan(g->dev, tx, 8, 16, 8);
         g->plan.blocks = (int)g->plan.tiles;
     }
     *out = g;
@@ -366,9 +366,10 @@ int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, i
     if (!g) return fail(LBW_EINVAL, "geometry is NULL");
     if (g->dev.dim != 3) return fail(LBW_EINVAL, "step configuration applies to 3-D geometries");
     if (g->general) {
-        // general kernel: 256-thread tiles 32 x 8 or 64 x 4, one workgroup per tile
-        if (!((tile_x == 32 && tile_y == 8) || (tile_x == 64 && tile_y == 4)) || chunk_z < 1 || blocks != 0)
-            return fail(LBW_EINVAL, "geometry given by its metric: tile 32 x 8 or 64 x 4, chunk_z >= 1, blocks 0");
+        // general kernel: tiles 32 x 8, 64 x 4 (256 threads) or 64 x 8 (512), one workgroup per tile
+        if (!((tile_x == 32 && tile_y == 8) || (tile_x == 64 && (tile_y == 4 || tile_y == 8))) || chunk_z < 1 ||
+            blocks != 0)
+            return fail(LBW_EINVAL, "geometry given by its metric: tile 32 x 8, 64 x 4 or 64 x 8, chunk_z >= 1, blocks 0");
         g->plan = lbw::make_march_plan(g->dev, tile_x, tile_y, chunk_z, 8);
         g->plan.blocks = (int)g->plan.tiles;
         g->plan_version += 1;

@@ -14,7 +14,7 @@
 // A^{22}; beyond a wall the node's own A is mirrored (odd for fixed walls).
 //
 // Data movement (as the z-marching kernel of the built-in geometries): a
-// workgroup of 256 threads owns a TX x TY tile of (axis 0, axis 1) columns
+// workgroup of NT = 256 or 512 threads owns a TX x TY tile of (axis 0, axis 1) columns
 // and walks a chunk of planes along axis 2.  A thread keeps its column's
 // populations, coefficients and the axis-2 products A^{d2} of planes z-1, z
 // and z+1 in registers (plane z+2 is loaded while plane z is computed); the
@@ -29,7 +29,6 @@
 namespace lbw {
 namespace {
 
-constexpr int kGT = 256;  // threads per workgroup
 constexpr int kXcd = 8;   // tiles are dealt to XCDs in contiguous ranges
 
 // Buffer loads with 32-bit byte offsets: an offset of kOff lies beyond every
@@ -78,11 +77,11 @@ __device__ inline void load_node(__amdgpu_buffer_rsrc_t rf, __amdgpu_buffer_rsrc
     for (int m = 0; m < 6; ++m) v.a[m] = v.t[m] * s;
 }
 
-template <int TX>
-__global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs pr, GenPlan plan,
+template <int TX, int NT>
+__global__ __launch_bounds__(NT) void general_march_kernel(GeomDev g, ProbeArgs pr, GenPlan plan,
                                                             const float* __restrict__ fin,
                                                             float* __restrict__ fout) {
-    constexpr int TY = kGT / TX;
+    constexpr int TY = NT / TX;
     constexpr int W = TX + 2;
     constexpr int SLOTS = (TY + 2) * W;
     // LDS products per slot: 0 A^{00}, 1 A^{11}, 2 A^{01}, 3 A^{02}, 4 A^{12}
@@ -294,7 +293,9 @@ __global__ __launch_bounds__(kGT) void general_march_kernel(GeomDev g, ProbeArgs
 
 hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& mp, const float* fin,
                                float* fout, hipStream_t st) {
-    if (!((mp.tx == 32 && mp.ty == 8) || (mp.tx == 64 && mp.ty == 4)) || mp.lz < 1) return hipErrorInvalidValue;
+    const int nt = mp.tx * mp.ty;
+    if (!((mp.tx == 32 && mp.ty == 8) || (mp.tx == 64 && (mp.ty == 4 || mp.ty == 8))) || mp.lz < 1)
+        return hipErrorInvalidValue;
     GenPlan plan;
     plan.ntx = (g.n0 + mp.tx - 1) / mp.tx;
     plan.nty = (g.n1 + mp.ty - 1) / mp.ty;
@@ -303,10 +304,12 @@ hipError_t launch_step_general(const GeomDev& g, const ProbeArgs& pr, const Marc
     const int64_t tiles = (int64_t)plan.ntx * plan.nty * plan.nch;
     if (tiles > 0x7fffffffLL - 8) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((tiles + kXcd - 1) / kXcd * kXcd);
-    if (mp.tx == 64)
-        hipLaunchKernelGGL(general_march_kernel<64>, dim3(blocks), dim3(kGT), 0, st, g, pr, plan, fin, fout);
+    if (nt == 512)
+        hipLaunchKernelGGL((general_march_kernel<64, 512>), dim3(blocks), dim3(512), 0, st, g, pr, plan, fin, fout);
+    else if (mp.tx == 64)
+        hipLaunchKernelGGL((general_march_kernel<64, 256>), dim3(blocks), dim3(256), 0, st, g, pr, plan, fin, fout);
     else
-        hipLaunchKernelGGL(general_march_kernel<32>, dim3(blocks), dim3(kGT), 0, st, g, pr, plan, fin, fout);
+        hipLaunchKernelGGL((general_march_kernel<32, 256>), dim3(blocks), dim3(256), 0, st, g, pr, plan, fin, fout);
     return hipGetLastError();
 }
 

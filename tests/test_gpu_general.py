@@ -39,7 +39,8 @@ def duct(n=(12, 10, 16), periodic1=False):
 # a periodic axis (ring nodes wrap), a fixed wall, chunks of 1 to 32 planes
 @pytest.mark.parametrize("n,periodic1,shape", [((12, 10, 16), False, None), ((33, 7, 20), False, None),
                                                ((70, 9, 12), False, (64, 4, 5)), ((20, 12, 17), True, None),
-                                               ((40, 11, 9), False, (32, 8, 1)), ((40, 11, 9), True, (64, 4, 32))])
+                                               ((40, 11, 9), False, (32, 8, 1)), ((40, 11, 9), True, (64, 4, 32)),
+                                               ((70, 19, 12), False, (64, 8, 8))])
 def test_general_duct_matches_oracle(n, periodic1, shape):
     geom = duct(n, periodic1)
     N = W.num_nodes(geom)
