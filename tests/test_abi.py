@@ -76,3 +76,44 @@ def test_null_arguments():
     assert L.lbw_make_geometry(None, None, None) == -1
     assert L.lbw_step_n(None, 1) == -1
     assert L.lbw_free_state(None) == 0 and L.lbw_free_geometry(None) == 0
+
+
+def _general_rc(geom, metric):
+    d = lbw.to_desc(geom)
+    h = ctypes.c_void_p()
+    ptr = None if metric is None else metric.ctypes.data
+    rc = lbw.lib().lbw_make_geometry_general(ctypes.byref(d), ptr, None, ctypes.byref(h))
+    return rc, lbw.lib().lbw_last_error().decode(), h
+
+
+def test_general_metric_rejected_on_host():
+    import numpy as np
+    geom = W.general_duct(n=(6, 5, 4))
+    metric = W.general_coefficients(geom)
+    rc, err, h = _rc(geom)                                  # built-in entry point refuses the kind
+    assert rc == -1 and "lbw_make_geometry_general" in err and not h.value
+    rc, err, h = _general_rc(dict(geom, kind="box"), metric)
+    assert rc == -1 and "LBW_GENERAL" in err and not h.value
+    rc, err, h = _general_rc(geom, None)
+    assert rc == -1 and "metric is NULL" in err
+    bad = metric.copy()
+    bad[3, 17] = np.inf
+    rc, err, h = _general_rc(geom, bad)
+    assert rc == -1 and "non-finite" in err and not h.value
+    bad = metric.copy()
+    bad[0, 9] = -1.0
+    rc, err, h = _general_rc(geom, bad)
+    assert rc == -1 and "sqrt(g)" in err and not h.value
+    # 36 N bytes of coefficients must stay below 2^31 (rejected before the
+    # metric is read, so a small array stands in)
+    rc, err, h = _general_rc(dict(geom, n=(1024, 1024, 60)), metric)
+    assert rc == -1 and "per-node coefficients" in err and not h.value
+
+
+def test_source_calls_reject_null():
+    L = lbw.lib()
+    L.lbw_set_sources.restype = ctypes.c_int
+    assert L.lbw_set_sources(None, None, 0, 1.0, 0.1) == -1
+    assert L.lbw_amplitude(None, 0, 1, None) == -1
+    assert L.lbw_batch_set_sources(None, None, None, None, None, 0) == -1
+    assert L.lbw_batch_amplitude(None, 0, 1, None) == -1
