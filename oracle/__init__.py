@@ -72,7 +72,7 @@ def _load():
                                 ctypes.c_int, dp]
         lib.orc_run_driven.argtypes = [gp, dp, dp, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.c_int, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
-                                       ctypes.c_int, ctypes.c_double, ctypes.c_double]
+                                       ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]
         lib.orc_invariant.argtypes = [gp, dp]
         lib.orc_invariant.restype = ctypes.c_double
         lib.orc_pressure.argtypes = [gp, dp, dp, dp]
@@ -160,12 +160,14 @@ class Oracle:
         return self.run(f, n, [])[0]
 
     def run(self, f: np.ndarray, nsteps: int, probes, sources=None, amplitude: float = 0.0, omega: float = 0.0,
-            t0: int = 0):
+            t0: int = 0, flux_axis=None):
         """Advances f in place from time t0; returns (f, trace[nsteps, n_probes])
         where trace[s] is the pressure at each probe at time t0 + s, before
         that step.  With sources (node indices) the pressure
         amplitude * sin(omega t) is imposed at those nodes at every time t
-        before the probes are read (populations at rest at that pressure)."""
+        before the probes are read (populations at rest at that pressure);
+        with flux_axis = a the flux J'_a = amplitude * sin(omega t) is imposed
+        instead (the node keeps its S; the oscillating plate)."""
         assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (self.Q, self.N)
         probes = np.ascontiguousarray(probes, dtype=np.int64).reshape(-1)
         src = np.ascontiguousarray([] if sources is None else sources, dtype=np.int64).reshape(-1)
@@ -174,7 +176,8 @@ class Oracle:
         w = self._workbuf()
         self.lib.orc_run_driven(ctypes.byref(self._g), _ptr(self.Mhat), _ptr(self.Gamh), _ptr(self.sqrtg), _ptr(f),
                                 _ptr(w), int(nsteps), _ptr(probes, ctypes.c_int64), int(probes.size), _ptr(trace),
-                                int(t0), _ptr(src, ctypes.c_int64), int(src.size), float(amplitude), float(omega))
+                                int(t0), _ptr(src, ctypes.c_int64), int(src.size), float(amplitude), float(omega),
+                                0 if flux_axis is None else 1 + int(flux_axis))
         return f, trace
 
     @staticmethod

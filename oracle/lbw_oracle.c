@@ -431,21 +431,35 @@ static double orc_probe_value(const orc_geom* g, const double* f, const double* 
     return s / sqrtg[node];
 }
 
-/* Driven source (Sec. IV.A and IV.C: the pressure imposed at source nodes
- * as a harmonic function of time).  At time t every source node is put at
- * rest at the imposed pressure P = amp sin(omega t): f_0 = w_0 sqrt(g) P,
- * f_l = w sqrt(g) P (the initial-state rule, zero first moment). */
+/* Driven sources (Sec. IV.A and IV.C), imposed at time t on every source
+ * node with v = amp sin(omega t):
+ *  kind 0, pressure: the node is put at rest at P = v, f_0 = w_0 sqrt(g) P,
+ *          f_l = w sqrt(g) P (the initial-state rule, zero first moment);
+ *  kind 1 + a, flux along axis a (the oscillating plate of Sec. IV.A,
+ *          J'_a = v): the node keeps its S = sum_l f_l and is put at the
+ *          corrected equilibrium with sqrt(g) J'_a = sqrt(g) v and the other
+ *          components zero, f_0 = w_0 S, f_{+-a} = w S +- sqrt(g) v / 2,
+ *          the rest w S. */
 static void orc_impose(const orc_geom* g, const double* sqrtg, double* f, int64_t t, const int64_t* src, int ns,
-                       double amp, double omega) {
+                       double amp, double omega, int kind) {
     int d = g->dim, Q = 2 * d + 1;
     int64_t N = orc_nodes(g);
     double c2 = g->c * g->c;
-    double P = amp * sin(omega * (double)t);
+    double v = amp * sin(omega * (double)t);
     for (int i = 0; i < ns; ++i) {
         int64_t n = src[i];
+        double S = 0.0;
+        if (kind > 0)
+            for (int l = 0; l < Q; ++l) S += f[l * N + n];
         for (int l = 0; l < Q; ++l) {
             double w = (l == 0) ? 1.0 - d * c2 : 0.5 * c2;
-            f[l * N + n] = w * sqrtg[n] * P;
+            if (kind == 0) {
+                f[l * N + n] = w * sqrtg[n] * v;
+            } else {
+                double val = w * S;
+                if (l > 0 && orc_axis_of(l) == kind - 1) val += 0.5 * orc_sign_of(l) * sqrtg[n] * v;
+                f[l * N + n] = val;
+            }
         }
     }
 }
@@ -456,13 +470,13 @@ static void orc_impose(const orc_geom* g, const double* sqrtg, double* f, int64_
  * work holds (Q + 1) * N doubles. */
 int orc_run_driven(const orc_geom* g, const double* Mhat, const double* Gamh, const double* sqrtg, double* f,
                    double* work, int64_t nsteps, const int64_t* probes, int np, double* trace, int64_t t0,
-                   const int64_t* src, int ns, double amp, double omega) {
+                   const int64_t* src, int ns, double amp, double omega, int kind) {
     int Q = 2 * g->dim + 1;
     int64_t N = orc_nodes(g);
     double* fs = work;
     double* S = work + (int64_t)Q * N;
     for (int64_t s = 0; s < nsteps; ++s) {
-        if (ns > 0) orc_impose(g, sqrtg, f, t0 + s, src, ns, amp, omega);
+        if (ns > 0) orc_impose(g, sqrtg, f, t0 + s, src, ns, amp, omega, kind);
         for (int p = 0; p < np; ++p) trace[s * np + p] = orc_probe_value(g, f, sqrtg, probes[p]);
         orc_step(g, Mhat, Gamh, f, fs, S);
     }
@@ -472,7 +486,7 @@ int orc_run_driven(const orc_geom* g, const double* Mhat, const double* Gamh, co
 /* Undriven run: as orc_run_driven with no sources. */
 int orc_run(const orc_geom* g, const double* Mhat, const double* Gamh, const double* sqrtg, double* f,
             double* work, int64_t nsteps, const int64_t* probes, int np, double* trace) {
-    return orc_run_driven(g, Mhat, Gamh, sqrtg, f, work, nsteps, probes, np, trace, 0, NULL, 0, 0.0, 0.0);
+    return orc_run_driven(g, Mhat, Gamh, sqrtg, f, work, nsteps, probes, np, trace, 0, NULL, 0, 0.0, 0.0, 0);
 }
 
 /* Scalar invariant sum_x sqrt(g) P = sum_x sum_l f_l (Sec. III, curvilinear

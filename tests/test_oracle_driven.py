@@ -2,9 +2,11 @@
 
 A driven source imposes the pressure C sin(omega t) at chosen nodes at every
 time t, the populations there put at rest at that pressure (Sec. IV.A and
-IV.C, the ring and point sources of the pipe and torus experiments); the
-response intensity is the largest |P| at a probe over a late window of the
-run (the pipe and torus frequency sweeps).  Pins:
+IV.C, the ring and point sources of the pipe and torus experiments); a flux
+source (the oscillating plate of Sec. IV.A) imposes J'_a = C sin(omega t)
+instead, each node keeping its S and taking the equilibrium with that flux;
+the response intensity is the largest |P| at a probe over a late window of
+the run (the pipe and torus frequency sweeps).  Pins:
 
 * a probe on a source node reads C sin(omega t) exactly, on a curvilinear
   grid (sqrt(g) != 1), so the imposed populations carry sqrt(g) and sum to
@@ -23,6 +25,18 @@ run (the pipe and torus frequency sweeps).  Pins:
   switching the drive on leaves behind (measured <= 3.2e-4 of |Z| after 8000
   steps for the frequencies below), against a deviation of order omega for a
   drive applied one step early or late;
+* the same exact steady state for the flux source: the imposition is then
+  the linear map that replaces the source node's populations by w_l times
+  their sum, plus +-C sin(omega t) / 2 on the two links of the driven axis
+  (a sign error, a wrong axis or a drive one step off fails it);
+* a flux drive in a closed undamped geometry conserves sum_l f_l exactly
+  (the node keeps its S), and a plate drive over a whole end plane of the
+  cylinder keeps the field axisymmetric;
+* the plate of the pipe (flux J'_z over the whole z = 0 end of the annulus
+  r in [1, 25]) launches a nearly plane wave: in the continuum a uniform
+  piston in a rigid pipe excites the plane mode alone, so P may vary with r
+  only by the lattice's radial modes (8 % here); a flux imposed without
+  sqrt(g) (uniform sum_l f_l xi_l instead of uniform J'_z) gives 78 %;
 * the intensity rule on the steady sinusoid: within |Z| (1 - omega^2 / 8)
   (integer-time sampling of the crest) and |Z| plus that residual;
 * the radial wave from a driven ring on the polar grid has the radial
@@ -105,11 +119,7 @@ def line_step(f, c, D):
 def steady_phasors(N, c, D, omega, C):
     """Phasor X[7, N] of the periodic steady state, source at node 0."""
     n = 7 * N
-    A = np.empty((n, n))
-    for j in range(n):
-        e = np.zeros(n)
-        e[j] = 1.0
-        A[:, j] = line_step(e.reshape(7, N), c, D).reshape(-1)
+    A = line_operator(N, c, D)
     keep = np.ones(n)
     keep[np.arange(7) * N] = 0.0
     b = np.zeros(n)
@@ -134,6 +144,82 @@ def test_driven_line_reaches_exact_steady_state(omega):
     amp = o.amplitude(tr, T - win, T)
     assert np.all(amp >= np.abs(Z) * (1.0 - omega * omega / 8.0) - resid * np.abs(Z) - 1e-12)
     assert np.all(amp <= np.abs(Z) * (1.0 + resid) + 1e-12)
+
+
+def line_operator(N, c, D):
+    n = 7 * N
+    A = np.empty((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        A[:, j] = line_step(e.reshape(7, N), c, D).reshape(-1)
+    return A
+
+
+def flux_steady_phasors(N, c, D, omega, C):
+    """Phasor X[7, N] of the periodic steady state of the line driven by the
+    flux J'_z = C sin(omega t) at node 0 (sqrt(g) = 1): the imposition maps
+    the node's populations to w_l sum_m f_m and adds +-1/2 C sin(omega t) on
+    the +z / -z links."""
+    n = 7 * N
+    A = line_operator(N, c, D)
+    rows = np.arange(7) * N
+    w = np.array([1.0 - 3.0 * c * c] + [0.5 * c * c] * 6)
+    Pi = np.eye(n)
+    Pi[rows, :] = 0.0
+    Pi[np.ix_(rows, rows)] = w[:, None]
+    b = np.zeros(n)
+    b[5 * N], b[6 * N] = 0.5, -0.5
+    z = np.exp(1j * omega)
+    return np.linalg.solve(z * np.eye(n) - Pi @ A, C * b * z).reshape(7, N)
+
+
+@pytest.mark.parametrize("omega", [0.013, 0.047, 0.09, 0.15])
+def test_flux_driven_line_reaches_exact_steady_state(omega):
+    N, c, D, C, T, win = 40, 0.5, 0.65, 1.3, 8000, 400
+    o = oracle.Oracle(line_geom(N, c, D))
+    probes = [0, 1, N // 2, N - 1]
+    Z = flux_steady_phasors(N, c, D, omega, C)[:, probes].sum(axis=0)
+    f = o.init(np.zeros(o.N))
+    _, tr = o.run(f, T, probes, sources=[0], amplitude=C, omega=omega, flux_axis=2)
+    t = np.arange(T - win, T)
+    steady = np.imag(Z[None, :] * np.exp(1j * omega * t)[:, None])
+    resid = np.abs(tr[T - win:] - steady).max(axis=0) / np.abs(Z)
+    assert resid.max() <= 1.5e-3, resid                       # measured <= 6.9e-4
+    assert np.abs(tr).max() > 0.5                             # the drive is felt
+
+
+def test_flux_drive_conserves_and_keeps_axisymmetry():
+    geom = W.closed_cylinder(scale=16)                        # bounce-back, D = 1, periodic theta
+    n0, n1, n2 = geom["n"]
+    o = oracle.Oracle(geom)
+    plate = list(range(n0 * n1))                              # the whole z = 0 plane
+    P0 = np.random.default_rng(3).uniform(0.0, 1.0, o.N)
+    f = o.init(P0)
+    I0 = f.sum()
+    o.run(f, 300, [], sources=plate, amplitude=0.8, omega=0.06, flux_axis=2)
+    assert abs(f.sum() - I0) <= 1e-12 * I0
+    g = o.init(P0)
+    o.run(g, 300, [], sources=plate, amplitude=0.8, omega=0.06)
+    assert abs(g.sum() - I0) > 1e-2 * I0                      # a pressure drive does not conserve
+    f = o.init(np.zeros(o.N))
+    o.run(f, 300, [], sources=plate, amplitude=0.8, omega=0.06, flux_axis=2)
+    P = o.pressure(f).reshape(n2, n1, n0)
+    assert np.abs(P).max() > 0.5
+    assert np.abs(P - P[:, :1, :]).max() <= 1e-12 * np.abs(P).max()
+
+
+def test_plate_launches_nearly_plane_wave():
+    geom = W.driven_pipe("fixed")
+    n0, n1, n2 = geom["n"]
+    o = oracle.Oracle(geom)
+    f = o.init(np.zeros(o.N))
+    o.run(f, 600, [], sources=list(range(n0 * n1)), amplitude=0.8, omega=0.02, flux_axis=2)
+    P = o.pressure(f).reshape(n2, n1, n0)
+    assert np.abs(P - P[:, :1]).max() <= 1e-12 * np.abs(P).max()
+    Pr = P[:, 0, :]
+    assert np.abs(Pr - Pr.mean(axis=1, keepdims=True)).max() <= 0.2 * np.abs(P).max()
+    assert np.abs(P).max() > 1.0
 
 
 def test_radial_wave_follows_outgoing_hankel_profile():
