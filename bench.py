@@ -101,7 +101,7 @@ def sweep_leg(points):
     from paper_1705_01801_amd import sweep_study
     log("bench: sweep leg, %d drive frequencies batched" % points)
     r = sweep_study.run(points=points, plain=2, ends=("fixed",))
-    m = r["response"]["fixed"]["closed_open"]
+    m = r["response"]["ring"]["fixed"]["closed_open"]
     return {"unit": "sweep points/s", "batched": round(r["batched"]["points_per_s"], 2),
             "plain": round(r["plain"]["points_per_s"], 3), "batched_vs_plain": round(r["batched_vs_plain"], 1),
             "points": r["points"], "steps": r["steps"], "nodes": r["nodes"], "glups": round(r["batched"]["glups"], 2),

@@ -217,17 +217,27 @@ int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out);
 /* Current step count and the device buffer holding the current populations. */
 int lbw_state_info(lbw_state_t s, int64_t* t, float** f_current);
 
-/* Driven sources (Sec. IV.A pipe ring source, Sec. IV.C torus ring and point
- * sources: the pressure imposed at chosen nodes as a harmonic function of
- * time).  From the next queued step on, at every time t (steps since
- * lbw_init) the populations of each node in nodes[0..n) are put at rest at
- * the pressure P = amplitude * sin(omega t), f_0 = w_0 sqrt(g) P and
- * f_l = w sqrt(g) P (the rule of lbw_init), before the probes are read and
- * the step t -> t+1 is taken; omega is in radians per step.  nodes is host
- * memory, read during the call.  n = 0 removes the sources.  Waits for the
- * stream.  Errors: LBW_EINVAL (n < 0, NULL nodes with n > 0, a node outside
- * the grid, non-finite amplitude or omega), LBW_ENOMEM, LBW_EDEVICE. */
-int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude, double omega);
+/* Driven sources (Sec. IV.A pipe plate and ring sources, Sec. IV.C torus
+ * ring and point sources: a pressure, or a flux, imposed at chosen nodes as a
+ * harmonic function of time).  From the next queued step on, at every time t
+ * (steps since lbw_init), with v = amplitude * sin(omega t), each node in
+ * nodes[0..n) is set before the probes are read and the step t -> t+1 is
+ * taken; omega is in radians per step:
+ *  kind LBW_SOURCE_PRESSURE: put at rest at the pressure P = v,
+ *    f_0 = w_0 sqrt(g) P and f_l = w sqrt(g) P (the rule of lbw_init);
+ *  kind LBW_SOURCE_FLUX + a (axis a < dim; the oscillating plate, J'_a = v):
+ *    the node keeps S = sum_l f_l and takes the equilibrium with first
+ *    moment sqrt(g) v along a, f_0 = w_0 S, f_l = w S + e_l^a sqrt(g) v / 2.
+ *    This is sqrt(g) J'_a where the flux definition's force correction
+ *    vanishes on axis a (Gamma^a = 0 and g^{aj} = delta^{aj}, as for the
+ *    axis of the cylindrical pipe); elsewhere it is the imposed first moment.
+ * nodes is host memory, read during the call.  n = 0 removes the sources.
+ * Waits for the stream.  Errors: LBW_EINVAL (n < 0, NULL nodes with n > 0, a
+ * node outside the grid, non-finite amplitude or omega, kind outside
+ * [0, dim]), LBW_ENOMEM, LBW_EDEVICE. */
+#define LBW_SOURCE_PRESSURE 0
+#define LBW_SOURCE_FLUX 1
+int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude, double omega, int kind);
 
 /* Response intensity of a driven run (the frequency sweeps of Sec. IV.A and
  * IV.C): out (host, n_probes values) receives the largest |P| of each probe
@@ -300,16 +310,17 @@ int lbw_batch_probe(lbw_batch_t b, double* host_dst, int64_t t0, int64_t t1);
  * values, geometry-major.  Synchronises.  Errors as lbw_modes. */
 int lbw_batch_modes(lbw_batch_t b, int k, double* freq_out, double* power_out);
 
-/* Driven sources of a batch (the rule of lbw_set_sources): source i sits at
- * node nodes[i] of geometry geom[i] with its own amplitude[i] and omega[i],
- * so one batch can sweep many drive frequencies over copies of a geometry;
+/* Driven sources of a batch (the rules of lbw_set_sources): source i sits
+ * at node nodes[i] of geometry geom[i] with its own amplitude[i], omega[i]
+ * and kind[i] (NULL kind: all LBW_SOURCE_PRESSURE), so one batch can sweep
+ * many drive frequencies, and both source kinds, over copies of a geometry;
  * t is that geometry's step count.  All arrays are host memory of n
  * entries, read during the call; n = 0 removes the sources.  Waits for the
- * stream.  Errors: LBW_EINVAL (n < 0, NULL arrays with n > 0, a geometry
- * index or node out of range, non-finite amplitude or omega), LBW_ENOMEM,
- * LBW_EDEVICE. */
+ * stream.  Errors: LBW_EINVAL (n < 0, NULL nodes, geom, amplitude or omega
+ * with n > 0, a geometry index or node out of range, non-finite amplitude or
+ * omega, a kind outside [0, 3]), LBW_ENOMEM, LBW_EDEVICE. */
 int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* geom, const double* amplitude,
-                          const double* omega, int n);
+                          const double* omega, const int32_t* kind, int n);
 
 /* Response intensity of every probe of the batch (P values in global probe
  * order) over rows [t0, t1); as lbw_amplitude. */

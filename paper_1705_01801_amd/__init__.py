@@ -105,7 +105,7 @@ def lib():
         L.lbw_state_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(vp)]
         L.lbw_pressure.argtypes = [vp, vp]
         L.lbw_free_state.argtypes = [vp]
-        L.lbw_set_sources.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.c_double, ctypes.c_double]
+        L.lbw_set_sources.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.c_double, ctypes.c_double, i32]
         L.lbw_amplitude.argtypes = [vp, i64, i64, vp]
         L.lbw_batch_make.argtypes = [ctypes.POINTER(GeometryDesc), i32, vp, vp, vp, ctypes.POINTER(i64),
                                      ctypes.POINTER(ctypes.c_int32), vp, i64, vp, ctypes.POINTER(vp)]
@@ -120,7 +120,8 @@ def lib():
         L.lbw_batch_modes.argtypes = [vp, i32, vp, vp]
         L.lbw_batch_free.argtypes = [vp]
         L.lbw_batch_set_sources.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32),
-                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), i32]
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int32), i32]
         L.lbw_batch_amplitude.argtypes = [vp, i64, i64, vp]
         L.lbw_mlp_create.argtypes = [ctypes.POINTER(ctypes.c_int32), i32, i32, vp, ctypes.POINTER(vp)]
         L.lbw_mlp_param_count.argtypes = [vp, ctypes.POINTER(i64)]
@@ -302,12 +303,15 @@ class Simulation:
         check(lib().lbw_modes(self.handle, int(k), freq.ctypes.data, power.ctypes.data))
         return freq, power
 
-    def set_sources(self, nodes, amplitude: float, omega: float):
+    def set_sources(self, nodes, amplitude: float, omega: float, flux_axis=None):
         """Drives the pressure amplitude * sin(omega t) at the given nodes
-        from the next step on (an empty list removes the sources)."""
+        from the next step on (an empty list removes the sources); with
+        flux_axis = a, the flux J'_a = amplitude * sin(omega t) instead (the
+        oscillating plate)."""
         nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64).reshape(-1))
+        kind = 0 if flux_axis is None else 1 + int(flux_axis)
         check(lib().lbw_set_sources(self.handle, nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                    int(nodes.size), float(amplitude), float(omega)))
+                                    int(nodes.size), float(amplitude), float(omega), kind))
 
     def amplitude(self, t0: int, t1: int) -> np.ndarray:
         """Largest |P| of each probe over recorded rows [t0, t1)."""
@@ -414,18 +418,25 @@ class Batch:
         check(lib().lbw_batch_probe(self.handle, out.ctypes.data, int(t0), int(t1)))
         return out
 
-    def set_sources(self, nodes, geom, amplitude, omega):
+    def set_sources(self, nodes, geom, amplitude, omega, flux_axis=None):
         """Source i drives amplitude[i] * sin(omega[i] t) at node nodes[i]
-        of geometry geom[i] (scalars broadcast); empty lists remove them."""
+        of geometry geom[i] (scalars broadcast); empty lists remove them.
+        The drive is a pressure, or with flux_axis[i] = a >= 0 the flux
+        J'_a (a negative entry keeps that source a pressure)."""
         nodes = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64).reshape(-1))
         n = nodes.size
         geom = np.ascontiguousarray(np.broadcast_to(np.asarray(geom, dtype=np.int32), (n,)))
         amp = np.ascontiguousarray(np.broadcast_to(np.asarray(amplitude, dtype=np.float64), (n,)))
         om = np.ascontiguousarray(np.broadcast_to(np.asarray(omega, dtype=np.float64), (n,)))
+        kp = None
+        if flux_axis is not None:
+            ax = np.broadcast_to(np.asarray(flux_axis, dtype=np.int64), (n,))
+            kind = np.ascontiguousarray(np.where(ax < 0, 0, ax + 1).astype(np.int32))
+            kp = kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         check(lib().lbw_batch_set_sources(self.handle, nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                           geom.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                           amp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                          om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n)))
+                                          om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), kp, int(n)))
 
     def amplitude(self, t0: int, t1: int) -> np.ndarray:
         """Largest |P| of every probe (global order) over rows [t0, t1)."""

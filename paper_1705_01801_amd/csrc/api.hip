@@ -646,11 +646,12 @@ int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out) {
     return LBW_OK;
 }
 
-int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude, double omega) {
+int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude, double omega, int kind) {
     if (!s) return fail(LBW_EINVAL, "state is NULL");
     if (n < 0 || (n > 0 && !nodes)) return fail(LBW_EINVAL, "invalid source list");
     if (!std::isfinite(amplitude) || !std::isfinite(omega)) return fail(LBW_EINVAL, "non-finite amplitude or omega");
     lbw_geometry* g = s->g;
+    if (kind < 0 || kind > g->dev.dim) return fail(LBW_EINVAL, "source kind %d outside [0, %d]", kind, g->dev.dim);
     for (int i = 0; i < n; ++i)
         if (nodes[i] < 0 || nodes[i] >= g->N) return fail(LBW_EINVAL, "source %d outside the grid", i);
     // sqrt(g) per (i0, i2) entry (FP64 table plane 7) or per node (plane 9)
@@ -672,8 +673,9 @@ int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude
         e.N = (uint32_t)g->N;
         e.q = g->Q;
         e.counter = 0;
-        e.a0 = amplitude * (1.0 - d * c2) * sq;
-        e.a1 = amplitude * 0.5 * c2 * sq;
+        e.kind = kind;
+        e.a0 = kind ? amplitude * 0.5 * sq : amplitude * (1.0 - d * c2) * sq;
+        e.a1 = kind ? 0.5 * c2 : amplitude * 0.5 * c2 * sq;
         e.omega = omega;
         host[(size_t)i] = e;
     }

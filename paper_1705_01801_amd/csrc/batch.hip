@@ -486,10 +486,11 @@ int lbw_batch_modes(lbw_batch_t b, int k, double* freq_out, double* power_out) {
 }
 
 int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* geom, const double* amplitude,
-                          const double* omega, int n) {
+                          const double* omega, const int32_t* kind, int n) {
     if (!b) return fail(LBW_EINVAL, "batch is NULL");
     if (n < 0 || (n > 0 && (!nodes || !geom || !amplitude || !omega))) return fail(LBW_EINVAL, "invalid source list");
     for (int i = 0; i < n; ++i) {
+        if (kind && (kind[i] < 0 || kind[i] > 3)) return fail(LBW_EINVAL, "source %d: kind outside [0, 3]", i);
         if (geom[i] < 0 || geom[i] >= b->n) return fail(LBW_EINVAL, "source %d: geometry out of range", i);
         const int64_t N = b->node_off[geom[i] + 1] - b->node_off[geom[i]];
         if (nodes[i] < 0 || nodes[i] >= N) return fail(LBW_EINVAL, "source %d outside its geometry", i);
@@ -522,8 +523,9 @@ int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* ge
         e.N = (uint32_t)N;
         e.q = 7;
         e.counter = h;
-        e.a0 = amplitude[i] * (1.0 - 3.0 * c2) * sq;
-        e.a1 = amplitude[i] * 0.5 * c2 * sq;
+        e.kind = kind ? kind[i] : 0;
+        e.a0 = e.kind ? amplitude[i] * 0.5 * sq : amplitude[i] * (1.0 - 3.0 * c2) * sq;
+        e.a1 = e.kind ? 0.5 * c2 : amplitude[i] * 0.5 * c2 * sq;
         e.omega = omega[i];
         host[(size_t)i] = e;
     }

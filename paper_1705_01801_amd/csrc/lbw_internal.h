@@ -126,14 +126,15 @@ hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_
                              const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st);
 
 // One driven node (Sec. IV.A/IV.C sources): its populations sit at
-// f[f_off + l N], l < q; a0 = amplitude w_0 sqrt(g), a1 = amplitude w sqrt(g);
-// the time is counters[counter].
+// f[f_off + l N], l < q; the time is counters[counter].  kind 0 imposes a
+// pressure (a0 = amplitude w_0 sqrt(g), a1 = amplitude w sqrt(g)); kind
+// 1 + a a flux along axis a (a0 = amplitude sqrt(g) / 2, a1 = w).
 struct SourceEntry {
     uint64_t f_off;
     uint32_t N;
     int32_t q;
     int32_t counter;
-    int32_t pad;
+    int32_t kind;
     double a0, a1, omega;
 };
 // Imposes every source at its current time (before the step that reads f).

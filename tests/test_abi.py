@@ -113,7 +113,7 @@ def test_general_metric_rejected_on_host():
 def test_source_calls_reject_null():
     L = lbw.lib()
     L.lbw_set_sources.restype = ctypes.c_int
-    assert L.lbw_set_sources(None, None, 0, 1.0, 0.1) == -1
+    assert L.lbw_set_sources(None, None, 0, 1.0, 0.1, 0) == -1
     assert L.lbw_amplitude(None, 0, 1, None) == -1
-    assert L.lbw_batch_set_sources(None, None, None, None, None, 0) == -1
+    assert L.lbw_batch_set_sources(None, None, None, None, None, None, 0) == -1
     assert L.lbw_batch_amplitude(None, 0, 1, None) == -1

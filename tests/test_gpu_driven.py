@@ -1,7 +1,8 @@
 """GPU: driven sources and response intensity against the FP64 oracle.
 
-Sources impose amplitude * sin(omega t) at chosen nodes before every step
-(Sec. IV.A and IV.C ring and point sources); the intensity is the largest
+Sources impose amplitude * sin(omega t) at chosen nodes before every step,
+as a pressure (Sec. IV.A and IV.C ring and point sources) or as the flux
+J'_a of an oscillating plate (Sec. IV.A); the intensity is the largest
 |P| per probe over a late window (the frequency sweeps).  The HIP path
 keeps populations in FP32, so fields and traces are compared with the field
 tolerance of the undriven parity tests (relative L2 1e-5); a probe on a
@@ -68,6 +69,37 @@ def test_driven_run_matches_oracle(case):
     assert np.array_equal(a, np.abs(tr[T - 100:]).max(axis=0))
 
 
+@pytest.mark.parametrize("case", ["cylinder_plate", "polar2d_radial", "general_duct"])
+def test_flux_run_matches_oracle(case):
+    if case == "cylinder_plate":
+        geom, _, probes = cyl()
+        n0, n1 = geom["n"][0], geom["n"][1]
+        src, axis = list(range(n0 * n1)), 2               # the whole z = 0 plane
+    elif case == "polar2d_radial":
+        geom = dict(W.polar_disk(scale=4), damp=0.65)
+        n0 = geom["n"][0]
+        src, axis = [3 + n0 * i1 for i1 in range(geom["n"][1])], 0
+        probes = [src[2], 9 + n0 * 4, 14 + n0 * 11]
+    else:
+        geom = W.general_duct(n=(12, 10, 16))
+        geom = dict(geom, coeffs=W.general_coefficients(geom))
+        n0, n1 = geom["n"][0], geom["n"][1]
+        src, axis = [4 + n0 * (i1 + n1 * 3) for i1 in range(2, 8)], 1
+        probes = [src[0], 7 + n0 * (5 + n1 * 9), 2 + n0 * (8 + n1 * 14)]
+    C, w, T = 0.8, 0.07, 300
+    say("flux", case, W.shape_of(geom), "sources", len(src), "axis", axis, "steps", T)
+    o = oracle.Oracle(geom)
+    f = o.init(np.zeros(o.N))
+    _, tr_o = o.run(f, T, probes, sources=src, amplitude=C, omega=w, flux_axis=axis)
+    assert np.abs(tr_o).max() > 1e-2
+    sim = lbw.Simulation(lbw.Geometry(geom), np.zeros(o.N), probes, t_max=T)
+    sim.set_sources(src, C, w, flux_axis=axis)
+    sim.step(T)
+    assert rel_l2(sim.populations().double().cpu().numpy(), f) <= 1e-5
+    tr = sim.probe()
+    assert np.abs(tr - tr_o).max() <= 1e-5 * np.abs(tr_o).max()
+
+
 def test_sources_graph_replay_and_removal():
     geom, src, probes = cyl()
     T = 150
@@ -116,6 +148,30 @@ def test_batch_sweep_matches_single_runs():
     assert not trace[:, -len(probes):].any()          # the undriven copy stays at rest
 
 
+def test_batch_mixes_source_kinds():
+    """Ring (pressure) and plate (flux) copies in one batch, each equal bit
+    for bit to the same copy driven alone."""
+    geom, src, probes = cyl()
+    n0, n1 = geom["n"][0], geom["n"][1]
+    plate = list(range(n0 * n1))
+    cases = [(src, -1, 0.05), (plate, 2, 0.05), (plate, 2, 0.11), (src[:3], 1, 0.08)]
+    N, T = W.num_nodes(geom), 160
+    say("mixed-kind batch of", len(cases))
+    b = lbw.Batch([geom] * len(cases), [np.zeros(N)] * len(cases), [probes] * len(cases), t_max=T)
+    b.set_sources(np.concatenate([c[0] for c in cases]), np.repeat(np.arange(len(cases)), [len(c[0]) for c in cases]),
+                  0.7, np.repeat([c[2] for c in cases], [len(c[0]) for c in cases]),
+                  np.repeat([c[1] for c in cases], [len(c[0]) for c in cases]))
+    b.step(T)
+    trace = b.probe()
+    for h, (nodes, axis, w) in enumerate(cases):
+        sim = lbw.Simulation(lbw.Geometry(geom), np.zeros(N), probes, t_max=T)
+        sim.set_sources(nodes, 0.7, w, None if axis < 0 else axis)
+        sim.step(T)
+        assert np.array_equal(b.populations(h).cpu().numpy(), sim.populations().cpu().numpy()), h
+        cols = slice(int(b.probe_offsets[h]), int(b.probe_offsets[h + 1]))
+        assert np.array_equal(trace[:, cols], sim.probe()), h
+
+
 def test_source_errors():
     geom, src, probes = cyl()
     N = W.num_nodes(geom)
@@ -126,6 +182,13 @@ def test_source_errors():
         sim.set_sources([-1], 1.0, 0.1)
     with pytest.raises(lbw.LbwError):
         sim.set_sources([0], float("nan"), 0.1)
+    with pytest.raises(lbw.LbwError):
+        sim.set_sources([0], 1.0, 0.1, flux_axis=3)     # no fourth axis
+    with pytest.raises(lbw.LbwError):
+        sim.set_sources([0], 1.0, 0.1, flux_axis=-2)
+    disk = lbw.Geometry(W.polar_disk(scale=4))
+    with pytest.raises(lbw.LbwError):
+        lbw.Simulation(disk, np.zeros(disk.N)).set_sources([0], 1.0, 0.1, flux_axis=2)
     with pytest.raises(lbw.LbwError):
         sim.amplitude(0, 1)                          # nothing recorded yet
     sim.step(4)
@@ -138,6 +201,8 @@ def test_source_errors():
         b.set_sources([0], [2], 1.0, 0.1)
     with pytest.raises(lbw.LbwError):
         b.set_sources([N], [1], 1.0, 0.1)
+    with pytest.raises(lbw.LbwError):
+        b.set_sources([0], [1], 1.0, 0.1, flux_axis=3)
 
 
 def test_pipe_sweep_point_full_size():

@@ -389,6 +389,13 @@ def pipe_ring(geom) -> np.ndarray:
     return np.array([n0 * i1 for i1 in range(n1)], dtype=np.int64)
 
 
+def pipe_plate(geom) -> np.ndarray:
+    """Source nodes of the oscillating plate: the whole closed-end plane
+    (driven by the flux J'_z)."""
+    n0, n1 = geom["n"][0], geom["n"][1]
+    return np.arange(n0 * n1, dtype=np.int64)
+
+
 def pipe_probes(geom) -> np.ndarray:
     """Probes: r = 2.8, z = 10.5 (the paper's r = 3, z = z_max / 10) and the
     pipe's mid-length at the same radius."""
