@@ -230,6 +230,28 @@ def test_pipe_sweep_point_full_size():
     assert rel_l2(b.populations(1).double().cpu().numpy(), f) <= 5e-4
 
 
+def test_torus_sweep_points_match_oracle():
+    """Three points of the torus sweep (Sec. IV.C small ring, 20 x 200 x 30,
+    M^phiphi up to 39 near rho_min) batched, 600 steps, the middle one
+    against the oracle; FP32 rounding over 600 steps: 600 x 6e-8 ~ 4e-5."""
+    geom = W.driven_torus()
+    ring = W.torus_sources(geom)["small_ring"]
+    probes = np.concatenate([W.torus_probes(geom), ring[[3, 10]] + 2])   # two probes near the ring
+    N, T = W.num_nodes(geom), 600
+    omegas = [0.03, 0.071, 0.2]
+    say("torus sweep points, batch of", len(omegas), "steps", T)
+    b = lbw.Batch([geom] * 3, [np.zeros(N)] * 3, [probes] * 3, t_max=T)
+    b.set_sources(np.concatenate([ring] * 3), np.repeat(np.arange(3), ring.size), 1.0, np.repeat(omegas, ring.size))
+    b.step(T)
+    tr = b.probe()[:, len(probes):2 * len(probes)]
+    o = oracle.Oracle(geom)
+    f = o.init(np.zeros(o.N))
+    _, tr_o = o.run(f, T, probes, sources=ring, amplitude=1.0, omega=omegas[1])
+    assert np.abs(tr_o).max() > 1e-3
+    assert np.abs(tr - tr_o).max() <= 5e-5 * np.abs(tr_o).max()
+    assert rel_l2(b.populations(1).double().cpu().numpy(), f) <= 5e-5
+
+
 def test_radial_wave_matches_oracle():
     """The radial wave of the oracle pin (polar grid 199 x 4, ring drive,
     400 steps) through the 2-D kernel."""

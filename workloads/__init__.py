@@ -408,6 +408,49 @@ def sweep_omegas(n: int = 119, lo: float = 0.0005, hi: float = 0.03) -> np.ndarr
     return np.linspace(lo, hi, n)
 
 
+TORUS_STEPS = 8000
+
+
+def driven_torus(c: float = PIPE_C, damp: float = PIPE_DAMP) -> dict:
+    """Torus of the Sec. IV.C sweep: (rho, theta major, phi minor) with
+    20 x 200 x 30 cells, major radius 640, rho in [5.12, 409.6], theta and phi
+    periodic, a reflecting wall damped by 0.65 at rho_max; one lattice unit
+    per radial cell.  The paper's free wall at rho_min is replaced by a
+    reflecting one (damped alike): with the free rule a field from noise
+    grows about 100-fold per 500 steps on this grid.  The paper gives no
+    wave speed for the torus; its pipe's c = 0.1 is used."""
+    return dict(kind="torus", dim=3, n=(20, 200, 30), qmin=(5.12, 0.0, 0.0), qmax=(409.6, TWO_PI, TWO_PI),
+                bc_lo=("bounceback", "periodic", "periodic"), bc_hi=("bounceback", "periodic", "periodic"),
+                h_ref=(409.6 - 5.12) / 20, c=c, damp=damp, params=(640.0,))
+
+
+def torus_sources(geom) -> dict:
+    """The three sources of the torus experiments, as node lists: the ring
+    over the whole inner surface (rho_min, all theta and phi), the small ring
+    (rho_min, theta = 0, all phi) of the sweep, and the point at the middle
+    radius, theta = 0, phi = pi / 2."""
+    n0, n1, n2 = geom["n"]
+    i2 = np.arange(n2)
+    inner = (n0 * (np.arange(n1)[None, :] + n1 * i2[:, None])).reshape(-1)
+    small = n0 * n1 * i2
+    point = np.array([n0 // 2 + n0 * n1 * (n2 // 4)])
+    return {"inner": inner.astype(np.int64), "small_ring": small.astype(np.int64), "point": point.astype(np.int64)}
+
+
+def torus_probes(geom) -> np.ndarray:
+    """Probes: the sweep's point opposite the source on the major circle
+    (rho_max, theta = pi, phi = 0), then (rho_max, pi / 2, 0) and the middle
+    radius at (pi, pi / 2)."""
+    n0, n1, n2 = geom["n"]
+    return np.array([n0 - 1 + n0 * (n1 // 2), n0 - 1 + n0 * (n1 // 4), n0 // 2 + n0 * (n1 // 2 + n1 * (n2 // 4))],
+                    dtype=np.int64)
+
+
+def torus_omegas(n: int = 499, lo: float = 0.001, hi: float = 0.499) -> np.ndarray:
+    """Drive frequencies of the torus sweep (steps of 0.001 rad/step)."""
+    return np.linspace(lo, hi, n)
+
+
 # ---------------------------------------------------------------------------
 # general (non-separable) metric: a stretched, sheared and bumped duct
 # ---------------------------------------------------------------------------
