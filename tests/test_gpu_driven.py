@@ -41,16 +41,21 @@ def cyl():
     return dict(geom, damp=0.65), src, probes
 
 
-@pytest.mark.parametrize("case", ["cylinder", "polar2d"])
+@pytest.mark.parametrize("case", ["cylinder", "polar2d", "box2d_point"])
 def test_driven_run_matches_oracle(case):
+    C, w, T = 0.8, 0.07, 300
     if case == "cylinder":
         geom, src, probes = cyl()
+    elif case == "box2d_point":                       # the Cartesian point source, 100 x 100
+        geom, src, w = W.point_source_box()
+        n = geom["n"][0]
+        probes = [src[0], src[0] + 7, src[0] + 20 * n, 5 + 5 * n]
+        T = 150
     else:
         geom = dict(W.polar_disk(scale=4), damp=0.65)  # 16 x 16, D2Q5 kernel
         n0 = geom["n"][0]
         src = [0 + n0 * i1 for i1 in range(geom["n"][1])]
         probes = [src[3], 9 + n0 * 4, 14 + n0 * 11]
-    C, w, T = 0.8, 0.07, 300
     say("driven", case, W.shape_of(geom), "sources", len(src), "steps", T)
     o = oracle.Oracle(geom)
     f = o.init(np.zeros(o.N))

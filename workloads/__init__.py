@@ -408,6 +408,17 @@ def sweep_omegas(n: int = 119, lo: float = 0.0005, hi: float = 0.03) -> np.ndarr
     return np.linspace(lo, hi, n)
 
 
+def point_source_box(n: int = 100, c: float = 0.5, wavelength: float = 10.0):
+    """The Cartesian point source of Sec. II: a 2-D box of n x n cells
+    (D2Q5, reflecting walls), wave speed c, the central cell driven at
+    omega = 2 pi c / wavelength (a wavelength of 10 cells).  Returns
+    (geometry, source node list, omega)."""
+    geom = dict(kind="box", dim=2, n=(n, n), qmin=(0.0, 0.0), qmax=(float(n), float(n)),
+                bc_lo=("bounceback", "bounceback"), bc_hi=("bounceback", "bounceback"), h_ref=1.0, c=c, damp=1.0,
+                params=())
+    return geom, [n // 2 + n * (n // 2)], 2.0 * math.pi * c / wavelength
+
+
 TORUS_STEPS = 8000
 
 
