@@ -128,7 +128,7 @@ def main():
                     help="drive frequencies in the driven-pipe sweep leg (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this build", file=sys.stderr)
+        print("bench.py runs on exactly one GPU; the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
