@@ -17,6 +17,7 @@ struct lbw_batch {
     std::vector<lbw::BatchItem> items;
     lbw::BatchItem* d_items = nullptr;
     int tx = 32, lz = 16, blocks = 8;
+    int section_nt = 0;  // > 0: whole-section tiles of this many threads (tx unused)
     int64_t tiles = 0;
     int plan_version = 0;
     float* f[2] = {nullptr, nullptr};
@@ -66,7 +67,7 @@ void release(lbw_batch* b) {
 hipError_t build_items(lbw_batch* b) {
     hipError_t e0 = hipStreamSynchronize(b->stream);
     if (e0 != hipSuccess) return e0;
-    const int ty = 256 / b->tx;
+    const int ty = b->section_nt ? 1 : 256 / b->tx;
     int64_t tile = 0;
     for (int h = 0; h < b->n; ++h) {
         const lbw_geometry_desc& d = b->d[h];
@@ -83,8 +84,8 @@ hipError_t build_items(lbw_batch* b) {
         it.c2 = v.c2;
         it.two_w0 = v.two_w0;
         it.damp = v.damp;
-        it.ntx = (v.n0 + b->tx - 1) / b->tx;
-        it.nty = (v.n1 + ty - 1) / ty;
+        it.ntx = b->section_nt ? 1 : (v.n0 + b->tx - 1) / b->tx;
+        it.nty = b->section_nt ? 1 : (v.n1 + ty - 1) / ty;
         it.lz = b->lz;
         const int nchunks = (v.n2 + b->lz - 1) / b->lz;
         it.tile_begin = tile;
@@ -121,7 +122,7 @@ hipError_t launch_batch(lbw_batch* b, const lbw::BatchProbeArgs& bp, const float
         const hipError_t e = lbw::launch_sources(b->d_src, b->n_src, b->d_tcount, const_cast<float*>(fin), st);
         if (e != hipSuccess) return e;
     }
-    return lbw::launch_step_batch(b->d_items, b->n, b->tiles, b->tx, b->blocks, bp, fin, fout, st);
+    return lbw::launch_step_batch(b->d_items, b->n, b->tiles, b->tx, b->section_nt, b->blocks, bp, fin, fout, st);
 }
 
 hipError_t build_graph(lbw_batch* b, int from) {
@@ -154,35 +155,48 @@ void drop_graphs(lbw_batch* b) {
     }
 }
 
-// Tile width with the fewest idle lanes over the whole batch: lanes
-// allotted = sum over geometries of ceil(n0 / TX) TX * ceil(n1 / TY) TY * n2;
-// ties go to the wider tile (longer contiguous rows per wave).
-int default_tile_x(const lbw_batch* b) {
-    int best = 64;
-    double best_slots = 0.0;
-    for (int tx : {64, 32, 16}) {
-        const int ty = 256 / tx;
-        double slots = 0.0;
-        for (int h = 0; h < b->n; ++h) {
-            const lbw_geometry_desc& d = b->d[h];
-            slots += (double)((d.n[0] + tx - 1) / tx * tx) * (double)((d.n[1] + ty - 1) / ty * ty) * (double)d.n[2];
-        }
-        if (tx == 64 || slots < best_slots) {
-            best = tx;
-            best_slots = slots;
+
+// Workgroup size for whole-section tiles over the whole batch (the largest
+// any geometry needs), or 0 if some cross-section does not fit one.
+int section_threads(const lbw_batch* b) {
+    int nt = 0;
+    for (int h = 0; h < b->n; ++h) {
+        const int t = lbw::batch_section_threads(b->d[h].n[0], b->d[h].n[1]);
+        if (t == 0) return 0;
+        nt = t > nt ? t : nt;
+    }
+    return nt;
+}
+
+// Lanes allotted over the whole batch: TX-wide tiles (tile_x > 0) or
+// whole-section tiles (tile_x = 0).
+double lane_slots(const lbw_batch* b, int tile_x) {
+    double slots = 0.0;
+    const int nt = section_threads(b);
+    for (int h = 0; h < b->n; ++h) {
+        const lbw_geometry_desc& d = b->d[h];
+        if (tile_x == 0) {
+            slots += (double)nt * (double)d.n[2];
+        } else {
+            const int ty = 256 / tile_x;
+            slots += (double)((d.n[0] + tile_x - 1) / tile_x * tile_x) * (double)((d.n[1] + ty - 1) / ty * ty) *
+                     (double)d.n[2];
         }
     }
-    return best;
+    return slots;
 }
 
 int set_config(lbw_batch* b, int tile_x, int chunk_z, int blocks) {
     int cus = 0;
     int rc = lbw::device_cus(&cus);
     if (rc) return rc;
-    if (blocks == 0) blocks = cus * lbw::batch_blocks_per_cu(tile_x);
+    const int nt = tile_x == 0 ? section_threads(b) : 0;
+    if (tile_x == 0 && nt == 0) return fail(LBW_EINVAL, "a cross-section is too large for whole-section tiles");
+    if (blocks == 0) blocks = cus * (nt ? lbw::batch_section_blocks_per_cu(nt) : lbw::batch_blocks_per_cu(tile_x));
     blocks = (blocks / 8) * 8;
     if (blocks < 8) blocks = 8;
     b->tx = tile_x;
+    b->section_nt = nt;
     b->lz = chunk_z;
     b->blocks = blocks;
     HIP_TRY(build_items(b), "batch step configuration");
@@ -280,11 +294,26 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
     int rc = LBW_OK;
     {
         // default: chunk 16, two waves of resident workgroups (measured best
-        // on the 512-horn ensemble among chunks 8..128 and one or two waves)
+        // on the 512-horn ensemble among chunks 8..128 and one or two
+        // waves), and the tile with the fewest idle lanes over the whole
+        // batch: TX-wide (lanes allotted = sum over geometries of
+        // ceil(n0 / TX) TX ceil(n1 / TY) TY n2, ties to the wider tile) or
+        // whole cross-sections (workgroup size times n2)
         int cus = 0;
         rc = lbw::device_cus(&cus);
-        const int tx = default_tile_x(b);
-        if (rc == LBW_OK) rc = set_config(b, tx, 16, 2 * cus * lbw::batch_blocks_per_cu(tx));
+        int tx = 64;
+        double best = lane_slots(b, 64);
+        for (int cand : {32, 16}) {
+            const double sl = lane_slots(b, cand);
+            if (sl < best) {
+                tx = cand;
+                best = sl;
+            }
+        }
+        const int nt = section_threads(b);
+        if (nt > 0 && lane_slots(b, 0) < best) tx = 0;
+        const int bpc = tx == 0 ? lbw::batch_section_blocks_per_cu(nt) : lbw::batch_blocks_per_cu(tx);
+        if (rc == LBW_OK) rc = set_config(b, tx, 16, 2 * cus * bpc);
     }
     if (rc == LBW_OK && b->P > 0 && hipStreamSynchronize(b->stream) != hipSuccess)
         rc = fail(LBW_EDEVICE, "lbw_batch_make: synchronise");
@@ -307,7 +336,8 @@ int lbw_batch_layout(lbw_batch_t b, int64_t* node_offsets, int64_t* probe_offset
 
 int lbw_batch_set_step_config(lbw_batch_t b, int tile_x, int chunk_z, int blocks) {
     if (!b) return fail(LBW_EINVAL, "batch is NULL");
-    if (tile_x != 16 && tile_x != 32 && tile_x != 64) return fail(LBW_EINVAL, "tile_x must be 16, 32 or 64");
+    if (tile_x != 0 && tile_x != 16 && tile_x != 32 && tile_x != 64)
+        return fail(LBW_EINVAL, "tile_x must be 0 (whole cross-sections), 16, 32 or 64");
     if (chunk_z < 1 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 1 and blocks >= 0");
     return set_config(b, tile_x, chunk_z, blocks);
 }

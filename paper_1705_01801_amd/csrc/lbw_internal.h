@@ -122,8 +122,15 @@ struct BatchProbeArgs {
     const float4* tab4;    // device, batch float table (2 float4 per record)
 };
 int batch_blocks_per_cu(int tx);
-hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int blocks,
-                             const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st);
+// Workgroup size of a whole-section tile for an n0 x n1 cross-section (128
+// or 256 threads, covering the section, its ring loaders and its row
+// loaders), or 0 when the section is too large for one.
+int batch_section_threads(int n0, int n1);
+int batch_section_blocks_per_cu(int nt);
+// section_nt > 0 selects whole-section tiles of section_nt threads (the tile
+// list must then hold one tile per chunk of planes, ntx = nty = 1).
+hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int section_nt,
+                             int blocks, const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st);
 
 // One driven node (Sec. IV.A/IV.C sources): its populations sit at
 // f[f_off + l N], l < q; the time is counters[counter].  kind 0 imposes a

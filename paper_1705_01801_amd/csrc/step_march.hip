@@ -56,7 +56,17 @@ struct TileGeom {
     float c2, two_w0, damp;
     const float4* tab4;
     int ntx, nty, lz;
+    int rtx, rty;  // tile width and height when they are run-time values
 };
+
+// LDS floats per S slot: the tile plus its one-node ring (and a sink slot).
+// With a run-time tile of at most NT columns the ring-padded tile and every
+// neighbour read of an idle lane (lane index up to NT - 1) stay below
+// 4 NT + 8.
+template <int TX, int NT, bool RT>
+constexpr int lds_s() {
+    return RT ? 4 * NT + 8 : (NT / TX + 2) * (TX + 2) + 1;
+}
 
 __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* __restrict__ fin) {
     const int64_t t = *(volatile const int64_t*)pr.tcount;
@@ -112,17 +122,22 @@ __device__ inline float bounce(int wall, float damp, float out_l, float own_lb) 
 
 // One tile of one geometry: columns [x0, x0 + TX) x [y0, y0 + TY), planes
 // [z0, z0 + lz).  fin/fout point at the geometry's own population block.
-template <int TX, int NT, bool ROW>
+// RT: the tile is g.rtx x g.rty columns instead (at most NT of them, with
+// 2 (rtx + rty) <= NT ring loaders and rtx + 2 <= NT row loaders, checked by
+// the host); TX = NT then only sizes the LDS arrays, and ROW must be false.
+template <int TX, int NT, bool ROW, bool RT = false>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
-                                           float* __restrict__ fout, float (&sS)[2][(NT / TX + 2) * (TX + 2) + 1],
+                                           float* __restrict__ fout, float (&sS)[2][lds_s<TX, NT, RT>()],
                                            float4 (&sElo)[3][TX + 3], float4 (&sEhi)[3][TX + 3]) {
-    constexpr int TY = NT / TX;
-    constexpr int W = TX + 2;
-    constexpr int kSinkS = (TY + 2) * W;  // LDS slot written by disabled lanes
+    static_assert(!(RT && ROW), "run-time tiles use the shifted stores");
+    const int TXr = RT ? g.rtx : TX;
+    const int TY = RT ? g.rty : NT / TX;
+    const int W = TXr + 2;
+    const int kSinkS = (TY + 2) * W;  // LDS slot written by disabled lanes
     const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
     const uint32_t N = g.N;
     const uint32_t plane = (uint32_t)n0 * (uint32_t)n1;
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int lx = (int)(threadIdx.x % (unsigned)TXr), ly = (int)(threadIdx.x / (unsigned)TXr);
     const float c2 = g.c2, two_w0 = g.two_w0, damp = g.damp;
     const float4* __restrict__ tab4 = g.tab4;
     {
@@ -130,11 +145,11 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
         const int r1 = tile / g.ntx;
         const int ty = r1 % g.nty;
         const int chunk = r1 / g.nty;
-        const int x0 = tx * TX, y0 = ty * TY;
+        const int x0 = tx * TXr, y0 = ty * TY;
         const int z0 = chunk * g.lz;
         if (z0 >= n2 || ty >= g.nty) return;  // tile outside the grid (uniform per block)
         const int z1 = min(z0 + g.lz, n2);
-        const int wdt = min(TX, n0 - x0);
+        const int wdt = min(TXr, n0 - x0);
         const int hgt = min(TY, n1 - y0);
         const int x = x0 + lx, y = y0 + ly;
         const bool active = lx < wdt && ly < hgt;
@@ -160,12 +175,12 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             bool have = false;
             if (r < wdt) {
                 rx = x0 + r; ry = y0 - 1; sx = r + 1; sy = 0; have = true;
-            } else if (r >= TX && r < TX + wdt) {
-                rx = x0 + (r - TX); ry = y0 + hgt; sx = r - TX + 1; sy = hgt + 1; have = true;
-            } else if (r >= 2 * TX && r < 2 * TX + hgt) {
-                rx = x0 - 1; ry = y0 + (r - 2 * TX); sx = 0; sy = r - 2 * TX + 1; have = true;
-            } else if (r >= 2 * TX + TY && r < 2 * TX + TY + hgt) {
-                rx = x0 + wdt; ry = y0 + (r - 2 * TX - TY); sx = wdt + 1; sy = r - 2 * TX - TY + 1; have = true;
+            } else if (r >= TXr && r < TXr + wdt) {
+                rx = x0 + (r - TXr); ry = y0 + hgt; sx = r - TXr + 1; sy = hgt + 1; have = true;
+            } else if (r >= 2 * TXr && r < 2 * TXr + hgt) {
+                rx = x0 - 1; ry = y0 + (r - 2 * TXr); sx = 0; sy = r - 2 * TXr + 1; have = true;
+            } else if (r >= 2 * TXr + TY && r < 2 * TXr + TY + hgt) {
+                rx = x0 + wdt; ry = y0 + (r - 2 * TXr - TY); sx = wdt + 1; sy = r - 2 * TXr - TY + 1; have = true;
             }
             if (have) {
                 int w = 0;
@@ -371,8 +386,8 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             if (more) {
                 // disabled lanes write the sink slot past the end (never read)
                 sS[sb ^ 1][ring_on ? ring_lds : kSinkS] = sum7(r1);
-                sElo[es2][e_on ? (int)threadIdx.x : TX + 2] = e1[0];
-                sEhi[es2][e_on ? (int)threadIdx.x : TX + 2] = e1[1];
+                sElo[es2][e_on ? (int)threadIdx.x : TXr + 2] = e1[0];
+                sEhi[es2][e_on ? (int)threadIdx.x : TXr + 2] = e1[1];
                 sS[sb ^ 1][active ? my_lds : kSinkS] = Sp;
                 Sm = Sc;
                 Sc = Sp;
@@ -396,7 +411,7 @@ template <int TX, int NT, bool ROW>
 __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
-    __shared__ float sS[2][(NT / TX + 2) * (TX + 2) + 1];
+    __shared__ float sS[2][lds_s<TX, NT, false>()];
     __shared__ float4 sElo[3][TX + 3];
     __shared__ float4 sEhi[3][TX + 3];
     if (blockIdx.x == 0) probe_block(g, pr, fin);
@@ -428,12 +443,15 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
 // one list (geometry h owns tiles [tile_begin, tile_begin + tiles)), split
 // into one contiguous range per XCD.  Block b first records the probes of
 // geometries b, b + gridDim.x, ... (one step counter per geometry).
-template <int TX>
-__global__ __launch_bounds__(kBatchThreads) void step_batch_kernel(const BatchItem* __restrict__ items, int n_items,
-                                                              int64_t tiles_total, BatchProbeArgs bp,
-                                                              const float* __restrict__ fin,
-                                                              float* __restrict__ fout) {
-    __shared__ float sS[2][(kBatchThreads / TX + 2) * (TX + 2) + 1];
+// SECTION: every tile is a whole (axis 0, axis 1) cross-section of its
+// geometry (run-time tile n0 x n1, one tile per chunk of planes), for
+// batches of small cross-sections that a TX-wide tile would leave mostly
+// idle; TX = NT then only sizes the LDS arrays.
+template <int TX, int NT, bool SECTION>
+__global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restrict__ items, int n_items,
+                                                         int64_t tiles_total, BatchProbeArgs bp,
+                                                         const float* __restrict__ fin, float* __restrict__ fout) {
+    __shared__ float sS[2][lds_s<TX, NT, SECTION>()];
     __shared__ float4 sElo[3][TX + 3];
     __shared__ float4 sEhi[3][TX + 3];
     for (int h = blockIdx.x; h < n_items; h += gridDim.x) {
@@ -488,7 +506,10 @@ __global__ __launch_bounds__(kBatchThreads) void step_batch_kernel(const BatchIt
         tg.ntx = it.ntx;
         tg.nty = it.nty;
         tg.lz = it.lz;
-        march_tile<TX, kBatchThreads, true>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sElo, sEhi);
+        tg.rtx = it.n0;
+        tg.rty = it.n1;
+        march_tile<TX, NT, !SECTION, SECTION>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS,
+                                              sElo, sEhi);
     }
 }
 
@@ -545,23 +566,47 @@ hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchP
 
 int batch_blocks_per_cu(int tx) {
     int nb = 0;
-    hipError_t e = tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<16>, kBatchThreads, 0)
-                   : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32>, kBatchThreads, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64>, kBatchThreads, 0);
+    hipError_t e =
+        tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<16, kBatchThreads, false>,
+                                                                  kBatchThreads, 0)
+        : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32, kBatchThreads, false>,
+                                                                  kBatchThreads, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64, kBatchThreads, false>,
+                                                                  kBatchThreads, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int blocks,
-                             const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st) {
-    if (tx == 16)
-        hipLaunchKernelGGL(step_batch_kernel<16>, dim3(blocks), dim3(kBatchThreads), 0, st, items, n_items, tiles_total,
-                           bp, fin, fout);
+int batch_section_threads(int n0, int n1) {
+    const int need = max(n0 * n1, max(2 * (n0 + n1), n0 + 2));
+    return need <= 128 ? 128 : (need <= 256 ? 256 : 0);
+}
+
+int batch_section_blocks_per_cu(int nt) {
+    int nb = 0;
+    hipError_t e = nt == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<128, 128, true>,
+                                                                            128, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<256, 256, true>,
+                                                                            256, 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int section_nt,
+                             int blocks, const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st) {
+    if (section_nt == 128)
+        hipLaunchKernelGGL((step_batch_kernel<128, 128, true>), dim3(blocks), dim3(128), 0, st, items, n_items,
+                           tiles_total, bp, fin, fout);
+    else if (section_nt == 256)
+        hipLaunchKernelGGL((step_batch_kernel<256, 256, true>), dim3(blocks), dim3(256), 0, st, items, n_items,
+                           tiles_total, bp, fin, fout);
+    else if (tx == 16)
+        hipLaunchKernelGGL((step_batch_kernel<16, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
+                           items, n_items, tiles_total, bp, fin, fout);
     else if (tx == 32)
-        hipLaunchKernelGGL(step_batch_kernel<32>, dim3(blocks), dim3(kBatchThreads), 0, st, items, n_items, tiles_total,
-                           bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<32, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
+                           items, n_items, tiles_total, bp, fin, fout);
     else
-        hipLaunchKernelGGL(step_batch_kernel<64>, dim3(blocks), dim3(kBatchThreads), 0, st, items, n_items, tiles_total,
-                           bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<64, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
+                           items, n_items, tiles_total, bp, fin, fout);
     return hipGetLastError();
 }
 

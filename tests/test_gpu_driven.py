@@ -177,6 +177,35 @@ def test_batch_mixes_source_kinds():
         assert np.array_equal(trace[:, cols], sim.probe()), h
 
 
+def test_whole_section_tiles_match_wide_tiles():
+    """Small cross-sections (pipe 20 x 5, cylinder 8 x 8) default to
+    whole-section tiles; the same batch on 32-wide tiles, and on whole
+    sections with ragged chunks of 7 planes, gives identical bits (same
+    per-node arithmetic, only the lane mapping differs)."""
+    geoms = [W.driven_pipe("fixed"), W.driven_pipe("free"), cyl()[0]] * 2
+    N = [W.num_nodes(g) for g in geoms]
+    rng = np.random.default_rng(5)
+    P0 = [rng.uniform(-1, 1, n) for n in N]
+    probes = [[0, 7, n - 1] for n in N]
+    ring = W.pipe_ring(geoms[0])
+    out = []
+    for shape in (None, (32, 16, 0), (0, 7, 0)):
+        b = lbw.Batch(geoms, P0, probes, t_max=200)
+        if shape is None:
+            assert b.step_config()[0] == 0                 # whole sections by default
+        else:
+            b.set_step_config(*shape)
+        b.set_graph_block(16)
+        b.set_sources(np.concatenate([ring, ring]), np.repeat([0, 3], ring.size), 0.5, 0.02)
+        say("batch launch shape", b.step_config())
+        b.step(200)
+        out.append(([b.populations(h).cpu().numpy() for h in range(len(geoms))], b.probe()))
+    for pops, tr in out[1:]:
+        for h in range(len(geoms)):
+            assert np.array_equal(pops[h], out[0][0][h]), h
+        assert np.array_equal(tr, out[0][1])
+
+
 def test_source_errors():
     geom, src, probes = cyl()
     N = W.num_nodes(geom)
