@@ -20,32 +20,37 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM peak; shape-spectra/sec batched+surrogate vs plain LBM"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_cylinder_128x128x256.txt")
+# committed counter summaries per configuration, and the kernel sources they cover
+TRAFFIC = {1: ("traffic_step_cylinder_128x128x256.txt", ("step_march.hip", "step.hip", "lbw_internal.h")),
+           4: ("traffic_step_general_duct_128x128x128.txt", ("step_general.hip", "lbw_internal.h"))}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def kernel_source_hash(config: int = 1):
     h = hashlib.sha256()
-    for name in ("step_march.hip", "step.hip", "lbw_internal.h"):
+    for name in TRAFFIC[config][1]:
         with open(os.path.join(ROOT, "paper_1705_01801_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current step kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(config: int = 1):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this configuration, if it was taken on the current kernel source."""
+    if config not in TRAFFIC:
+        return None
+    path = os.path.join(ROOT, "profiles", TRAFFIC[config][0])
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(config):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -170,7 +175,7 @@ def main():
     # 9 float coefficients read per node for a geometry given by its metric
     bytes_per_launch = (92.0 if general else 56.0) * N
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
-    traffic = read_traffic() if args.config == 1 else None  # counters were taken on the cylinder
+    traffic = read_traffic(args.config)
     # practical ceiling: a device-to-device copy moving the same bytes
     src = torch.empty(7 * N, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
