@@ -182,7 +182,7 @@ def run(points: int = 119, steps: int = W.PIPE_STEPS, plain: int = 4, ends=("fix
     return rep
 
 
-def run_torus(points: int = 499, steps: int = W.TORUS_STEPS, modes: int = 400) -> dict:
+def run_torus(points: int = 499, steps: int = W.TORUS_STEPS, modes: int = 400, plain: int = 2) -> dict:
     """The torus sweep of Sec. IV.C: the small ring (rho_min, theta = 0, all
     phi) driven at every frequency, one torus copy per frequency in one
     batch, intensity opposite the source on the major circle.  The paper has
@@ -206,12 +206,30 @@ def run_torus(points: int = 499, steps: int = W.TORUS_STEPS, modes: int = 400) -
     t_step = time.perf_counter() - t0
     amp = b.amplitude(T // 2, T).reshape(len(omegas), len(probes))
     b.close()
+    plain_rep = None
+    if plain > 0:                                    # a few points one at a time
+        idx = np.linspace(0, len(omegas) - 1, plain).astype(int)
+        same = True
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in idx:
+            sim = Simulation(Geometry(geom), np.zeros(N), probes, t_max=T)
+            sim.set_sources(ring, 1.0, float(omegas[i]))
+            sim.step(T)
+            same = same and bool(np.array_equal(sim.amplitude(T // 2, T), amp[i]))
+            sim.close()
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        plain_rep = {"points": len(idx), "seconds": tp, "points_per_s": len(idx) / tp, "identical_to_batched": same}
     rep = {"workload": "driven torus 20x200x30 (rho, theta, phi), R 640, rho in [5.12, 409.6], small-ring source, "
                        "c %.2f, damping %.2f" % (geom["c"], geom["damp"]),
            "points": len(omegas), "omegas": [float(omegas[0]), float(omegas[-1]), len(omegas)], "steps": T,
            "nodes": int(N * len(omegas)),
            "batched": {"step_seconds": t_step, "points_per_s": len(omegas) / t_step,
                        "glups": N * len(omegas) * T / t_step / 1e9}}
+    if plain_rep:
+        rep["plain"] = plain_rep
+        rep["batched_vs_plain"] = rep["batched"]["points_per_s"] / plain_rep["points_per_s"]
     # the same torus without losses, rung down from the small ring
     lossless = dict(geom, damp=1.0)
     P0 = np.zeros(N)
