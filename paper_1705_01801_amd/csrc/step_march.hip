@@ -363,8 +363,21 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
                 // whole-row tile: population 1 of this node comes from the
                 // lane on the left (or the wall at x = 0), population 2 from
                 // the lane on the right (or the wall at x = n0 - 1)
-                const float from_left = __shfl_up(fs[1], 1, TX);
-                const float from_right = __shfl_down(fs[2], 1, TX);
+                float from_left, from_right;
+                if constexpr (TX > 64) {
+                    // a row spans two waves: exchange through LDS (the reads
+                    // of the previous plane ended before this plane's first
+                    // barrier, so the slots are free)
+                    __shared__ float sX[2][NT];
+                    sX[0][threadIdx.x] = fs[1];
+                    sX[1][threadIdx.x] = fs[2];
+                    __syncthreads();
+                    from_left = sX[0][lx > 0 ? threadIdx.x - 1 : threadIdx.x];
+                    from_right = sX[1][lx < TX - 1 ? threadIdx.x + 1 : threadIdx.x];
+                } else {
+                    from_left = __shfl_up(fs[1], 1, TX);
+                    from_right = __shfl_down(fs[2], 1, TX);
+                }
                 const float in1 = jx_m >= 0 ? from_left : v2;
                 const float in2 = jx_p >= 0 ? from_right : v1;
                 v1 = row_tile ? in1 : v1;
@@ -518,6 +531,8 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restr
 int march_tx_for(int n0) { return n0 <= 16 ? 16 : (n0 <= 32 ? 32 : 64); }
 
 bool march_shape_ok(int tx, int ty) {
+    // 128-wide rows only with 4 of them: the ring needs 2 (tx + ty) loaders
+    if (tx == 128) return ty == 4;
     return (tx == 16 || tx == 32 || tx == 64) && (tx * ty == 256 || tx * ty == 512);
 }
 
@@ -543,6 +558,7 @@ void launch_of(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, con
 
 int march_blocks_per_cu(int tx, int ty) {
     const int nt = tx * ty;
+    if (tx == 128) return blocks_per_cu_of<128, 512>();
     if (nt == 512) return tx == 16 ? blocks_per_cu_of<16, 512>() : tx == 32 ? blocks_per_cu_of<32, 512>()
                                                                             : blocks_per_cu_of<64, 512>();
     return tx == 16 ? blocks_per_cu_of<16, 256>() : tx == 32 ? blocks_per_cu_of<32, 256>() : blocks_per_cu_of<64, 256>();
@@ -552,7 +568,9 @@ hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchP
                              float* fout, hipStream_t st) {
     if (!march_shape_ok(plan.tx, plan.ty)) return hipErrorInvalidValue;
     const int nt = plan.tx * plan.ty;
-    if (nt == 512) {
+    if (plan.tx == 128) {
+        launch_of<128, 512>(g, pr, plan, fin, fout, st);
+    } else if (nt == 512) {
         if (plan.tx == 16) launch_of<16, 512>(g, pr, plan, fin, fout, st);
         else if (plan.tx == 32) launch_of<32, 512>(g, pr, plan, fin, fout, st);
         else launch_of<64, 512>(g, pr, plan, fin, fout, st);
