@@ -265,7 +265,7 @@ def test_launch_shapes_bit_identical():
     ref = None
     for tx, ty, lz, blocks in [(64, 4, 16, 0), (32, 8, 1, 8), (32, 8, 5, 16), (64, 4, 37, 24), (64, 4, 64, 8),
                                (32, 8, 7, 0), (16, 16, 16, 0), (16, 16, 3, 8), (64, 8, 16, 0), (32, 16, 5, 8),
-                               (16, 32, 9, 0), (128, 4, 16, 0), (128, 4, 5, 8)]:
+                               (16, 32, 9, 0), (128, 4, 16, 0), (128, 4, 5, 8), (96, 4, 16, 0), (96, 4, 4, 8)]:
         say("launch shape", tx, ty, lz, blocks)
         g = lbw.Geometry(geom)
         g.set_step_config(tx, ty, lz, blocks)
@@ -278,17 +278,19 @@ def test_launch_shapes_bit_identical():
             assert np.abs(sim.probe() - tr).max() <= 1e-5 * np.abs(tr).max()
         else:
             assert np.array_equal(fg, ref), (tx, ty, lz, blocks)
-    for bad in [(48, 4, 16, 0), (64, 2, 16, 0), (16, 64, 16, 0), (64, 4, 0, 0), (128, 2, 16, 0), (128, 8, 16, 0)]:
+    for bad in [(48, 4, 16, 0), (64, 2, 16, 0), (16, 64, 16, 0), (64, 4, 0, 0), (128, 2, 16, 0), (128, 8, 16, 0),
+                (96, 8, 16, 0)]:
         with pytest.raises(lbw.LbwError):
             lbw.Geometry(geom).set_step_config(*bad)
 
 
 def test_whole_row_tiles_bit_identical():
-    """Walled axis 0 of up to 128 nodes: 128 x 4 tiles hold whole rows and
-    pass the axis-0 populations across the two waves of a row through LDS;
-    64-wide tiles store them shifted.  Both match the oracle and each other
-    bit for bit, on a curvilinear grid (cylinder, n0 = 100 and 128)."""
-    for n in ((100, 12, 20), (128, 9, 14)):
+    """Walled axis 0 of up to 96 or 128 nodes: 96 x 4 and 128 x 4 tiles hold
+    whole rows and pass the axis-0 populations across the waves of a row
+    through LDS; narrower tiles, and 96-wide tiles on longer rows, store them
+    shifted.  All match the oracle and each other bit for bit, on a
+    curvilinear grid (cylinder, n0 = 90, 100 and 128)."""
+    for n in ((90, 10, 16), (100, 12, 20), (128, 9, 14)):
         geom = dict(W.closed_cylinder(scale=1), n=n)
         N = W.num_nodes(geom)
         P0 = np.random.default_rng(3).uniform(-1, 1, N)
@@ -296,7 +298,8 @@ def test_whole_row_tiles_bit_identical():
         o = oracle.Oracle(geom)
         f, tr = o.run(o.init(P0), 50, probes)
         ref = None
-        for tx, ty, lz, blocks in [(64, 4, 16, 0), (128, 4, 16, 0), (128, 4, 3, 8), (32, 8, 7, 0)]:
+        for tx, ty, lz, blocks in [(64, 4, 16, 0), (128, 4, 16, 0), (128, 4, 3, 8), (32, 8, 7, 0), (96, 4, 16, 0),
+                                   (96, 4, 5, 8)]:
             say("whole-row tiles", n, tx, ty, lz, blocks)
             g = lbw.Geometry(geom)
             g.set_step_config(tx, ty, lz, blocks)
