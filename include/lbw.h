@@ -145,8 +145,8 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max);
  * arithmetic, and so every result, is the same for every shape; only speed
  * changes).  A workgroup owns a tile_x x tile_y tile of (axis 0, axis 1)
  * columns: tile_x is 16, 32 or 64 and tile_x * tile_y, the workgroup size,
- * is 256 or 512, or the tile is 96 x 4, 128 x 4 or 128 x 8 (384, 512 or
- * 1024 threads; rows of up to 96 or 128 nodes in one tile); chunk_z >= 1
+ * is 256 or 512, or the tile is 96 x 4, 96 x 8, 128 x 4 or 128 x 8 (384
+ * to 1024 threads; rows of up to 96 or 128 nodes in one tile); chunk_z >= 1
  * planes per tile along axis 2; blocks:
  * persistent grid size, rounded down to a multiple of 8 (0 = one full wave
  * of resident workgroups).  Used by lbw_autotune and by tests.

@@ -378,7 +378,7 @@ int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, i
     if (!lbw::march_shape_ok(tile_x, tile_y))
         return fail(LBW_EINVAL,
                     "tile %d x %d: tile_x must be 16, 32 or 64 with tile_x * tile_y 256 or 512, or the tile "
-                    "96 x 4, 128 x 4 or 128 x 8",
+                    "96 x 4, 96 x 8, 128 x 4 or 128 x 8",
                     tile_x, tile_y);
     if (chunk_z < 1 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 1 and blocks >= 0");
     if (blocks == 0) {
@@ -547,7 +547,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     lbw::MarchPlan best = keep;
     float best_ms = 1e30f;
     float* other = s->f[1 - s->cur];
-    for (int nt : {256, 384, 512, 1024})
+    for (int nt : {256, 384, 512, 768, 1024})
     for (int tx : {16, 32, 64, 96, 128}) {
         if (err != hipSuccess) break;
         const int ty = nt / tx;

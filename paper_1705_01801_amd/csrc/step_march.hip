@@ -531,10 +531,9 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restr
 int march_tx_for(int n0) { return n0 <= 16 ? 16 : (n0 <= 32 ? 32 : 64); }
 
 bool march_shape_ok(int tx, int ty) {
-    // 96-wide rows only with 4 of them (384 threads), 128-wide ones with 4
-    // or 8 (512 or 1024 threads): the ring needs 2 (tx + ty) loaders
-    if (tx == 128) return ty == 4 || ty == 8;
-    if (tx == 96) return ty == 4;
+    // 96- and 128-wide rows only with 4 or 8 of them (384 to 1024 threads):
+    // the ring needs 2 (tx + ty) loaders
+    if (tx == 96 || tx == 128) return ty == 4 || ty == 8;
     return (tx == 16 || tx == 32 || tx == 64) && (tx * ty == 256 || tx * ty == 512);
 }
 
@@ -561,7 +560,7 @@ void launch_of(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, con
 int march_blocks_per_cu(int tx, int ty) {
     const int nt = tx * ty;
     if (tx == 128) return nt == 1024 ? blocks_per_cu_of<128, 1024>() : blocks_per_cu_of<128, 512>();
-    if (tx == 96) return blocks_per_cu_of<96, 384>();
+    if (tx == 96) return nt == 768 ? blocks_per_cu_of<96, 768>() : blocks_per_cu_of<96, 384>();
     if (nt == 512) return tx == 16 ? blocks_per_cu_of<16, 512>() : tx == 32 ? blocks_per_cu_of<32, 512>()
                                                                             : blocks_per_cu_of<64, 512>();
     return tx == 16 ? blocks_per_cu_of<16, 256>() : tx == 32 ? blocks_per_cu_of<32, 256>() : blocks_per_cu_of<64, 256>();
@@ -575,6 +574,8 @@ hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchP
         launch_of<128, 1024>(g, pr, plan, fin, fout, st);
     } else if (plan.tx == 128) {
         launch_of<128, 512>(g, pr, plan, fin, fout, st);
+    } else if (plan.tx == 96 && nt == 768) {
+        launch_of<96, 768>(g, pr, plan, fin, fout, st);
     } else if (plan.tx == 96) {
         launch_of<96, 384>(g, pr, plan, fin, fout, st);
     } else if (nt == 512) {

@@ -280,7 +280,7 @@ def test_launch_shapes_bit_identical():
         else:
             assert np.array_equal(fg, ref), (tx, ty, lz, blocks)
     for bad in [(48, 4, 16, 0), (64, 2, 16, 0), (16, 64, 16, 0), (64, 4, 0, 0), (128, 2, 16, 0), (128, 16, 16, 0),
-                (96, 8, 16, 0)]:
+                (96, 2, 16, 0), (96, 16, 16, 0)]:
         with pytest.raises(lbw.LbwError):
             lbw.Geometry(geom).set_step_config(*bad)
 
@@ -300,7 +300,7 @@ def test_whole_row_tiles_bit_identical():
         f, tr = o.run(o.init(P0), 50, probes)
         ref = None
         for tx, ty, lz, blocks in [(64, 4, 16, 0), (128, 4, 16, 0), (128, 4, 3, 8), (32, 8, 7, 0), (96, 4, 16, 0),
-                                   (96, 4, 5, 8), (128, 8, 16, 0), (128, 8, 6, 8)]:
+                                   (96, 4, 5, 8), (128, 8, 16, 0), (128, 8, 6, 8), (96, 8, 16, 0), (96, 8, 7, 8)]:
             say("whole-row tiles", n, tx, ty, lz, blocks)
             g = lbw.Geometry(geom)
             g.set_step_config(tx, ty, lz, blocks)
