@@ -287,17 +287,19 @@ int lbw_batch_layout(lbw_batch_t b, int64_t* node_offsets, int64_t* probe_offset
 
 /* Launch shape shared by all geometries of the batch (as
  * lbw_set_step_config, with 256-thread workgroups: tile_y = 256 / tile_x).
- * tile_x = 0 selects whole-section tiles instead: each workgroup (128 or
- * 256 threads) takes one geometry's entire (axis 0, axis 1) cross-section
- * over a chunk of planes, for batches of small cross-sections (every
- * geometry needs n0 n1, 2 (n0 + n1) and n0 + 2 at most 256, else
- * LBW_EINVAL).  Results are identical for every shape.  The default made
- * by lbw_batch_make is chunk_z 16, two waves of resident workgroups, and
- * the tile with the fewest idle lanes over all geometries: tile_x = 16, 32
- * or 64 (lanes: sum of ceil(n0/tile_x) tile_x * ceil(n1/tile_y) tile_y *
- * n2, ties to the wider tile) or whole sections (lanes: workgroup size *
- * n2).  lbw_batch_autotune is switched off in this version and returns
- * LBW_ESTATE without launching anything; set shapes with
+ * tile_x = 0 selects whole-row tiles instead: each workgroup (128, 256 or
+ * 512 threads, one size for the batch) takes r whole axis-0 rows of one
+ * geometry over a chunk of planes, r the most rows with n0 r and
+ * 2 (n0 + r) at most the workgroup size (the whole cross-section when it
+ * fits); every geometry needs n0 + 2 <= 512 and r >= 1, else LBW_EINVAL.
+ * Results are identical for every shape.  The default made by
+ * lbw_batch_make is chunk_z 16 and the tile with the fewest idle lanes
+ * over all geometries: tile_x = 16, 32 or 64 (lanes: sum of
+ * ceil(n0/tile_x) tile_x * ceil(n1/tile_y) tile_y * n2, ties to the wider
+ * tile; two waves of resident workgroups) or whole rows (lanes: workgroup
+ * size * ceil(n1/r) * n2, ties to TX-wide tiles; one wave of resident
+ * workgroups).  lbw_batch_autotune is switched off in this version and
+ * returns LBW_ESTATE without launching anything; set shapes with
  * lbw_batch_set_step_config. */
 int lbw_batch_set_step_config(lbw_batch_t b, int tile_x, int chunk_z, int blocks);
 int lbw_batch_get_step_config(lbw_batch_t b, int* tile_x, int* chunk_z, int* blocks);

@@ -17,7 +17,7 @@ struct lbw_batch {
     std::vector<lbw::BatchItem> items;
     lbw::BatchItem* d_items = nullptr;
     int tx = 32, lz = 16, blocks = 8;
-    int section_nt = 0;  // > 0: whole-section tiles of this many threads (tx unused)
+    int section_nt = 0;  // > 0: whole-row tiles of this many threads (tx unused)
     int64_t tiles = 0;
     int plan_version = 0;
     float* f[2] = {nullptr, nullptr};
@@ -84,8 +84,9 @@ hipError_t build_items(lbw_batch* b) {
         it.c2 = v.c2;
         it.two_w0 = v.two_w0;
         it.damp = v.damp;
+        it.rty = b->section_nt ? lbw::batch_row_tile(v.n0, v.n1, b->section_nt) : 0;
         it.ntx = b->section_nt ? 1 : (v.n0 + b->tx - 1) / b->tx;
-        it.nty = b->section_nt ? 1 : (v.n1 + ty - 1) / ty;
+        it.nty = b->section_nt ? (v.n1 + it.rty - 1) / it.rty : (v.n1 + ty - 1) / ty;
         it.lz = b->lz;
         const int nchunks = (v.n2 + b->lz - 1) / b->lz;
         it.tile_begin = tile;
@@ -156,32 +157,45 @@ void drop_graphs(lbw_batch* b) {
 }
 
 
-// Workgroup size for whole-section tiles over the whole batch (the largest
-// any geometry needs), or 0 if some cross-section does not fit one.
-int section_threads(const lbw_batch* b) {
-    int nt = 0;
+// Lanes allotted over the whole batch by whole-row tiles of nt threads
+// (0 if some geometry's rows do not fit them).
+double row_slots(const lbw_batch* b, int nt) {
+    double slots = 0.0;
     for (int h = 0; h < b->n; ++h) {
-        const int t = lbw::batch_section_threads(b->d[h].n[0], b->d[h].n[1]);
-        if (t == 0) return 0;
-        nt = t > nt ? t : nt;
+        const lbw_geometry_desc& d = b->d[h];
+        const int r = lbw::batch_row_tile(d.n[0], d.n[1], nt);
+        if (r == 0) return 0.0;
+        slots += (double)nt * (double)((d.n[1] + r - 1) / r) * (double)d.n[2];
     }
-    return nt;
+    return slots;
+}
+
+// Workgroup size for whole-row tiles over the whole batch: the one of 128,
+// 256 and 512 threads that leaves the fewest lanes idle (ties to the
+// larger), or 0 if some geometry's rows fit none.
+int section_threads(const lbw_batch* b) {
+    int best = 0;
+    double best_slots = 0.0;
+    for (int nt : {512, 256, 128}) {
+        const double sl = row_slots(b, nt);
+        if (sl > 0.0 && (best == 0 || sl < best_slots)) {
+            best = nt;
+            best_slots = sl;
+        }
+    }
+    return best;
 }
 
 // Lanes allotted over the whole batch: TX-wide tiles (tile_x > 0) or
-// whole-section tiles (tile_x = 0).
+// whole-row tiles (tile_x = 0).
 double lane_slots(const lbw_batch* b, int tile_x) {
+    if (tile_x == 0) return row_slots(b, section_threads(b));
     double slots = 0.0;
-    const int nt = section_threads(b);
     for (int h = 0; h < b->n; ++h) {
         const lbw_geometry_desc& d = b->d[h];
-        if (tile_x == 0) {
-            slots += (double)nt * (double)d.n[2];
-        } else {
-            const int ty = 256 / tile_x;
-            slots += (double)((d.n[0] + tile_x - 1) / tile_x * tile_x) * (double)((d.n[1] + ty - 1) / ty * ty) *
-                     (double)d.n[2];
-        }
+        const int ty = 256 / tile_x;
+        slots += (double)((d.n[0] + tile_x - 1) / tile_x * tile_x) * (double)((d.n[1] + ty - 1) / ty * ty) *
+                 (double)d.n[2];
     }
     return slots;
 }
@@ -191,7 +205,7 @@ int set_config(lbw_batch* b, int tile_x, int chunk_z, int blocks) {
     int rc = lbw::device_cus(&cus);
     if (rc) return rc;
     const int nt = tile_x == 0 ? section_threads(b) : 0;
-    if (tile_x == 0 && nt == 0) return fail(LBW_EINVAL, "a cross-section is too large for whole-section tiles");
+    if (tile_x == 0 && nt == 0) return fail(LBW_EINVAL, "axis-0 rows too long for whole-row tiles");
     if (blocks == 0) blocks = cus * (nt ? lbw::batch_section_blocks_per_cu(nt) : lbw::batch_blocks_per_cu(tile_x));
     blocks = (blocks / 8) * 8;
     if (blocks < 8) blocks = 8;
@@ -293,12 +307,14 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
     }
     int rc = LBW_OK;
     {
-        // default: chunk 16, two waves of resident workgroups (measured best
-        // on the 512-horn ensemble among chunks 8..128 and one or two
-        // waves), and the tile with the fewest idle lanes over the whole
-        // batch: TX-wide (lanes allotted = sum over geometries of
+        // default: chunk 16 and the tile with the fewest idle lanes over
+        // the whole batch: TX-wide (lanes allotted = sum over geometries of
         // ceil(n0 / TX) TX ceil(n1 / TY) TY n2, ties to the wider tile) or
-        // whole cross-sections (workgroup size times n2)
+        // whole rows (workgroup size times the tiles per plane times n2;
+        // ties to TX-wide tiles); two waves of resident workgroups for
+        // TX-wide tiles (measured best on the 512-horn ensemble among chunks
+        // 8..128 and one or two waves), one for whole-row tiles (measured
+        // on a 64-horn ensemble: 136 against 152 us per step)
         int cus = 0;
         rc = lbw::device_cus(&cus);
         int tx = 64;
@@ -313,7 +329,7 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
         const int nt = section_threads(b);
         if (nt > 0 && lane_slots(b, 0) < best) tx = 0;
         const int bpc = tx == 0 ? lbw::batch_section_blocks_per_cu(nt) : lbw::batch_blocks_per_cu(tx);
-        if (rc == LBW_OK) rc = set_config(b, tx, 16, 2 * cus * bpc);
+        if (rc == LBW_OK) rc = set_config(b, tx, 16, (tx == 0 ? 1 : 2) * cus * bpc);
     }
     if (rc == LBW_OK && b->P > 0 && hipStreamSynchronize(b->stream) != hipSuccess)
         rc = fail(LBW_EDEVICE, "lbw_batch_make: synchronise");

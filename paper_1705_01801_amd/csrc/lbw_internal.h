@@ -104,6 +104,7 @@ struct BatchItem {
     int bc_lo[3], bc_hi[3];
     float c2, two_w0, damp;
     int ntx, nty, lz;
+    int rty;             // rows per tile when the tiles hold whole rows (run-time tiles)
     int64_t tile_begin;  // first global tile of this geometry
     int64_t tiles;
     uint64_t f_off;      // float offset of the population block (Q * N floats)
@@ -122,13 +123,13 @@ struct BatchProbeArgs {
     const float4* tab4;    // device, batch float table (2 float4 per record)
 };
 int batch_blocks_per_cu(int tx);
-// Workgroup size of a whole-section tile for an n0 x n1 cross-section (128
-// or 256 threads, covering the section, its ring loaders and its row
-// loaders), or 0 when the section is too large for one.
-int batch_section_threads(int n0, int n1);
+// Rows per whole-row tile of nt threads (128, 256 or 512) for an n0 x n1
+// cross-section: the most rows r <= n1 with n0 r <= nt lanes and
+// 2 (n0 + r) <= nt ring loaders (and n0 + 2 <= nt row loaders), or 0.
+int batch_row_tile(int n0, int n1, int nt);
 int batch_section_blocks_per_cu(int nt);
-// section_nt > 0 selects whole-section tiles of section_nt threads (the tile
-// list must then hold one tile per chunk of planes, ntx = nty = 1).
+// section_nt > 0 selects whole-row tiles of section_nt threads (the tile
+// list must then hold ntx = 1 and nty = ceil(n1 / rty) tiles per chunk).
 hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int section_nt,
                              int blocks, const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st);
 

@@ -124,12 +124,11 @@ __device__ inline float bounce(int wall, float damp, float out_l, float own_lb) 
 // [z0, z0 + lz).  fin/fout point at the geometry's own population block.
 // RT: the tile is g.rtx x g.rty columns instead (at most NT of them, with
 // 2 (rtx + rty) <= NT ring loaders and rtx + 2 <= NT row loaders, checked by
-// the host); TX = NT then only sizes the LDS arrays, and ROW must be false.
+// the host); TX = NT then only sizes the LDS arrays.
 template <int TX, int NT, bool ROW, bool RT = false>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
                                            float* __restrict__ fout, float (&sS)[2][lds_s<TX, NT, RT>()],
                                            float4 (&sElo)[3][TX + 3], float4 (&sEhi)[3][TX + 3]) {
-    static_assert(!(RT && ROW), "run-time tiles use the shifted stores");
     const int TXr = RT ? g.rtx : TX;
     const int TY = RT ? g.rty : NT / TX;
     const int W = TXr + 2;
@@ -365,7 +364,8 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
                 // the lane on the right (or the wall at x = n0 - 1)
                 float from_left, from_right;
                 if constexpr (TX > 64) {
-                    // a row spans two waves: exchange through LDS (the reads
+                    // a row may span several waves (always so for run-time
+                    // tiles, where TX = NT): exchange through LDS (the reads
                     // of the previous plane ended before this plane's first
                     // barrier, so the slots are free)
                     __shared__ float sX[2][NT];
@@ -373,7 +373,11 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
                     sX[1][threadIdx.x] = fs[2];
                     __syncthreads();
                     from_left = sX[0][lx > 0 ? threadIdx.x - 1 : threadIdx.x];
-                    from_right = sX[1][lx < TX - 1 ? threadIdx.x + 1 : threadIdx.x];
+                    // (a run-time tile may end inside a row: the last lane
+                    // then has no right neighbour in the workgroup; its
+                    // value is unused, the index is kept in range)
+                    const unsigned xr = lx < TXr - 1 ? threadIdx.x + 1 : threadIdx.x;
+                    from_right = sX[1][RT ? min(xr, (unsigned)NT - 1) : xr];
                 } else {
                     from_left = __shfl_up(fs[1], 1, TX);
                     from_right = __shfl_down(fs[2], 1, TX);
@@ -456,10 +460,10 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
 // one list (geometry h owns tiles [tile_begin, tile_begin + tiles)), split
 // into one contiguous range per XCD.  Block b first records the probes of
 // geometries b, b + gridDim.x, ... (one step counter per geometry).
-// SECTION: every tile is a whole (axis 0, axis 1) cross-section of its
-// geometry (run-time tile n0 x n1, one tile per chunk of planes), for
-// batches of small cross-sections that a TX-wide tile would leave mostly
-// idle; TX = NT then only sizes the LDS arrays.
+// SECTION: every tile holds whole axis-0 rows of its geometry (run-time
+// tile n0 x rty, rty rows chosen per geometry by the host; the whole
+// cross-section when it fits), for geometries whose rows a TX-wide tile
+// would split or leave mostly idle; TX = NT then only sizes the LDS arrays.
 template <int TX, int NT, bool SECTION>
 __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restrict__ items, int n_items,
                                                          int64_t tiles_total, BatchProbeArgs bp,
@@ -520,9 +524,9 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restr
         tg.nty = it.nty;
         tg.lz = it.lz;
         tg.rtx = it.n0;
-        tg.rty = it.n1;
-        march_tile<TX, NT, !SECTION, SECTION>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS,
-                                              sElo, sEhi);
+        tg.rty = it.rty;
+        march_tile<TX, NT, true, SECTION>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sElo,
+                                          sEhi);
     }
 }
 
@@ -602,17 +606,18 @@ int batch_blocks_per_cu(int tx) {
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-int batch_section_threads(int n0, int n1) {
-    const int need = max(n0 * n1, max(2 * (n0 + n1), n0 + 2));
-    return need <= 128 ? 128 : (need <= 256 ? 256 : 0);
+int batch_row_tile(int n0, int n1, int nt) {
+    if (n0 < 1 || n1 < 1 || n0 + 2 > nt) return 0;
+    int r = min(n1, min(nt / n0, nt / 2 - n0));
+    return r >= 1 ? r : 0;
 }
 
 int batch_section_blocks_per_cu(int nt) {
     int nb = 0;
-    hipError_t e = nt == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<128, 128, true>,
-                                                                            128, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<256, 256, true>,
-                                                                            256, 0);
+    hipError_t e =
+        nt == 128   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<128, 128, true>, 128, 0)
+        : nt == 256 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<256, 256, true>, 256, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<512, 512, true>, 512, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
@@ -623,6 +628,9 @@ hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_
                            tiles_total, bp, fin, fout);
     else if (section_nt == 256)
         hipLaunchKernelGGL((step_batch_kernel<256, 256, true>), dim3(blocks), dim3(256), 0, st, items, n_items,
+                           tiles_total, bp, fin, fout);
+    else if (section_nt == 512)
+        hipLaunchKernelGGL((step_batch_kernel<512, 512, true>), dim3(blocks), dim3(512), 0, st, items, n_items,
                            tiles_total, bp, fin, fout);
     else if (tx == 16)
         hipLaunchKernelGGL((step_batch_kernel<16, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
