@@ -131,7 +131,8 @@ def test_batch_launch_shapes_and_graphs_identical():
     """Launch shapes and graph blocks change nothing (no autotuning)."""
     geoms, P0s, probes = members()
     ref = None
-    for cfg, block in [((32, 16, 0), 0), ((64, 5, 8), 16), ((32, 64, 24), 7), ((16, 16, 0), 32), ((16, 9, 16), 5)]:
+    for cfg, block in [((32, 16, 0), 0), ((64, 5, 8), 16), ((32, 64, 24), 7), ((16, 16, 0), 32), ((16, 9, 16), 5),
+                       ((0, 16, 0), 8), ((0, 5, 16), 3)]:
         say("batch shape", cfg, block)
         b = lbw.Batch(geoms, P0s, probes, t_max=70)
         b.set_step_config(*cfg)
