@@ -35,7 +35,7 @@ class _Geom(ctypes.Structure):
         ("n", ctypes.c_int32 * 3),
         ("bc_lo", ctypes.c_int32 * 3),
         ("bc_hi", ctypes.c_int32 * 3),
-        ("pad", ctypes.c_int32),
+        ("hermite", ctypes.c_int32),
         ("qmin", ctypes.c_double * 3),
         ("qmax", ctypes.c_double * 3),
         ("href", ctypes.c_double),
@@ -99,6 +99,10 @@ def _to_struct(geom: dict) -> _Geom:
         s.qmax[a] = float(qmax[a])
         s.bc_lo[a] = BCS[lo[a]]
         s.bc_hi[a] = BCS[hi[a]]
+    eq = geom.get("equilibrium", "corrected")
+    if eq not in ("corrected", "hermite") or (eq == "hermite" and geom["kind"] != "box"):
+        raise ValueError("equilibrium must be 'corrected', or 'hermite' on a box")
+    s.hermite = 1 if eq == "hermite" else 0
     s.href = float(geom["h_ref"])
     s.c = float(geom["c"])
     s.damp = float(geom.get("damp", 1.0))

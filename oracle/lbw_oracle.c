@@ -43,7 +43,7 @@ typedef struct {
     int32_t n[3];
     int32_t bc_lo[3];
     int32_t bc_hi[3];
-    int32_t pad;
+    int32_t hermite;   /* 1: the Hermite-expansion equilibrium of Sec. II (Cartesian box only) */
     double qmin[3];
     double qmax[3];
     double href;
@@ -329,12 +329,24 @@ int orc_maps(const orc_geom* g, uint8_t* mask, int32_t* pull) {
 
 /* Initial populations: the corrected equilibrium (Sec. III) at rest,
  * f_l = w_l sqrt(g) P0, i.e. zero first moment. */
+/* Weight of population l in the equilibrium at rest (J = 0) per unit of
+ * sqrt(g) P: the corrected equilibrium of Sec. III (w_0 = 1 - D c^2,
+ * w = c^2 / 2) or, for the Hermite form of Sec. II, its rest value
+ * w [1 + (c^2 - c_s^2)(1 - D c_s^2) / (2 c_s^4)] with f_0 taking the rest. */
+static double orc_rest_weight(const orc_geom* g, int l) {
+    int d = g->dim;
+    double c2 = g->c * g->c;
+    if (!g->hermite) return (l == 0) ? 1.0 - d * c2 : 0.5 * c2;
+    double cs2 = 1.0 / (d + 1), w = 0.5 * cs2;
+    double wl = w * (1.0 + (c2 - cs2) * (1.0 - d * cs2) / (2.0 * cs2 * cs2));
+    return (l == 0) ? 1.0 - 2 * d * wl : wl;
+}
+
 int orc_init(const orc_geom* g, const double* sqrtg, const double* P0, double* f) {
     int d = g->dim, Q = 2 * d + 1;
     int64_t N = orc_nodes(g);
-    double c2 = g->c * g->c;
     for (int l = 0; l < Q; ++l) {
-        double w = (l == 0) ? 1.0 - d * c2 : 0.5 * c2;
+        double w = orc_rest_weight(g, l);
         for (int64_t n = 0; n < N; ++n) f[l * N + n] = w * sqrtg[n] * P0[n];
     }
     return 0;
@@ -359,6 +371,34 @@ static int orc_mcomp(int d, int e) {
  *  pass 3: pull streaming f_l(x, t+1) = f*_l(x - xi_l) with wall rules.
  * A values beyond a wall are mirrored: even for bounce-back and free walls,
  * odd for fixed (P = 0) walls; periodic axes wrap. */
+/* Collision with the Hermite-expansion equilibrium of Sec. II (Cartesian,
+ * no forcing), written as printed: the lattice weights of D2Q5/D3Q7
+ * (w_0 = c_s^2 = 1 / (D + 1), w = c_s^2 / 2), P = sum_l f_l, J = sum_l f_l xi_l,
+ * f_i^eq = w [P + xi_i.J / c_s^2 + P (c^2 - c_s^2)(xi_i^2 - D c_s^2) / (2 c_s^4)]
+ * for i >= 1 (the printed 3 c_s^2 is D c_s^2 for D = 3) and
+ * f_0^eq = P - sum_{i>=1} f_i^eq; post-collision f* = 2 f^eq - f (tau = 1/2). */
+static void orc_collide_hermite(const orc_geom* g, const double* f, double* fs) {
+    int d = g->dim, Q = 2 * d + 1;
+    int64_t N = orc_nodes(g);
+    double cs2 = 1.0 / (d + 1), w = 0.5 * cs2, c2 = g->c * g->c;
+    for (int64_t n = 0; n < N; ++n) {
+        double P = 0.0, J[3] = {0.0, 0.0, 0.0};
+        for (int l = 0; l < Q; ++l) {
+            P += f[l * N + n];
+            if (l > 0) J[orc_axis_of(l)] += orc_sign_of(l) * f[l * N + n];
+        }
+        double sum = 0.0;
+        for (int l = 1; l < Q; ++l) {
+            double xiJ = orc_sign_of(l) * J[orc_axis_of(l)];
+            double xi2 = 1.0;
+            double feq = w * (P + xiJ / cs2 + P * (c2 - cs2) * (xi2 - d * cs2) / (2.0 * cs2 * cs2));
+            sum += feq;
+            fs[l * N + n] = 2.0 * feq - f[l * N + n];
+        }
+        fs[n] = 2.0 * (P - sum) - f[n];
+    }
+}
+
 int orc_step(const orc_geom* g, const double* Mhat, const double* Gamh, double* f, double* fs, double* S) {
     int d = g->dim, Q = 2 * d + 1;
     int64_t N = orc_nodes(g);
@@ -372,6 +412,8 @@ int orc_step(const orc_geom* g, const double* Mhat, const double* Gamh, double* 
         S[n] = s;
     }
 
+    if (g->hermite) orc_collide_hermite(g, f, fs);
+    else
     for (int i2 = 0; i2 < n2; ++i2)
         for (int i1 = 0; i1 < g->n[1]; ++i1)
             for (int i0 = 0; i0 < g->n[0]; ++i0) {
@@ -444,7 +486,6 @@ static void orc_impose(const orc_geom* g, const double* sqrtg, double* f, int64_
                        double amp, double omega, int kind) {
     int d = g->dim, Q = 2 * d + 1;
     int64_t N = orc_nodes(g);
-    double c2 = g->c * g->c;
     double v = amp * sin(omega * (double)t);
     for (int i = 0; i < ns; ++i) {
         int64_t n = src[i];
@@ -452,7 +493,7 @@ static void orc_impose(const orc_geom* g, const double* sqrtg, double* f, int64_
         if (kind > 0)
             for (int l = 0; l < Q; ++l) S += f[l * N + n];
         for (int l = 0; l < Q; ++l) {
-            double w = (l == 0) ? 1.0 - d * c2 : 0.5 * c2;
+            double w = orc_rest_weight(g, l);
             if (kind == 0) {
                 f[l * N + n] = w * sqrtg[n] * v;
             } else {
