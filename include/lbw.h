@@ -67,13 +67,26 @@ enum { LBW_BOX = 0, LBW_POLAR2D = 1, LBW_CYLINDER = 2, LBW_HORN = 3, LBW_TORUS =
  *  FIXED       half-way anti-bounce-back, pressure P = 0 on the wall */
 enum { LBW_BC_PERIODIC = 0, LBW_BC_BOUNCEBACK = 1, LBW_BC_FREE = 2, LBW_BC_FIXED = 3 };
 
+/* Equilibrium.
+ *  CORRECTED  the corrected equilibrium of Sec. III, f_0 = w_0 sqrt(g) P,
+ *             f_l = w sqrt(g) (P + xi_l.J' / c^2) with c_s = c (every kind)
+ *  HERMITE    the Hermite-expansion equilibrium of Sec. II, Cartesian boxes
+ *             only: the fixed D2Q5/D3Q7 weights (c_s^2 = 1/(D+1), w = c_s^2/2)
+ *             plus the second-order term P (c^2 - c_s^2)(xi^2 - D c_s^2) /
+ *             (2 c_s^4), f_0 = P - sum_{l>=1} f_l.  Its second moment is
+ *             c_eff^2 P, c_eff^2 = c_s^2 + (c^2 - c_s^2)(1 - D c_s^2) / (2 c_s^2)
+ *             (c^2/2 + 1/8 on D3Q7), so it steps exactly as CORRECTED at wave
+ *             speed c_eff, which is how the library runs it; the two coincide
+ *             at c = c_s. */
+enum { LBW_EQ_CORRECTED = 0, LBW_EQ_HERMITE = 1 };
+
 typedef struct {
     int32_t kind;      /* LBW_BOX ... LBW_BESSEL_HORN */
     int32_t dim;       /* 2 -> D2Q5, 3 -> D3Q7 */
     int32_t n[3];      /* nodes per axis (n[2] ignored for dim 2) */
     int32_t bc_lo[3];  /* wall code of the low face of each axis */
     int32_t bc_hi[3];  /* wall code of the high face of each axis */
-    int32_t reserved;  /* must be 0 */
+    int32_t equilibrium; /* LBW_EQ_CORRECTED or LBW_EQ_HERMITE (boxes only) */
     double qmin[3];    /* coordinate range; periodic axis nodes at qmin + i h, */
     double qmax[3];    /* walled axis nodes at qmin + (i + 1/2) h, h = (qmax - qmin) / n */
     double h_ref;      /* physical length of one lattice unit (> 0) */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblbw.so")
 
 KINDS = {"box": 0, "polar2d": 1, "cylinder": 2, "horn": 3, "torus": 4, "bessel_horn": 5, "general": 6}
 BCS = {"periodic": 0, "bounceback": 1, "free": 2, "fixed": 3}
+EQUILIBRIA = {"corrected": 0, "hermite": 1}
 EXPORT_TABLE_F64, EXPORT_MASK_U8, EXPORT_PULL_I32 = 0, 1, 2
 TABLE_PLANES = ("Mhat00", "Mhat11", "Mhat22", "Mhat02", "Gamh0", "Gamh1", "Gamh2", "sqrtg")
 
@@ -40,7 +41,7 @@ class GeometryDesc(ctypes.Structure):
         ("n", ctypes.c_int32 * 3),
         ("bc_lo", ctypes.c_int32 * 3),
         ("bc_hi", ctypes.c_int32 * 3),
-        ("reserved", ctypes.c_int32),
+        ("equilibrium", ctypes.c_int32),
         ("qmin", ctypes.c_double * 3),
         ("qmax", ctypes.c_double * 3),
         ("h_ref", ctypes.c_double),
@@ -160,7 +161,10 @@ def to_desc(geom: dict) -> GeometryDesc:
             d.bc_hi[a] = BCS[geom["bc_hi"][a]]
         else:
             d.n[a], d.qmin[a], d.qmax[a] = 1, 0.0, 1.0
-    d.reserved = 0
+    eq = geom.get("equilibrium", "corrected")
+    if eq not in EQUILIBRIA:
+        raise ValueError("equilibrium must be one of %s" % sorted(EQUILIBRIA))
+    d.equilibrium = EQUILIBRIA[eq]
     d.h_ref = float(geom["h_ref"])
     d.c = float(geom["c"])
     d.damping = float(geom.get("damp", 1.0))

@@ -101,6 +101,13 @@ lbw_geometry_desc normalised(const lbw_geometry_desc& in) {
     return d;
 }
 
+double lattice_c2(const lbw_geometry_desc& d) {
+    const double c2 = d.c * d.c;
+    if (d.equilibrium != LBW_EQ_HERMITE) return c2;
+    const double cs2 = 1.0 / (d.dim + 1);
+    return cs2 + (c2 - cs2) * (1.0 - d.dim * cs2) / (2.0 * cs2);
+}
+
 GeomDev make_geomdev(const lbw_geometry_desc& d, const float* tab32, const double* sqrtg) {
     GeomDev v{};
     v.dim = d.dim;
@@ -112,7 +119,7 @@ GeomDev make_geomdev(const lbw_geometry_desc& d, const float* tab32, const doubl
         v.bc_lo[a] = d.bc_lo[a];
         v.bc_hi[a] = d.bc_hi[a];
     }
-    const double c2 = d.c * d.c;
+    const double c2 = lattice_c2(d);
     v.c2 = (float)c2;
     v.two_w0 = (float)(2.0 * (1.0 - d.dim * c2));
     v.damp = (float)d.damping;
@@ -128,7 +135,10 @@ int validate_desc(const lbw_geometry_desc* d) {
     if (d->dim != 2 && d->dim != 3) return fail(LBW_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
     if (d->kind == LBW_POLAR2D && d->dim != 2) return fail(LBW_EINVAL, "polar2d needs dim 2");
     if (d->kind != LBW_POLAR2D && d->kind != LBW_BOX && d->dim != 3) return fail(LBW_EINVAL, "kind needs dim 3");
-    if (d->reserved != 0) return fail(LBW_EINVAL, "reserved field must be 0");
+    if (d->equilibrium != LBW_EQ_CORRECTED && d->equilibrium != LBW_EQ_HERMITE)
+        return fail(LBW_EINVAL, "unknown equilibrium %d", d->equilibrium);
+    if (d->equilibrium == LBW_EQ_HERMITE && d->kind != LBW_BOX)
+        return fail(LBW_EINVAL, "the Hermite equilibrium applies to Cartesian boxes only");
     int64_t N = 1;
     for (int a = 0; a < d->dim; ++a) {
         if (d->n[a] < 1) return fail(LBW_EINVAL, "n[%d] = %d < 1", a, d->n[a]);

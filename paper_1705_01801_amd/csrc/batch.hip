@@ -563,7 +563,7 @@ int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* ge
         const int64_t n0 = d.n[0], plane = n0 * d.n[1];
         const int64_t N = b->node_off[h + 1] - b->node_off[h];
         const double sq = sg[h][(size_t)(nodes[i] % n0 + n0 * (nodes[i] / plane))];
-        const double c2 = d.c * d.c;
+        const double c2 = lbw::lattice_c2(d);
         lbw::SourceEntry e{};
         e.f_off = (uint64_t)(7 * b->node_off[h] + nodes[i]);
         e.N = (uint32_t)N;

@@ -14,6 +14,11 @@ int validate_desc(const lbw_geometry_desc* d);
 lbw_geometry_desc normalised(const lbw_geometry_desc& d);
 // Kernel view of a geometry whose tables live at tab32 / sqrtg.
 GeomDev make_geomdev(const lbw_geometry_desc& d, const float* tab32, const double* sqrtg);
+// c^2 the kernels step with: the descriptor's c^2 for the corrected
+// equilibrium, the effective c_eff^2 = c_s^2 + (c^2 - c_s^2)(1 - D c_s^2) /
+// (2 c_s^2), c_s^2 = 1 / (D + 1), for the Hermite form (Sec. II), whose
+// collision is the corrected one at that speed on a Cartesian box.
+double lattice_c2(const lbw_geometry_desc& d);
 int device_cus(int* cus);
 
 }  // namespace lbw

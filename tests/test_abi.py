@@ -117,3 +117,18 @@ def test_source_calls_reject_null():
     assert L.lbw_amplitude(None, 0, 1, None) == -1
     assert L.lbw_batch_set_sources(None, None, None, None, None, None, 0) == -1
     assert L.lbw_batch_amplitude(None, 0, 1, None) == -1
+
+
+def test_hermite_equilibrium_checked_on_host():
+    cyl = dict(W.closed_cylinder(scale=16), equilibrium="hermite")
+    rc, err, h = _rc(cyl)
+    assert rc == -1 and "Cartesian boxes only" in err and not h.value
+    box = dict(kind="box", dim=3, n=(4, 4, 4), qmin=(0.0, 0.0, 0.0), qmax=(4.0, 4.0, 4.0),
+               bc_lo=("bounceback",) * 3, bc_hi=("bounceback",) * 3, h_ref=1.0, c=0.5, damp=1.0, params=())
+    d = lbw.to_desc(box)
+    d.equilibrium = 2
+    hh = ctypes.c_void_p()
+    rc = lbw.lib().lbw_make_geometry(ctypes.byref(d), None, ctypes.byref(hh))
+    assert rc == -1 and "unknown equilibrium" in lbw.lib().lbw_last_error().decode() and not hh.value
+    with pytest.raises(ValueError):
+        lbw.to_desc(dict(box, equilibrium="lattice"))
