@@ -90,7 +90,8 @@ typedef struct {
     double qmin[3];    /* coordinate range; periodic axis nodes at qmin + i h, */
     double qmax[3];    /* walled axis nodes at qmin + (i + 1/2) h, h = (qmax - qmin) / n */
     double h_ref;      /* physical length of one lattice unit (> 0) */
-    double c;          /* lattice wave speed c = c_phys dt / h_ref (c_s = c) */
+    double c;          /* lattice wave speed c = c_phys dt / h_ref (c_s = c; for
+                          LBW_EQ_HERMITE the c of its formula, see above) */
     double damping;    /* bounce-back damping factor D in [0, 1] */
     double params[4];  /* kind-specific, see above */
 } lbw_geometry_desc;
