@@ -55,3 +55,26 @@ def test_resonance_series():
         plane = [w for w in plane if 0 < w <= wmax]
         for w in plane:
             assert min(abs(r - w) for r in res) <= 1e-15
+
+
+def test_sweep_source_and_probe_nodes():
+    """Node lists of the sweeps land where their docstrings say (CPU)."""
+    import workloads as W
+    pipe = W.driven_pipe("fixed")
+    n0, n1, n2 = pipe["n"]
+    ring, plate, probes = W.pipe_ring(pipe), W.pipe_plate(pipe), W.pipe_probes(pipe)
+    assert np.array_equal(ring % n0, np.zeros(n1)) and np.all(ring // (n0 * n1) == 0)   # r_min, z = 0
+    assert np.array_equal(np.sort(plate), np.arange(n0 * n1))                         # the whole z = 0 plane
+    assert np.array_equal(probes // (n0 * n1), [10, 50]) and np.all(probes % n0 == 1)
+    tor = W.driven_torus()
+    t0, t1, t2 = tor["n"]
+    src = W.torus_sources(tor)
+    assert src["inner"].size == t1 * t2 and np.all(src["inner"] % t0 == 0)
+    small = src["small_ring"]
+    assert small.size == t2 and np.all(small % (t0 * t1) == 0)                        # rho_min, theta = 0
+    tp = W.torus_probes(tor)
+    assert tp[0] % t0 == t0 - 1 and (tp[0] // t0) % t1 == t1 // 2 and tp[0] // (t0 * t1) == 0
+    w = W.torus_omegas()
+    assert w.size == 499 and abs(w[1] - w[0] - 0.001) < 1e-12
+    geom, pt, om = W.point_source_box()
+    assert pt == [50 + 100 * 50] and abs(om - 2 * math.pi * 0.5 / 10) < 1e-15
