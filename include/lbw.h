@@ -312,11 +312,16 @@ int lbw_batch_layout(lbw_batch_t b, int64_t* node_offsets, int64_t* probe_offset
  * ceil(n0/tile_x) tile_x * ceil(n1/tile_y) tile_y * n2, ties to the wider
  * tile; two waves of resident workgroups) or whole rows (lanes: workgroup
  * size * ceil(n1/r) * n2, ties to TX-wide tiles; one wave of resident
- * workgroups).  lbw_batch_autotune is switched off in this version and
- * returns LBW_ESTATE without launching anything; set shapes with
- * lbw_batch_set_step_config. */
+ * workgroups).  lbw_batch_autotune times the candidates instead. */
 int lbw_batch_set_step_config(lbw_batch_t b, int tile_x, int chunk_z, int blocks);
 int lbw_batch_get_step_config(lbw_batch_t b, int* tile_x, int* chunk_z, int* blocks);
+/* Times every launch shape (whole-row tiles when the batch allows them,
+ * tile_x 16, 32 and 64; chunk_z 4 to 64; one or two waves of resident
+ * workgroups) with reps steps each on scratch buffers, recording no probes
+ * and leaving populations, step count and trace untouched, and keeps the
+ * fastest; best_us (may be NULL) receives its microseconds per step.
+ * Synchronises.  Errors: LBW_EINVAL (NULL batch, reps < 1), LBW_ENOMEM,
+ * LBW_EDEVICE (the previous shape is kept). */
 int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us);
 int lbw_batch_set_graph_block(lbw_batch_t b, int steps);
 

@@ -404,10 +404,9 @@ int lbw_batch_step_n(lbw_batch_t b, int64_t n) {
 int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us) {
     if (!b) return fail(LBW_EINVAL, "batch is NULL");
     if (reps < 1) return fail(LBW_EINVAL, "reps must be >= 1");
-    // Disabled: this path once read uninitialised step counters (fixed
-    // above and in the kernel's probe check) and awaits a GPU check of that
-    // fix; lbw_batch_set_step_config remains available.
-    if (b) return fail(LBW_ESTATE, "lbw_batch_autotune is disabled pending a GPU check; use lbw_batch_set_step_config");
+    // Timing launches record nothing: their probe arguments carry t_max = 0
+    // and the batch's own scratch step counters (zeroed when the batch is
+    // made), so no launch can store into the trace whatever a counter holds.
     int cus = 0;
     int rc = lbw::device_cus(&cus);
     if (rc) return rc;
@@ -421,9 +420,11 @@ int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us) {
     int best_tx = keep_tx, best_lz = keep_lz, best_blocks = keep_blocks;
     float best_ms = 1e30f;
     float* other = b->f[1 - b->cur];
-    for (int tx : {16, 32, 64}) {
+    const int row_nt = section_threads(b);
+    for (int tx : {0, 16, 32, 64}) {  // 0: whole-row tiles, when every geometry's rows fit them
         if (err != hipSuccess) break;
-        const int bpc = lbw::batch_blocks_per_cu(tx);
+        if (tx == 0 && row_nt == 0) continue;
+        const int bpc = tx == 0 ? lbw::batch_section_blocks_per_cu(row_nt) : lbw::batch_blocks_per_cu(tx);
         for (int lz : {4, 8, 16, 32, 64}) {
             for (int mult : {1, 2}) {
                 if (set_config(b, tx, lz, mult * cus * bpc) != LBW_OK) {

@@ -47,14 +47,16 @@ def physical(freq_steps: np.ndarray, geoms) -> np.ndarray:
     return freq_steps * scale[:, None]
 
 
-def run_batch(members, p0s, steps: int, k: int, chunk: int = 2000, tune: bool = False, log=None, keep_trace=False):
-    """Advances all members together; returns (physical frequencies [n, k],
-    seconds of stepping, seconds of mode extraction)."""
+def run_batch(members, p0s, steps: int, k: int, chunk: int = 2000, tune: bool = True, log=None, keep_trace=False):
+    """Advances all members together (after timing the batch's launch shapes
+    on scratch buffers when tune is set: results are the same for every
+    shape); returns (physical frequencies [n, k], seconds of stepping,
+    seconds of mode extraction)."""
     import torch
     geoms = [m["geom"] for m in members]
     b = Batch(geoms, p0s, [m["probes"] for m in members], t_max=steps)
     if tune:
-        b.autotune(reps=3)
+        b.autotune(reps=10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0

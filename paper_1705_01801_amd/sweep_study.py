@@ -121,6 +121,7 @@ def run(points: int = 119, steps: int = W.PIPE_STEPS, plain: int = 4, ends=("fix
             om.append(np.full(sn.size, w))
             axis.append(np.full(sn.size, ax))
     b.set_sources(np.concatenate(nodes), np.concatenate(which), 1.0, np.concatenate(om), np.concatenate(axis))
+    b.autotune(reps=10)                          # launch shape only: results are the same for every shape
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(T)
@@ -199,6 +200,7 @@ def run_torus(points: int = 499, steps: int = W.TORUS_STEPS, modes: int = 400, p
     b = Batch([geom] * len(omegas), [np.zeros(N)] * len(omegas), [probes] * len(omegas), t_max=T)
     b.set_sources(np.concatenate([ring] * len(omegas)), np.repeat(np.arange(len(omegas)), ring.size), 1.0,
                   np.repeat(omegas, ring.size))
+    b.autotune(reps=5)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(T)

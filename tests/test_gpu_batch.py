@@ -78,9 +78,6 @@ def test_batch_member_matches_oracle():
         assert np.abs(b.probe()[:, cols] - tr).max() <= 1e-5 * np.abs(tr).max()
 
 
-@pytest.mark.skip(reason="batch autotuning faulted the GPU twice (uninitialised step counters read as a trace "
-                         "row); the counters are now zeroed and the row check requires t >= 0, but the path stays "
-                         "disabled until that fix has been checked on a GPU")
 def test_batch_launch_shapes_autotune_graphs_identical():
     geoms, P0s, probes = members()
     ref = None
