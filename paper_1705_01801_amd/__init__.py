@@ -392,6 +392,9 @@ class Batch:
         return a.value, b.value, c.value
 
     def autotune(self, reps: int = 10) -> float:
+        """Times the batch's launch shapes on scratch buffers (state, step
+        count and trace unchanged) and keeps the fastest; returns
+        microseconds per step."""
         us = ctypes.c_double()
         check(lib().lbw_batch_autotune(self.handle, int(reps), ctypes.byref(us)))
         return us.value
