@@ -206,6 +206,31 @@ def test_whole_section_tiles_match_wide_tiles():
         assert np.array_equal(tr, out[0][1])
 
 
+def test_batch_autotune_with_sources_changes_nothing():
+    """Tuning a driven batch (as the sweeps do) imposes no source and records
+    no probe: populations, step count and trace stay as they were, and the
+    run continues bit for bit as an untuned one."""
+    geom, src, probes = cyl()
+    N = W.num_nodes(geom)
+    out = []
+    for tune in (False, True):
+        b = lbw.Batch([geom] * 3, [np.zeros(N)] * 3, [probes] * 3, t_max=120)
+        b.set_sources(np.concatenate([src] * 3), np.repeat(np.arange(3), len(src)), 0.5, [0.03] * len(src) * 3)
+        b.step(20)
+        if tune:
+            before = [b.populations(h).cpu().numpy().copy() for h in range(3)]
+            tr = b.probe().copy()
+            assert b.autotune(reps=2) > 0 and b.t == 20
+            for h in range(3):
+                assert np.array_equal(b.populations(h).cpu().numpy(), before[h])
+            assert np.array_equal(b.probe(), tr)
+        b.step(100)
+        out.append(([b.populations(h).cpu().numpy() for h in range(3)], b.probe()))
+    for h in range(3):
+        assert np.array_equal(out[0][0][h], out[1][0][h])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_source_errors():
     geom, src, probes = cyl()
     N = W.num_nodes(geom)
