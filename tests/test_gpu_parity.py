@@ -195,14 +195,20 @@ def test_polar_disk_modes_full_run():
     assert np.abs(pgpu[ok] / po2[ok] - 1.0).max() <= 1e-8
 
 
-@pytest.mark.parametrize("idx", [1, 2, 3])
-def test_full_size_one_step(idx):
-    """Full-size grids in the benchmark's launch configuration: after 20 GPU
-    steps, one oracle step on the GPU state must match the GPU's next step."""
+# the launch shapes the benchmark's tuner picks on these grids (profiles):
+# 64 x 8 tiles on the cylinder, whole-row 128 x 8 on the horn, 96 x 8 on the torus
+@pytest.mark.parametrize("idx,shape", [(1, (64, 8, 32, 256)), (2, (128, 8, 32, 256)), (3, (96, 8, 64, 256)),
+                                       (2, None), (3, None)])
+def test_full_size_one_step(idx, shape):
+    """Full-size grids in the benchmark's launch configuration (and the
+    default one): after 20 GPU steps, one oracle step on the GPU state must
+    match the GPU's next step."""
     w = W.workload(idx)
     geom, P0 = w["geom"], w["P0"]
-    say("full size one step", w["name"], geom["n"])
+    say("full size one step", w["name"], geom["n"], shape)
     g = lbw.Geometry(geom)
+    if shape:
+        g.set_step_config(*shape)
     sim = lbw.Simulation(g, P0, w["probes"], t_max=64)
     sim.step(20)
     f = sim.populations().double().cpu().numpy()
