@@ -142,3 +142,23 @@ def test_general_rejections():
         sim.autotune(reps=2)
     with pytest.raises(lbw.LbwError):
         lbw.Batch([geom], [np.zeros(N)], [[0]], t_max=4)
+
+
+def test_general_full_size_one_step():
+    """The 128^3 duct in the benchmark's launch configuration (the default
+    64 x 8 tiles, 16 planes per chunk): after 10 GPU steps, one oracle step
+    on the GPU state must match the GPU's next step."""
+    w = W.general_workload()
+    geom, P0 = w["geom"], w["P0"]
+    say("general full size one step", geom["n"])
+    g = lbw.Geometry(geom)
+    assert g.step_config()[:3] == (64, 8, 16)
+    sim = lbw.Simulation(g, P0, w["probes"], t_max=32)
+    sim.step(10)
+    f = sim.populations().double().cpu().numpy()
+    sim.step(1)
+    fg = sim.populations().double().cpu().numpy()
+    o = oracle.Oracle(geom)
+    o.step(f, 1)
+    assert np.abs(fg - f).max() <= 2e-6 * np.abs(f).max()
+    assert rel_l2(fg, f) <= 1e-6
