@@ -57,27 +57,38 @@ def build(force: bool = False) -> str:
 _lib = None
 
 
+def load_library(path: str):
+    """Loads a compiled copy of the oracle (the default build, or a copy
+    a test compiled from an edited source to plant a mistake) and declares
+    its entry points."""
+    lib = ctypes.CDLL(path)
+    _declare(lib)
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
-        dp = ctypes.POINTER(ctypes.c_double)
-        gp = ctypes.POINTER(_Geom)
-        lib.orc_coeffs.argtypes = [gp, dp, dp, dp]
-        lib.orc_coeffs_given.argtypes = [gp, dp, dp, dp, dp]
-        lib.orc_maps.argtypes = [gp, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)]
-        lib.orc_init.argtypes = [gp, dp, dp, dp]
-        lib.orc_step.argtypes = [gp, dp, dp, dp, dp, dp]
-        lib.orc_run.argtypes = [gp, dp, dp, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
-                                ctypes.c_int, dp]
-        lib.orc_run_driven.argtypes = [gp, dp, dp, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
-                                       ctypes.c_int, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
-                                       ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]
-        lib.orc_invariant.argtypes = [gp, dp]
-        lib.orc_invariant.restype = ctypes.c_double
-        lib.orc_pressure.argtypes = [gp, dp, dp, dp]
-        _lib = lib
+        _lib = load_library(build())
     return _lib
+
+
+def _declare(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    gp = ctypes.POINTER(_Geom)
+    lib.orc_coeffs.argtypes = [gp, dp, dp, dp]
+    lib.orc_coeffs_given.argtypes = [gp, dp, dp, dp, dp]
+    lib.orc_maps.argtypes = [gp, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32)]
+    lib.orc_init.argtypes = [gp, dp, dp, dp]
+    lib.orc_step.argtypes = [gp, dp, dp, dp, dp, dp]
+    lib.orc_run.argtypes = [gp, dp, dp, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                            ctypes.c_int, dp]
+    lib.orc_run_driven.argtypes = [gp, dp, dp, dp, dp, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.c_int, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.orc_invariant.argtypes = [gp, dp]
+    lib.orc_invariant.restype = ctypes.c_double
+    lib.orc_pressure.argtypes = [gp, dp, dp, dp]
 
 
 def _ptr(a, ctype=ctypes.c_double):
@@ -118,14 +129,14 @@ class Oracle:
     Arrays follow the layout f[l, n] with n = i0 + n0 * (i1 + n1 * i2).
     """
 
-    def __init__(self, geom: dict):
+    def __init__(self, geom: dict, lib=None):
         self.geom = dict(geom)
         self._g = _to_struct(geom)
         self.dim = self._g.dim
         self.Q = 2 * self.dim + 1
         self.shape = tuple(int(self._g.n[a]) for a in range(self.dim))
         self.N = int(np.prod(self.shape))
-        self.lib = _load()
+        self.lib = _load() if lib is None else lib
         self.sqrtg = np.zeros(self.N)
         self.Mhat = np.zeros((6, self.N))
         self.Gamh = np.zeros((3, self.N))
