@@ -19,8 +19,8 @@
  *    pointers are ordinary host memory.  The library owns only the opaque
  *    geometry/state objects and the small tables and scratch inside them.
  *  - stream arguments are hipStream_t passed as void* (NULL = the null
- *    stream).  All device work is queued on that stream; only lbw_probe,
- *    lbw_modes, lbw_geometry_export and lbw_stability_bound wait for it.
+ *    stream).  All device work is queued on that stream; the calls that
+ *    wait for it say so below ("Synchronises", "Waits for the stream").
  *  - populations are stored structure-of-arrays, f[l * N + n] with node
  *    n = i0 + n0 * (i1 + n1 * i2) and l in the order
  *    0: rest, 1: +e0, 2: -e0, 3: +e1, 4: -e1, 5: +e2, 6: -e2 (Q = 2*dim + 1).
@@ -197,8 +197,9 @@ int lbw_step_n(lbw_state_t s, int64_t n);
 
 /* Picks the fastest launch shape of the 3-D step kernel for this state's
  * geometry by timing candidates (tile_x 16/32/64 with workgroups of 256 and
- * 512 threads, chunk_z 4..64, one and two
- * waves of resident workgroups) for reps launches each with HIP events.  The
+ * 512 threads, and the whole-row tiles 96 x 4, 96 x 8, 128 x 4 and 128 x 8;
+ * chunk_z 4, 8, 16, 32, 64 (up to twice n2); one and two waves of resident
+ * workgroups) for reps launches each with HIP events.  The
  * candidates run real ping-pong steps (each launch reads what the previous
  * one wrote) from the state's current buffer into its other buffer and a
  * temporary buffer of Q*N floats (allocated for the call), with
@@ -223,11 +224,16 @@ int lbw_probe(lbw_state_t s, double* host_dst, int64_t t0, int64_t t1);
 /* Resonant frequencies of the recorded probe traces, computed on the device
  * in FP64: per probe subtract the mean, apply the symmetric Hann window
  * 1/2 - 1/2 cos(2 pi t/(T-1)), zero-pad to 4 x the next power of two of T,
- * FFT, sum |X_k|^2 over probes; peaks are bins k in [2, nfft/2 - 1] with
- * P[k-1] < P[k] >= P[k+1] and P[k] > 1e-3 max_{k>=2} P, refined by a parabola
- * through ln P; the k lowest, ascending, in cycles per step (NaN-padded).
- * power_out may be NULL.  Synchronises.  Errors: LBW_EINVAL (k < 1, fewer
- * than 8 recorded rows, no probes), LBW_EUNSTABLE (non-finite trace). */
+ * FFT, sum |X_k|^2 over probes; peaks are bins k in [16, nfft/2 - 1] with
+ * P[k-1] < P[k] >= P[k+1] and P[k] > 1e-3 max_{k>=16} P (bin 16 is the first
+ * outside the window's DC main lobe), refined by a parabola through ln P
+ * (no refinement when a neighbour bin is 0); the k lowest, ascending, in
+ * cycles per step (NaN-padded).  A trace holding a non-finite value gives
+ * no peaks (all NaN).  power_out may be NULL.  The FFT work space (32 nfft
+ * bytes per probe, up to 1 GiB per pass) is allocated on first use and kept
+ * with the state.  Synchronises.  Errors: LBW_EINVAL (k < 1, fewer than 8
+ * recorded rows, no probes, more probes than one 1 GiB pass holds),
+ * LBW_ENOMEM, LBW_EDEVICE. */
 int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out);
 
 /* Current step count and the device buffer holding the current populations. */
