@@ -1,12 +1,17 @@
 """Benchmark: fused collide-and-stream step of the curvilinear wave LBM on
-one MI355X, on the 3-D closed cylinder (D3Q7, 128 x 128 x 256 nodes, FP32
-populations, 16 probes recorded every step).
+one MI355X.  The headline is the largest single-GPU configuration, the
+torus (D3Q7, 96 x 256 x 512 = 12.6 M nodes, FP32 populations, 64 probes
+recorded every step); the closed cylinder (128 x 128 x 256, whose 235 MB
+working set fits the 256 MB Infinity Cache) and the horn (128 x 128 x 512)
+are timed as extra legs.
 
 Prints one JSON line.  value = whole-job MLUPS (node updates per second / 1e6)
-with the state resident in HBM; roofline = algorithmic bytes per launch
-(56 B per node: 7 float populations read and written) over the measured
-average launch duration, against 8 TB/s; cpu_baseline = the FP64 oracle on
-the host for a bounded number of steps of the same grid.
+with the state resident in device memory; roofline = algorithmic bytes per
+launch (56 B per node: 7 float populations read and written) over the
+measured average launch duration, against 8 TB/s; surrogate = shape-spectra
+per second of the plain per-shape LBM, the batched LBM and the trained
+surrogate with every fallback candidate simulated; cpu_baseline = the FP64
+oracle on the host for a bounded number of steps of the headline grid.
 """
 import argparse
 import hashlib
@@ -75,31 +80,91 @@ def cpu_baseline(w, steps):
                       % (steps, w["name"], dt, os.cpu_count() or 0)}
 
 
-def spectra_leg(n_horns, n_plain=4):
-    """Shape-spectra per second of the batched LBM (n_horns ensemble horns in
-    one launch per step) and of the per-shape LBM (the first n_plain of them,
-    one after another), 30000 steps and 10 modes each."""
-    import numpy as np
+# working sets below the 256 MB Infinity Cache are served from it, not HBM
+INFINITY_CACHE_BYTES = 256 * 2 ** 20
 
+
+def time_config(config, steps, warmup, launch="auto"):
+    """Runs one configuration's full step (probes recorded) after tuning the
+    launch shape, timed with HIP events on the stream the library launches
+    on; returns the numbers the JSON line reports."""
+    import torch
+
+    import paper_1705_01801_amd as lbw
     import workloads as W
-    from paper_1705_01801_amd import surrogate as S
-    members = S.with_wave_speeds(W.ensemble(n_horns, stream=2))
-    p0s = [W.horn_pulse(m["geom"]) for m in members]
-    steps, k = W.ENSEMBLE_STEPS, W.ENSEMBLE_MODES
-    log("bench: spectra leg, %d horns batched, %d per shape" % (n_horns, n_plain))
-    f_b, t_step, t_modes = S.run_batch(members, p0s, steps, k)
-    f_p, t_plain = S.run_plain(members[:n_plain], p0s[:n_plain], steps, k)
-    same = np.isfinite(f_p) & np.isfinite(f_b[:n_plain])
-    nodes = int(sum(np.prod(m["geom"]["n"]) for m in members))
-    batched = n_horns / (t_step + t_modes)
-    plain = n_plain / t_plain
-    return {"unit": "spectra/s", "batched": round(batched, 3), "plain": round(plain, 3),
-            "batched_vs_plain": round(batched / plain, 2), "horns": n_horns, "plain_horns": n_plain,
-            "nodes": nodes, "steps": steps, "modes": k,
-            "max_rel_diff_plain_vs_batched": float(np.max(np.abs(f_p[same] / f_b[:n_plain][same] - 1.0)))
-            if same.any() else None,
-            "note": "surrogate + LBM fallback rate comes from the surrogate study (python -m "
-                    "paper_1705_01801_amd.surrogate_study), which trains the surrogate first"}
+
+    w = W.general_workload() if config == 4 else W.workload(config)
+    geom = w["geom"]
+    N = W.num_nodes(geom)
+    g = lbw.Geometry(geom)
+    sim = lbw.Simulation(g, w["P0"], w["probes"], t_max=warmup + steps)
+    general = config == 4          # per-node kernel: no launch shapes to tune
+    if general:
+        tuned_us = float("nan")
+    elif launch == "auto":
+        tuned_us = sim.autotune(reps=20)
+    else:
+        g.set_step_config(*(int(v) for v in launch.split(",")))
+        tuned_us = float("nan")
+    tile = g.step_config()
+    log("bench: %s, %d nodes, warmup %d, steps %d, launch shape %s (tuner %.2f us)" % (w["name"], N, warmup,
+                                                                                   steps, tile, tuned_us))
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sim.probe(0, min(sim.t, sim.t_max))  # raises on a non-finite trace
+    ms_per_step = ms / steps
+    # algorithmic bytes per node update: 7 populations read and written, plus
+    # 9 float coefficients read per node for a geometry given by its metric
+    bpn = 92.0 if general else 56.0
+    achieved = bpn * N / (ms_per_step / 1e3) / 1e9
+    working_set = (2 * 28 + (36 if general else 0)) * N
+    out = {"workload": w["name"], "nodes": N, "ms_per_step": round(ms_per_step, 5),
+           "mlups": round(N * steps / (ms / 1e3) / 1e6, 1), "achieved_gbs": round(achieved, 1),
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(config),
+           "residency": "infinity-cache" if working_set <= INFINITY_CACHE_BYTES else "hbm",
+           "working_set_bytes": working_set, "probes": int(len(w["probes"])), "c": geom["c"],
+           "launch": {"tile_x": tile[0], "tile_y": tile[1], "chunk_z": tile[2], "blocks": tile[3],
+                      "graph_block": 32}}
+    sim.close()
+    g.close()
+    return out, w
+
+
+def copy_ceiling(N):
+    """A device-to-device copy moving the same 56 B per node (torch copy_)."""
+    import torch
+    src = torch.empty(7 * N, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(50):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    return 56.0 * N / (c0.elapsed_time(c1) / 50 / 1e3) / 1e9
+
+
+def surrogate_leg(candidates, train):
+    """Shape-spectra per second on the same GPU: plain per-shape LBM (the
+    first training horns one after another), batched LBM (the training
+    ensemble in one launch per step), and surrogate + fallback on
+    `candidates` candidate profiles with the whole fallback set simulated
+    (batched) and timed; 30000 steps and 10 modes per spectrum."""
+    from paper_1705_01801_amd import surrogate_study
+    log("bench: surrogate leg, %d training horns, %d candidates" % (train, candidates))
+    return surrogate_study.measured_rate(train=train, candidates=candidates, log=log)
 
 
 def sweep_leg(points):
@@ -123,90 +188,53 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="auto",
                     help="'auto' (autotune) or TILE_X,TILE_Y,CHUNK_Z,BLOCKS to fix the step kernel's launch shape")
-    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 3, 4),
-                    help="3-D workload to time: 1 cylinder 128x128x256 (the benchmark), 2 horn 128x128x512, "
-                         "3 torus 96x256x512, 4 duct 128x128x128 given by its metric (per-node kernel)")
-    ap.add_argument("--spectra-horns", type=int, default=64,
-                    help="horns in the batched-vs-plain spectra leg (0 skips it)")
+    ap.add_argument("--config", type=int, default=3, choices=(1, 2, 3, 4),
+                    help="3-D workload of the headline: 3 torus 96x256x512 (the largest single-GPU one), "
+                         "1 cylinder 128x128x256, 2 horn 128x128x512, 4 duct 128x128x128 given by its metric")
+    ap.add_argument("--legs", default="1,2",
+                    help="other configurations timed as extra legs (comma list, empty for none)")
+    ap.add_argument("--leg-steps", type=int, default=500)
+    ap.add_argument("--candidates", type=int, default=10000,
+                    help="candidate horn profiles of the surrogate leg (0 skips it)")
+    ap.add_argument("--train-horns", type=int, default=512)
     ap.add_argument("--sweep-points", type=int, default=119,
                     help="drive frequencies in the driven-pipe sweep leg (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU; the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (the slab decomposition that "
+              "would shard a grid is described in the design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
 
-    import paper_1705_01801_amd as lbw
-    import workloads as W
-
     torch.cuda.set_device(0)
-    w = W.general_workload() if args.config == 4 else W.workload(args.config)
-    geom = w["geom"]
-    N = W.num_nodes(geom)
-    g = lbw.Geometry(geom)
-    sim = lbw.Simulation(g, w["P0"], w["probes"], t_max=args.warmup + args.steps)
-    general = args.config == 4          # per-node kernel: no launch shapes to tune
-    if general:
-        tuned_us = float("nan")
-    elif args.launch == "auto":
-        tuned_us = sim.autotune(reps=20)
-    else:
-        sim.geometry.set_step_config(*(int(v) for v in args.launch.split(",")))
-        tuned_us = float("nan")
-    tile = g.step_config()  # the general kernel: its default shape, one workgroup per tile
-    log("bench: %s, %d nodes, warmup %d, steps %d, launch shape %s (tuner %.2f us)" % (w["name"], N, args.warmup,
-                                                                                   args.steps, tile, tuned_us))
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    sim.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    sim.probe(0, min(sim.t, sim.t_max))  # raises on a non-finite trace
-    ms_per_step = ms / args.steps
-    mlups = N * args.steps / (ms / 1e3) / 1e6
-    # algorithmic bytes per node update: 7 populations read and written, plus
-    # 9 float coefficients read per node for a geometry given by its metric
-    bytes_per_launch = (92.0 if general else 56.0) * N
-    achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
-    traffic = read_traffic(args.config)
-    # practical ceiling: a device-to-device copy moving the same bytes
-    src = torch.empty(7 * N, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    for _ in range(5):
-        dst.copy_(src)
-    c0 = torch.cuda.Event(enable_timing=True)
-    c1 = torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
-    for _ in range(50):
-        dst.copy_(src)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 56.0 * N / (c0.elapsed_time(c1) / 50 / 1e3) / 1e9
-    del src, dst
+    head, w = time_config(args.config, args.steps, args.warmup, args.launch)
+    N = head["nodes"]
+    copy_gbs = copy_ceiling(N)
     out = {
-        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": head["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w["name"], "nodes": N, "lattice": "D3Q7", "probes": int(len(w["probes"])),
-                   "c": geom["c"], "launch": {"tile_x": tile[0], "tile_y": tile[1], "chunk_z": tile[2],
-                                              "blocks": tile[3], "graph_block": 32}},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "config": {"workload": head["workload"], "nodes": N, "lattice": "D3Q7", "probes": head["probes"],
+                   "c": head["c"], "launch": head["launch"], "residency": head["residency"]},
+        "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["frac"], "traffic": head["traffic"]},
         "copy_ceiling": {"achieved": round(copy_gbs, 1), "unit": "GB/s",
                          "note": "device copy of the same 56 B/node, torch copy_"},
     }
-    if args.spectra_horns > 0:
-        out["spectra"] = spectra_leg(args.spectra_horns)
+    legs = [int(v) for v in args.legs.split(",") if v.strip() and int(v) != args.config]
+    if legs:
+        out["legs"] = {}
+        for c in legs:
+            leg, _ = time_config(c, args.leg_steps, max(args.leg_steps // 10, 10), args.launch)
+            out["legs"][leg["workload"]] = {k: leg[k] for k in ("mlups", "ms_per_step", "achieved_gbs", "frac",
+                                                                  "residency", "traffic", "launch")}
+    if args.candidates > 0:
+        out["surrogate"] = surrogate_leg(args.candidates, args.train_horns)
     if args.sweep_points > 0:
         out["sweep"] = sweep_leg(args.sweep_points)
     if not args.no_cpu_baseline:

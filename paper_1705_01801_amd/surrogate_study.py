@@ -24,6 +24,74 @@ import time
 import numpy as np
 
 
+def measured_rate(train: int = 512, candidates: int = 10000, plain: int = 4, judge: int = 64,
+                  threshold: float = 0.01, train_steps: int = 10000, log=None) -> dict:
+    """Measured shape-spectra rates on one GPU, every spectrum produced by the
+    library: the batched LBM on the training ensemble, the per-shape LBM on
+    its first horns, and surrogate + fallback on the first `candidates`
+    candidate profiles, where the whole fallback set is simulated (batched)
+    and timed, not projected.  A sample of accepted candidates is simulated
+    too, as the judge of the surrogate's error."""
+    import torch
+
+    import workloads as W
+    from paper_1705_01801_amd import surrogate as S
+
+    steps, K = W.ENSEMBLE_STEPS, W.ENSEMBLE_MODES
+    members = S.with_wave_speeds(W.ensemble(train, stream=0))
+    p0s = [W.horn_pulse(m["geom"]) for m in members]
+    f_train, t_step, t_modes = S.run_batch(members, p0s, steps, K)
+    batched = len(members) / (t_step + t_modes)
+    f_plain, t_plain = S.run_plain(members[:plain], p0s[:plain], steps, K)
+    same = np.isfinite(f_plain) & np.isfinite(f_train[:plain])
+    prof = np.array([m["profile"] for m in members])
+    sur = S.Surrogate([W.HORN_RANGES[k] for k in ("a", "b", "k")], members=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sur.fit(prof, f_train, steps=train_steps)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    cprof, cgrid = W.candidates(candidates)
+
+    def simulate(idx):
+        ms = S.with_wave_speeds([W.horn_member(cprof[i], cgrid[i]) for i in idx])
+        ps = [W.horn_pulse(m["geom"]) for m in ms]
+        f, ts, tm = S.run_batch(ms, ps, steps, K)
+        return f, ts + tm
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mean, spread, _ = sur.predict(cprof)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    fallback = np.flatnonzero(spread > threshold)
+    t_fb = 0.0
+    if len(fallback):
+        if log:
+            log("surrogate leg: %d of %d candidates fall back to the LBM" % (len(fallback), candidates))
+        _, t_fb = simulate(fallback)
+    rate = candidates / (t_inf + t_fb)
+    acc = np.flatnonzero(spread <= threshold)
+    out = {"unit": "spectra/s", "plain": round(plain / t_plain, 3), "batched": round(batched, 3),
+           "surrogate_plus_fallback": round(rate, 2), "surrogate_vs_plain": round(rate * t_plain / plain, 1),
+           "batched_vs_plain": round(batched * t_plain / plain, 2), "candidates": candidates,
+           "fallback": int(len(fallback)), "inference_s": round(t_inf, 4), "fallback_lbm_s": round(t_fb, 2),
+           "training_horns": len(members), "training_lbm_s": round(t_step + t_modes, 2),
+           "training_s": round(t_train, 2),
+           "end_to_end_with_training": round(candidates / (t_step + t_modes + t_train + t_inf + t_fb), 2),
+           "plain_horns": plain, "steps": steps, "modes": K,
+           "max_rel_diff_plain_vs_batched": float(np.max(np.abs(f_plain[same] / f_train[:plain][same] - 1.0)))
+           if same.any() else None}
+    if judge and len(acc):
+        jidx = np.random.default_rng(7).choice(acc, size=min(judge, len(acc)), replace=False)
+        f_judge, _ = simulate(jidx)
+        ok = np.isfinite(f_judge) & np.isfinite(mean[jidx])
+        err = np.abs(mean[jidx][ok] / f_judge[ok] - 1.0)
+        out["judge"] = {"accepted_sampled": len(jidx), "modes": int(ok.sum()),
+                        "rel_err_median": float(np.median(err)), "rel_err_max": float(err.max())}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=512)
