@@ -236,6 +236,24 @@ int lbw_probe(lbw_state_t s, double* host_dst, int64_t t0, int64_t t1);
  * LBW_ENOMEM, LBW_EDEVICE. */
 int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out);
 
+/* lbw_modes for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same rule and bit-identical results, but the FFT work space is a fixed
+ * 32 MiB array of device memory that the library holds on each GPU it runs
+ * on until the process ends (probe columns are transformed a few at a time
+ * through it), the results go to device memory and nothing is waited for.
+ *  freq_dev, power_dev  device, k doubles each (ascending frequencies in
+ *                       cycles per step, NaN-padded; their spectral powers),
+ *                       ready once the state's stream reaches this call
+ * Calls no allocator.  All calls on one GPU share that array: calls whose
+ * work overlaps in time on one GPU (other streams, other threads) race and
+ * must be ordered by the caller; the array is fully rewritten by each call,
+ * so nothing carries over from the previous one.  Errors: LBW_EINVAL (NULL
+ * arguments, k < 1, no probes, fewer than 8 or more than
+ * LBW_MODES_NOALLOC_MAX_ROWS recorded rows), LBW_EDEVICE. */
+#define LBW_MODES_NOALLOC_MAX_ROWS 131072
+int lbw_modes_noalloc(lbw_state_t s, int k, double* freq_dev, double* power_dev);
+
 /* Current step count and the device buffer holding the current populations. */
 int lbw_state_info(lbw_state_t s, int64_t* t, float** f_current);
 

@@ -25,7 +25,8 @@ TABLE_PLANES = ("Mhat00", "Mhat11", "Mhat22", "Mhat02", "Gamh0", "Gamh1", "Gamh2
 # every symbol include/lbw.h declares
 SYMBOLS = ("lbw_make_geometry", "lbw_make_geometry_general", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound",
            "lbw_set_step_config", "lbw_get_step_config", "lbw_init",
-           "lbw_step_n", "lbw_autotune", "lbw_set_graph_block", "lbw_probe", "lbw_modes", "lbw_state_info",
+           "lbw_step_n", "lbw_autotune", "lbw_set_graph_block", "lbw_probe", "lbw_modes", "lbw_modes_noalloc",
+           "lbw_state_info",
            "lbw_pressure", "lbw_free_state", "lbw_set_sources", "lbw_amplitude", "lbw_batch_make", "lbw_batch_layout", "lbw_batch_set_step_config",
            "lbw_batch_get_step_config", "lbw_batch_autotune", "lbw_batch_set_graph_block", "lbw_batch_step_n",
            "lbw_batch_info", "lbw_batch_probe", "lbw_batch_modes", "lbw_batch_set_sources",
@@ -103,6 +104,7 @@ def lib():
         L.lbw_set_graph_block.argtypes = [vp, i32]
         L.lbw_probe.argtypes = [vp, vp, i64, i64]
         L.lbw_modes.argtypes = [vp, i32, vp, vp]
+        L.lbw_modes_noalloc.argtypes = [vp, i32, vp, vp]
         L.lbw_state_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(vp)]
         L.lbw_pressure.argtypes = [vp, vp]
         L.lbw_free_state.argtypes = [vp]
@@ -306,6 +308,11 @@ class Simulation:
         power = np.zeros(k)
         check(lib().lbw_modes(self.handle, int(k), freq.ctypes.data, power.ctypes.data))
         return freq, power
+
+    def modes_noalloc(self, k: int, freq, power):
+        """lbw_modes into caller-owned device tensors (k float64 each) through
+        the library's fixed work space; queued, not waited for."""
+        check(lib().lbw_modes_noalloc(self.handle, int(k), freq.data_ptr(), power.data_ptr()))
 
     def set_sources(self, nodes, amplitude: float, omega: float, flux_axis=None):
         """Drives the pressure amplitude * sin(omega t) at the given nodes

@@ -659,6 +659,23 @@ int lbw_modes(lbw_state_t s, int k, double* freq_out, double* power_out) {
     return LBW_OK;
 }
 
+int lbw_modes_noalloc(lbw_state_t s, int k, double* freq_dev, double* power_dev) {
+    if (!s || !freq_dev || !power_dev) return fail(LBW_EINVAL, "NULL argument");
+    if (k < 1) return fail(LBW_EINVAL, "k must be >= 1");
+    if (s->n_probes < 1) return fail(LBW_EINVAL, "state has no probes");
+    const int64_t T = s->t < s->t_max ? s->t : s->t_max;
+    if (T < 8) return fail(LBW_EINVAL, "need at least 8 recorded rows (have %lld)", (long long)T);
+    if (lbw::modes_static_cols(T) < 1)
+        return fail(LBW_EINVAL, "%lld recorded rows exceed the fixed %zu-byte work space (at most %lld rows)",
+                    (long long)T, lbw::kModesScratchBytes, (long long)LBW_MODES_NOALLOC_MAX_ROWS);
+    void* scratch = nullptr;
+    HIP_TRY(lbw::modes_scratch(&scratch), "lbw_modes_noalloc: work space address");
+    HIP_TRY(lbw::launch_modes_static(scratch, s->trace, T, s->n_probes, s->n_probes, k, freq_dev, power_dev,
+                                     s->stream),
+            "lbw_modes_noalloc");
+    return LBW_OK;
+}
+
 int lbw_set_sources(lbw_state_t s, const int64_t* nodes, int n, double amplitude, double omega, int kind) {
     if (!s) return fail(LBW_EINVAL, "state is NULL");
     if (n < 0 || (n > 0 && !nodes)) return fail(LBW_EINVAL, "invalid source list");

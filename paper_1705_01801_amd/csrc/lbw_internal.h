@@ -159,5 +159,15 @@ int modes_max_cols(int64_t T);
 size_t modes_work_bytes(int64_t T, int max_cols, int max_groups);
 hipError_t launch_modes_grouped(const double* trace, int64_t T, int64_t stride, const int* group_ncols, int groups,
                                 int k, double* work, size_t work_bytes, double* freq, double* power, hipStream_t st);
+// The same spectrum for one group of ncols columns without allocating: the
+// work space is the library's fixed device array (kModesScratchBytes per
+// GPU; modes_scratch gives its address on the current device), columns are
+// transformed modes_static_cols(T) at a time and their power accumulated.
+// Nothing is waited for; freq and power (k doubles each) are device memory.
+constexpr size_t kModesScratchBytes = size_t(32) << 20;
+hipError_t modes_scratch(void** ptr);
+int modes_static_cols(int64_t T);  // 0 when one column does not fit
+hipError_t launch_modes_static(void* scratch_ptr, const double* trace, int64_t T, int64_t stride, int ncols, int k,
+                               double* freq, double* power, hipStream_t st);
 
 }  // namespace lbw

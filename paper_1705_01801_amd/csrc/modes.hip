@@ -16,6 +16,7 @@
 // trace whose rows hold `stride` values.  Groups are processed in chunks so
 // that the FFT work space stays bounded.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "lbw_internal.h"
@@ -148,7 +149,83 @@ __global__ __launch_bounds__(kPeakBlock) void peaks_kernel(const double* __restr
     }
 }
 
+// P[k] (+)= sum over columns [0, ncols) of |X|^2, for a single group whose
+// columns are transformed in passes (accumulate = 0 on the first pass).
+__global__ void power_accum_kernel(const double2* __restrict__ X, int64_t nfft, int ncols, int accumulate,
+                                   double* __restrict__ P) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k > nfft / 2) return;
+    double s = accumulate ? P[k] : 0.0;
+    for (int p = 0; p < ncols; ++p) {
+        const double2 v = X[(size_t)p * nfft + k];
+        s += v.x * v.x + v.y * v.y;
+    }
+    P[k] = s;
+}
+
+// Work space of the allocation-free spectrum: a fixed array in device
+// memory, one per GPU the library runs on, kept until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host the name
+// is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kModesScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+hipError_t modes_scratch(void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+int modes_static_cols(int64_t T) {
+    const int64_t nfft = modes_nfft(T);
+    const size_t per_col = 2 * (size_t)nfft * sizeof(double2);
+    const size_t p_bytes = ((size_t)(nfft / 2 + 1) * sizeof(double) + 255) / 256 * 256;
+    if (p_bytes + per_col > kModesScratchBytes) return 0;
+    return (int)((kModesScratchBytes - p_bytes) / per_col);
+}
+
+hipError_t launch_modes_static(void* scratch_ptr, const double* trace, int64_t T, int64_t stride, int ncols, int k,
+                               double* freq, double* power, hipStream_t st) {
+    const int64_t nfft = modes_nfft(T);
+    const int per_pass = modes_static_cols(T);
+    if (per_pass < 1 || ncols < 1) return hipErrorInvalidValue;
+    unsigned char* base = static_cast<unsigned char*>(scratch_ptr);
+    double* P = reinterpret_cast<double*>(base);
+    const size_t p_bytes = ((size_t)(nfft / 2 + 1) * sizeof(double) + 255) / 256 * 256;
+    double2* x0 = reinterpret_cast<double2*>(base + p_bytes);
+    double2* x1 = x0 + (size_t)nfft * per_pass;
+    for (int c0 = 0; c0 < ncols; c0 += per_pass) {
+        const int cols = std::min(per_pass, ncols - c0);
+        hipLaunchKernelGGL(prepare_kernel, dim3(cols), dim3(kBlock), 0, st, trace, T, stride, c0, nfft, x0);
+        double2* src = x0;
+        double2* dst = x1;
+        const unsigned fft_blocks = (unsigned)(((nfft / 2) * cols + kBlock - 1) / kBlock);
+        for (int64_t Ns = 1; Ns < nfft; Ns *= 2) {
+            hipLaunchKernelGGL(fft_pass_kernel, dim3(fft_blocks), dim3(kBlock), 0, st, src, dst, nfft, Ns, cols);
+            std::swap(src, dst);
+        }
+        hipLaunchKernelGGL(power_accum_kernel, dim3((unsigned)((nfft / 2 + 1 + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, st, src, nfft, cols, c0 > 0 ? 1 : 0, P);
+    }
+    hipLaunchKernelGGL(peaks_kernel, dim3(1), dim3(kPeakBlock), 0, st, P, nfft, k, freq, power);
+    return hipGetLastError();
+}
 
 int64_t modes_nfft(int64_t T) {
     int64_t p = 1;
