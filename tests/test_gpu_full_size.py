@@ -1,0 +1,116 @@
+"""GPU parity at the benchmark sizes against stored oracle results.
+
+The stored results are written by ``tests/golden/make_goldens.py``, which
+runs only the FP64 oracle on the seeded inputs of ``workloads``:
+
+* the full cylinder (128 x 128 x 256), horn (128 x 128 x 512) and torus
+  (96 x 256 x 512) for 1000 steps from their configured initial fields: the
+  probe traces (every probe, every step), the populations at 65,536 seeded
+  nodes, and sum sqrt(g) P before and after;
+* the same three on grids 4x coarser per axis, run for their configured
+  step counts (20,000 / 50,000 / 40,000): the first ten spectral peaks.
+
+The GPU runs in the launch shape the benchmark uses (the tuner's choice)
+and must match: traces within 1e-5 max|trace|, sampled populations within
+relative L2 1e-5, the invariant of the closed cylinder and torus within
+1e-5 of sum |f| (FP32 accumulation), mode frequencies within 1e-5
+relative with the same peaks found.
+"""
+import importlib.util
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1705_01801_amd as lbw
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+_spec = importlib.util.spec_from_file_location(
+    "make_goldens", os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_goldens.py"))
+G = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(G)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3])
+def test_full_size_thousand_steps_match_stored_oracle(idx):
+    ref = np.load(G.full_path(idx))
+    w = W.workload(idx)
+    assert str(ref["input_digest"]) == G.input_digest(w), "stored oracle run is for other inputs"
+    geom, P0, probes = w["geom"], w["P0"], w["probes"]
+    say("full size 1000 steps", w["name"])
+    g = lbw.Geometry(geom)
+    sim = lbw.Simulation(g, P0, probes, t_max=G.FULL_STEPS)
+    I0 = float(sim.populations().double().sum())
+    sim.autotune(reps=5)
+    say("  launch shape", g.step_config())
+    sim.step(G.FULL_STEPS)
+    f = sim.populations()
+    tr = sim.probe()
+    ref_tr = ref["trace"]
+    assert np.abs(tr - ref_tr).max() <= 1e-5 * np.abs(ref_tr).max()
+    nodes = ref["nodes"]
+    fs = f[:, nodes].double().cpu().numpy()
+    assert rel_l2(fs, ref["f"].astype(np.float64)) <= 1e-5
+    inv = ref["invariant"]
+    assert abs(I0 - inv[0]) <= 1e-6 * abs(f).double().sum().item()
+    if idx in (1, 3):                                   # closed: sum sqrt(g) P is conserved
+        I1 = float(f.double().sum())
+        assert abs(I1 - inv[1]) <= 1e-5 * float(f.double().abs().sum())
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3])
+def test_coarse_spectra_over_configured_steps_match_stored_oracle(idx):
+    ref = np.load(G.modes_path(idx))
+    w = W.workload(idx, scale=G.COARSE)
+    assert str(ref["input_digest"]) == G.input_digest(w), "stored oracle run is for other inputs"
+    steps = int(ref["steps"])
+    say("coarse spectra", w["name"], w["geom"]["n"], steps)
+    g = lbw.Geometry(w["geom"])
+    sim = lbw.Simulation(g, w["P0"], w["probes"], t_max=steps)
+    sim.step(steps)
+    freq, _ = sim.modes(G.MODES_K)
+    fo = ref["freq"]
+    ok = ~np.isnan(fo)
+    assert ok.sum() >= 5
+    assert np.array_equal(ok, ~np.isnan(freq))
+    assert np.abs(freq[ok] / fo[ok] - 1.0).max() <= 1e-5, (freq, fo)
+
+
+def test_full_torus_configured_run_growth_bounded():
+    """The torus configuration is not exactly neutral (its phi axis has
+    Mhat^phiphi >> 1 near rho_min with a phi-dependent Christoffel force):
+    the oracle on the 4x coarser grid grows 6369-fold over the configured
+    40,000 steps (2.2e-4 per step), and the rate falls about sixfold per
+    refinement, so on the full grid it is expected near 6e-6 per step,
+    about 1.3-fold over the run.  The full 96 x 256 x 512 torus in the
+    benchmark's launch shape runs the 40,000 steps with every probe value
+    finite and the population norm growing by at most 2x (rate <= 1.7e-5
+    per step)."""
+    import torch
+    w = W.workload(3)
+    steps = w["steps"]
+    say("full torus", steps, "steps")
+    g = lbw.Geometry(w["geom"])
+    sim = lbw.Simulation(g, w["P0"], w["probes"], t_max=steps)
+    sim.autotune(reps=5)
+    n0 = float(torch.linalg.vector_norm(sim.populations().double()))
+    ratios = []
+    for _ in range(10):
+        sim.step(steps // 10)
+        ratios.append(float(torch.linalg.vector_norm(sim.populations().double())) / n0)
+    say("  norm ratio every 4000 steps:", " ".join("%.4f" % r for r in ratios))
+    tr = sim.probe()                                       # raises on a non-finite value
+    assert tr.shape == (steps, len(w["probes"]))
+    assert max(ratios) <= 2.0, ratios
