@@ -107,8 +107,9 @@ def time_config(config, steps, warmup, launch="auto"):
         g.set_step_config(*(int(v) for v in launch.split(",")))
         tuned_us = float("nan")
     tile = g.step_config()
-    log("bench: %s, %d nodes, warmup %d, steps %d, launch shape %s (tuner %.2f us)" % (w["name"], N, warmup,
-                                                                                   steps, tile, tuned_us))
+    two = g.step2_config() if not general else (0, 0, 0, 0)
+    log("bench: %s, %d nodes, warmup %d, steps %d, launch shape %s, two-step %s (tuner %.2f us per step)"
+        % (w["name"], N, warmup, steps, tile, two, tuned_us))
     sim.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -132,7 +133,9 @@ def time_config(config, steps, warmup, launch="auto"):
            "residency": "infinity-cache" if working_set <= INFINITY_CACHE_BYTES else "hbm",
            "working_set_bytes": working_set, "probes": int(len(w["probes"])), "c": geom["c"],
            "launch": {"tile_x": tile[0], "tile_y": tile[1], "chunk_z": tile[2], "blocks": tile[3],
-                      "graph_block": 32}}
+                      "graph_block": 32, "steps_per_launch": 2 if two[0] else 1}}
+    if two[0]:
+        out["launch"]["two_step"] = {"tile_x": two[0], "tile_y": two[1], "chunk_z": two[2], "blocks": two[3]}
     sim.close()
     g.close()
     return out, w

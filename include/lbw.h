@@ -171,6 +171,24 @@ int lbw_stability_bound(lbw_geometry_t g, double* c_max);
 int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks);
 int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks);
 
+/* Two time steps per launch (temporal blocking) for this geometry: each
+ * launch advances the state from t to t+2 with one read and one write of
+ * every population, the intermediate state held on chip; the per-node
+ * arithmetic is the one-step kernel's, so results are identical bit for bit.
+ * A workgroup owns tile_y whole axis-0 rows plus a halo row either side
+ * (tile_x = 96 with tile_y = 6, or 128 with 4; 768 threads), chunk_z planes
+ * along axis 2; blocks as in lbw_set_step_config (0 = one wave).  Needs a
+ * 3-D built-in geometry with n0 <= tile_x and a walled axis 0.
+ * lbw_step_n then runs pairs of steps this way (an odd last step, and
+ * states with driven sources or with more than 16 probes in one tile of
+ * the pass, use one-step launches).  tile_x = 0 turns it off;
+ * lbw_set_step_config also turns it off; lbw_autotune turns it on when
+ * its best shape is faster per step.  Errors: LBW_EINVAL (other shapes, a
+ * geometry it does not fit, chunk_z < 1, blocks < 0). */
+int lbw_set_step2_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks);
+/* The two-step shape in use (tile_x = 0 and the rest 0 when off). */
+int lbw_get_step2_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks);
+
 /* Creates a simulation state on caller-owned device buffers.
  *  p0        device, N doubles: initial pressure P; populations start at the
  *            corrected equilibrium at rest, f_l = w_l sqrt(g) P0 with
@@ -204,7 +222,13 @@ int lbw_step_n(lbw_state_t s, int64_t n);
  * one wrote) from the state's current buffer into its other buffer and a
  * temporary buffer of Q*N floats (allocated for the call), with
  * probe recording off; the current buffer, step count and trace are
- * unchanged.  The choice is stored in the geometry and in a per-process
+ * unchanged.  The best shape is also timed with the other store policy
+ * (non-temporal population stores, the default where the two population
+ * buffers exceed the 256 MiB Infinity Cache, or cached ones).  Two-step
+ * launches (lbw_set_step2_config: tiles 96 x 6 and
+ * 128 x 4 where the geometry fits them, chunk_z 8 to 64, one and two waves)
+ * are timed per step as well, and used when faster.  The choice is stored in
+ * the geometry and in a per-process
  * cache keyed by the grid shape, which later geometries of that shape start
  * from.  Synchronises.  best_us (may be NULL) receives the best time per
  * step in microseconds.  Errors: LBW_EINVAL (2-D or LBW_GENERAL geometry,

@@ -24,7 +24,7 @@ TABLE_PLANES = ("Mhat00", "Mhat11", "Mhat22", "Mhat02", "Gamh0", "Gamh1", "Gamh2
 
 # every symbol include/lbw.h declares
 SYMBOLS = ("lbw_make_geometry", "lbw_make_geometry_general", "lbw_free_geometry", "lbw_geometry_export", "lbw_stability_bound",
-           "lbw_set_step_config", "lbw_get_step_config", "lbw_init",
+           "lbw_set_step_config", "lbw_get_step_config", "lbw_set_step2_config", "lbw_get_step2_config", "lbw_init",
            "lbw_step_n", "lbw_autotune", "lbw_set_graph_block", "lbw_probe", "lbw_modes", "lbw_modes_noalloc",
            "lbw_state_info",
            "lbw_pressure", "lbw_free_state", "lbw_set_sources", "lbw_amplitude", "lbw_batch_make", "lbw_batch_layout", "lbw_batch_set_step_config",
@@ -98,6 +98,8 @@ def lib():
         L.lbw_make_geometry_general.argtypes = [ctypes.POINTER(GeometryDesc), vp, vp, ctypes.POINTER(vp)]
         L.lbw_set_step_config.argtypes = [vp, i32, i32, i32, i32]
         L.lbw_get_step_config.argtypes = [vp, ip, ip, ip, ip]
+        L.lbw_set_step2_config.argtypes = [vp, i32, i32, i32, i32]
+        L.lbw_get_step2_config.argtypes = [vp, ip, ip, ip, ip]
         L.lbw_init.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), i32, vp, i64, vp, ctypes.POINTER(vp)]
         L.lbw_step_n.argtypes = [vp, i64]
         L.lbw_autotune.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
@@ -230,6 +232,17 @@ class Geometry:
         """(tile_x, tile_y, chunk_z, blocks) of the 3-D step kernel."""
         v = [ctypes.c_int() for _ in range(4)]
         check(lib().lbw_get_step_config(self.handle, *(ctypes.byref(x) for x in v)))
+        return tuple(x.value for x in v)
+
+    def set_step2_config(self, tile_x: int, tile_y: int = 0, chunk_z: int = 16, blocks: int = 0):
+        """Two time steps per launch with this shape (tile_x 96 with tile_y
+        6, or 128 with 4); tile_x = 0 turns it off."""
+        check(lib().lbw_set_step2_config(self.handle, int(tile_x), int(tile_y), int(chunk_z), int(blocks)))
+
+    def step2_config(self):
+        """(tile_x, tile_y, chunk_z, blocks) of the two-step launches, zeros when off."""
+        v = [ctypes.c_int() for _ in range(4)]
+        check(lib().lbw_get_step2_config(self.handle, *(ctypes.byref(x) for x in v)))
         return tuple(x.value for x in v)
 
     def close(self):

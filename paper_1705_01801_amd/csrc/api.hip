@@ -1,4 +1,5 @@
 // C-ABI entry points declared in include/lbw.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -26,6 +27,8 @@ struct lbw_geometry {
     hipStream_t stream = nullptr;
     GeomDev dev{};
     lbw::MarchPlan plan{};  // launch shape of the 3-D step
+    lbw::MarchPlan plan2{}; // launch shape of the two-step pass, used when use2
+    bool use2 = false;
     int plan_version = 0;   // bumped on every change of plan
 };
 
@@ -45,6 +48,8 @@ struct lbw_state {
     double* mode_out = nullptr;  // device, 2 * mode_k
     int mode_k = 0;
     int64_t* d_scratch_count = nullptr;  // step counter for timing launches
+    unsigned* d_done = nullptr;          // workgroups done in a two-step launch (real and timing runs)
+    std::vector<int64_t> probes_host;    // probe nodes (tiles of the two-step pass hold at most a few)
     lbw::SourceEntry* d_src = nullptr;   // driven sources, imposed before every step
     int n_src = 0;
     double* d_amp = nullptr;             // response intensities (n_probes)
@@ -52,15 +57,21 @@ struct lbw_state {
     int graph_block = 32;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_version = -1;
+    bool graph_two = false;  // the captured blocks are two-step launches
 };
 
 namespace {
 
 thread_local std::string g_err;
 
-// tuned launch shapes per grid shape (n0, n1, n2) -> (tile_x, tile_y, chunk_z, blocks)
+// tuned launch shapes per grid shape (n0, n1, n2) -> one-step (tile_x, tile_y,
+// chunk_z, blocks) and two-step shape (tile_x 0: one-step launches)
+struct Tuned {
+    int tx, ty, lz, blocks, nts;
+    int tx2, ty2, lz2, blocks2;
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, std::tuple<int, int, int, int>> g_tuned;
+std::map<std::tuple<int, int, int>, Tuned> g_tuned;
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -226,9 +237,15 @@ int lbw_make_geometry(const lbw_geometry_desc* desc, void* stream, lbw_geometry_
         g->plan = lbw::make_march_plan(v, tx, 256 / tx, 16, cus * lbw::march_blocks_per_cu(tx, 256 / tx));
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(std::make_tuple(v.n0, v.n1, v.n2));
-        if (it != g_tuned.end())
-            g->plan = lbw::make_march_plan(v, std::get<0>(it->second), std::get<1>(it->second),
-                                           std::get<2>(it->second), std::get<3>(it->second));
+        if (it != g_tuned.end()) {
+            const Tuned& c = it->second;
+            g->plan = lbw::make_march_plan(v, c.tx, c.ty, c.lz, c.blocks);
+            g->plan.nts = c.nts;
+            if (c.tx2 > 0 && lbw::march2_fits(v, c.tx2)) {
+                g->plan2 = lbw::make_march2_plan(v, c.tx2, c.ty2, c.lz2, c.blocks2);
+                g->use2 = true;
+            }
+        }
     }
     *out = g;
     return LBW_OK;
@@ -398,7 +415,42 @@ int lbw_set_step_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, i
         blocks = cus * lbw::march_blocks_per_cu(tile_x, tile_y);
     }
     g->plan = lbw::make_march_plan(g->dev, tile_x, tile_y, chunk_z, blocks);
+    g->use2 = false;
     g->plan_version += 1;
+    return LBW_OK;
+}
+
+int lbw_set_step2_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks) {
+    if (!g) return fail(LBW_EINVAL, "geometry is NULL");
+    if (tile_x == 0) {
+        g->use2 = false;
+        g->plan_version += 1;
+        return LBW_OK;
+    }
+    if (g->dev.dim != 3 || g->general) return fail(LBW_EINVAL, "two-step launches apply to built-in 3-D geometries");
+    if (!lbw::march2_shape_ok(tile_x, tile_y))
+        return fail(LBW_EINVAL, "two-step tile %d x %d: must be 96 x 6 or 128 x 4", tile_x, tile_y);
+    if (!lbw::march2_fits(g->dev, tile_x))
+        return fail(LBW_EINVAL, "two-step tile of %d lanes: needs n0 <= %d (n0 = %d) and a walled axis 0", tile_x,
+                    tile_x, g->dev.n0);
+    if (chunk_z < 1 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 1 and blocks >= 0");
+    if (blocks == 0) {
+        int cus = 0;
+        if (lbw::device_cus(&cus) != LBW_OK) return LBW_EDEVICE;
+        blocks = cus * lbw::march2_blocks_per_cu(tile_x, tile_y);
+    }
+    g->plan2 = lbw::make_march2_plan(g->dev, tile_x, tile_y, chunk_z, blocks);
+    g->use2 = true;
+    g->plan_version += 1;
+    return LBW_OK;
+}
+
+int lbw_get_step2_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks) {
+    if (!g) return fail(LBW_EINVAL, "geometry is NULL");
+    if (tile_x) *tile_x = g->use2 ? g->plan2.tx : 0;
+    if (tile_y) *tile_y = g->use2 ? g->plan2.ty : 0;
+    if (chunk_z) *chunk_z = g->use2 ? g->plan2.lz : 0;
+    if (blocks) *blocks = g->use2 ? g->plan2.blocks : 0;
     return LBW_OK;
 }
 
@@ -430,8 +482,11 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
     s->n_probes = n_probes;
     s->trace = trace;
     s->stream = (hipStream_t)stream;
+    s->probes_host.assign(probes, probes + n_probes);
     hipError_t e = hipMalloc(&s->d_tcount, sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc(&s->d_scratch_count, sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&s->d_done, 2 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_done, 0, 2 * sizeof(unsigned), s->stream);
     if (e == hipSuccess && n_probes > 0) e = hipMalloc(&s->d_probes, sizeof(int64_t) * n_probes);
     if (e == hipSuccess && n_probes > 0)
         e = hipMemcpyAsync(s->d_probes, probes, sizeof(int64_t) * n_probes, hipMemcpyHostToDevice, s->stream);
@@ -443,6 +498,7 @@ int lbw_init(lbw_geometry_t g, const double* p0, float* f_a, float* f_b, const i
     if (e != hipSuccess) {
         (void)hipFree(s->d_tcount);
         (void)hipFree(s->d_scratch_count);
+        (void)hipFree(s->d_done);
         (void)hipFree(s->d_probes);
         delete s;
         return hip_fail(e, "lbw_init");
@@ -465,6 +521,29 @@ hipError_t launch_one(lbw_state* s, const lbw::ProbeArgs& pr, int from, hipStrea
     return lbw::launch_step(s->g->dev, pr, s->f[from], s->f[1 - from], st);
 }
 
+// The two-step pass applies: chosen for the geometry, no driven sources
+// (they are imposed between steps), and no tile of the pass holds more
+// probes than it records.
+bool two_step_ok(const lbw_state* s) {
+    const lbw_geometry* g = s->g;
+    if (!g->use2 || g->general || g->dev.dim != 3 || s->n_src > 0 || !lbw::march2_fits(g->dev, g->plan2.tx))
+        return false;
+    if (s->n_probes == 0 || s->t >= s->t_max) return true;
+    std::map<int64_t, int> per_tile;
+    const int64_t n0 = g->dev.n0, n1 = g->dev.n1;
+    for (int64_t node : s->probes_host) {
+        const int64_t i1 = (node / n0) % n1, i2 = node / (n0 * n1);
+        const int64_t tile = i1 / g->plan2.ty + (int64_t)g->plan2.nty * (i2 / g->plan2.lz);
+        if (++per_tile[tile] > lbw::march2_tile_probes()) return false;
+    }
+    return true;
+}
+
+hipError_t launch_two(lbw_state* s, int from, hipStream_t st) {
+    lbw::ProbeArgs pr{s->d_probes, s->n_probes, s->trace, s->t_max, s->d_tcount, s->d_done};
+    return lbw::launch_step_march2(s->g->dev, pr, s->g->plan2, s->f[from], s->f[1 - from], st);
+}
+
 void drop_graphs(lbw_state* s) {
     for (auto& gx : s->graph) {
         if (gx) (void)hipGraphExecDestroy(gx);
@@ -472,9 +551,10 @@ void drop_graphs(lbw_state* s) {
     }
 }
 
-// Captures graph_block steps starting from buffer `from` on a private
+// Captures graph_block steps (one-step launches, or graph_block / 2
+// two-step launches when two) starting from buffer `from` on a private
 // stream (capture only records; nothing runs there).
-hipError_t build_graph(lbw_state* s, int from) {
+hipError_t build_graph(lbw_state* s, int from, bool two) {
     hipStream_t cap = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
@@ -484,8 +564,9 @@ hipError_t build_graph(lbw_state* s, int from) {
     if (e == hipSuccess) {
         int cur = from;
         hipError_t le = hipSuccess;
-        for (int i = 0; i < s->graph_block && le == hipSuccess; ++i) {
-            le = launch_one(s, pr, cur, cap);
+        const int launches = two ? s->graph_block / 2 : s->graph_block;
+        for (int i = 0; i < launches && le == hipSuccess; ++i) {
+            le = two ? launch_two(s, cur, cap) : launch_one(s, pr, cur, cap);
             cur ^= 1;
         }
         e = hipStreamEndCapture(cap, &graph);
@@ -502,20 +583,30 @@ hipError_t build_graph(lbw_state* s, int from) {
 int lbw_step_n(lbw_state_t s, int64_t n) {
     if (!s) return fail(LBW_EINVAL, "state is NULL");
     if (n < 0) return fail(LBW_EINVAL, "negative step count");
-    lbw::ProbeArgs pr{s->d_probes, s->n_probes, s->trace, s->t_max, s->d_tcount};
-    const int K = s->graph_block;
+    lbw::ProbeArgs pr{s->d_probes, s->n_probes, s->trace, s->t_max, s->d_tcount, s->d_done};
+    const bool two = two_step_ok(s);
+    // steps per captured block: even for two-step launches
+    const int K = two ? s->graph_block & ~1 : s->graph_block;
     if (K > 0 && n >= K) {
-        if (s->graph_version != s->g->plan_version) {
+        if (s->graph_version != s->g->plan_version || s->graph_two != two) {
             drop_graphs(s);
             s->graph_version = s->g->plan_version;
+            s->graph_two = two;
         }
+        const int launches = two ? K / 2 : K;
         while (n >= K) {
-            if (!s->graph[s->cur]) HIP_TRY(build_graph(s, s->cur), "lbw_step_n: graph capture");
+            if (!s->graph[s->cur]) HIP_TRY(build_graph(s, s->cur, two), "lbw_step_n: graph capture");
             HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream), "lbw_step_n: graph launch");
-            if (K & 1) s->cur ^= 1;
+            if (launches & 1) s->cur ^= 1;
             s->t += K;
             n -= K;
         }
+    }
+    while (two && n >= 2) {
+        HIP_TRY(launch_two(s, s->cur, s->stream), "lbw_step_n");
+        s->cur ^= 1;
+        s->t += 2;
+        n -= 2;
     }
     for (int64_t i = 0; i < n; ++i) {
         HIP_TRY(launch_one(s, pr, s->cur, s->stream), "lbw_step_n");
@@ -589,18 +680,94 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
             }
         }
     }
+    // two time steps per launch: timed per step (reps launches = 2 reps
+    // steps), on the same ping-pong buffers with the timing step counter
+    // and its own completion counter
+    lbw::MarchPlan best2{};
+    float best2_ms = 1e30f;  // per 2 reps steps
+    const lbw::ProbeArgs pr2{nullptr, 0, nullptr, 0, s->d_scratch_count, s->d_done + 1};
+    for (int tx : {96, 128}) {
+        const int ty = tx == 96 ? 6 : 4;
+        if (err != hipSuccess || !lbw::march2_fits(g->dev, tx)) continue;
+        const int bpc = lbw::march2_blocks_per_cu(tx, ty);
+        // chunk lengths: besides the plain ones, those whose tile count
+        // fills whole waves of resident workgroups (tiles of equal work)
+        std::vector<int> lzs{8, 12, 16, 20, 24, 32, 40, 48, 64};
+        for (int waves = 1; waves <= 8; ++waves) {
+            const int nty = (g->dev.n1 + ty - 1) / ty;
+            const int64_t want = (int64_t)waves * cus * bpc;  // tiles
+            if (want % nty) continue;
+            const int64_t chunks = want / nty;
+            const int lz = (int)((g->dev.n2 + chunks - 1) / chunks);
+            if (lz >= 4 && std::find(lzs.begin(), lzs.end(), lz) == lzs.end()) lzs.push_back(lz);
+        }
+        for (int lz : lzs) {
+            if (lz > 2 * g->dev.n2 && lz != 8) continue;
+            for (int mult : {1, 2}) {
+                const lbw::MarchPlan p = lbw::make_march2_plan(g->dev, tx, ty, lz, mult * cus * bpc);
+                float* bufs[2] = {other, tmp};
+                int w = 0;
+                auto run = [&](int count) {
+                    for (int r = 0; r < count && err == hipSuccess; ++r, w ^= 1)
+                        err = lbw::launch_step_march2(g->dev, pr2, p, bufs[w], bufs[w ^ 1], s->stream);
+                };
+                if (err == hipSuccess) err = lbw::launch_step_march2(g->dev, pr2, p, s->f[s->cur], other, s->stream);
+                run(2);
+                if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
+                run(reps);
+                if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                if (err != hipSuccess) break;
+                if (ms < best2_ms) {
+                    best2_ms = ms;
+                    best2 = p;
+                }
+            }
+        }
+    }
+    // the best shape with the other store policy (non-temporal stores pay on
+    // grids that do not fit the caches, and cost where they do)
+    if (err == hipSuccess) {
+        lbw::MarchPlan p = best;
+        p.nts = !p.nts;
+        float* bufs[2] = {other, tmp};
+        int w = 0;
+        auto run = [&](int count) {
+            for (int r = 0; r < count && err == hipSuccess; ++r, w ^= 1)
+                err = lbw::launch_step_march(g->dev, pr, p, bufs[w], bufs[w ^ 1], s->stream);
+        };
+        if (err == hipSuccess) err = lbw::launch_step_march(g->dev, pr, p, s->f[s->cur], other, s->stream);
+        run(2);
+        if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
+        run(reps);
+        if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = p;
+        }
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s->stream);
     (void)hipFree(tmp);
     g->plan = err == hipSuccess ? best : keep;
+    const bool two = err == hipSuccess && best2_ms < 2.f * best_ms;
+    g->use2 = two;
+    if (two) g->plan2 = best2;
     g->plan_version += 1;
     if (err != hipSuccess) return hip_fail(err, "lbw_autotune");
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[std::make_tuple(g->dev.n0, g->dev.n1, g->dev.n2)] = std::make_tuple(best.tx, best.ty, best.lz, best.blocks);
+        g_tuned[std::make_tuple(g->dev.n0, g->dev.n1, g->dev.n2)] =
+            Tuned{best.tx, best.ty, best.lz, best.blocks, best.nts, two ? best2.tx : 0, best2.ty, best2.lz,
+                  best2.blocks};
     }
-    if (best_us) *best_us = 1e3 * best_ms / reps;
+    if (best_us) *best_us = two ? 1e3 * best2_ms / (2 * reps) : 1e3 * best_ms / reps;
     return LBW_OK;
 }
 
@@ -758,6 +925,7 @@ int lbw_free_state(lbw_state_t s) {
     (void)hipStreamSynchronize(s->stream);
     drop_graphs(s);
     (void)hipFree(s->d_scratch_count);
+    (void)hipFree(s->d_done);
     (void)hipFree(s->d_tcount);
     (void)hipFree(s->d_probes);
     (void)hipFree(s->d_src);

@@ -73,6 +73,7 @@ struct ProbeArgs {
     double* trace;         // device, t_max * n
     int64_t t_max;
     int64_t* tcount;       // device step counter
+    unsigned* tdone;       // device, workgroups finished in the current two-step launch (0 between launches)
 };
 hipError_t launch_step(const GeomDev& g, const ProbeArgs& pr, const float* fin, float* fout, hipStream_t st);
 // One step of a geometry given by its metric (3-D, per-node coefficients),
@@ -89,13 +90,30 @@ struct MarchPlan {
     int ntx, nty, nchunks;
     int64_t tiles;       // ntx * nty * nchunks
     int blocks;          // persistent grid size (multiple of 8)
+    int nts;             // 1: non-temporal population stores (one-step kernel)
 };
+// Default store policy: non-temporal when the two population buffers exceed
+// the 256 MiB Infinity Cache.
+bool march_nts_default(const GeomDev& g);
 MarchPlan make_march_plan(const GeomDev& g, int tx, int ty, int lz, int blocks);
 int march_tx_for(int n0);
 bool march_shape_ok(int tx, int ty);  // tx in {16, 32, 64}, tx * ty in {256, 512}
 int march_blocks_per_cu(int tx, int ty);
 hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
                              float* fout, hipStream_t st);
+
+// Two time steps per launch (step_march2.hip): workgroups of tx x (ty + 2)
+// threads own ty whole axis-0 rows (n0 <= tx, axis 0 walled) over chunks of
+// lz planes; plan.ntx is 1.  Shapes: 96 x 6 and 128 x 4 (768 threads).
+// The step counter advances by two per launch (needs pr.tdone); the probes
+// of both times are recorded, at most march2_tile_probes() per tile.
+bool march2_shape_ok(int tx, int ty);
+bool march2_fits(const GeomDev& g, int tx);
+int march2_tile_probes();
+int march2_blocks_per_cu(int tx, int ty);
+MarchPlan make_march2_plan(const GeomDev& g, int tx, int ty, int lz, int blocks);
+hipError_t launch_step_march2(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
+                              float* fout, hipStream_t st);
 
 // One geometry of a batch (all D3Q7), as read by the batch step kernel.
 struct BatchItem {

@@ -1,0 +1,142 @@
+// Device helpers shared by the z-marching D3Q7 step kernels: buffer
+// addressing, wall rules and the per-node collision.  Every kernel that
+// updates a node calls collide(), so the per-node arithmetic, and with it
+// every result, is the same whichever kernel or launch shape runs it.
+#pragma once
+
+#include "lbw_internal.h"
+
+namespace lbw {
+namespace march {
+
+constexpr int kXcds = 8;
+
+__device__ inline float sum7(const float v[7]) {
+    return v[0] + v[1] + v[2] + v[3] + v[4] + v[5] + v[6];
+}
+
+// Buffer addressing: 32-bit byte offsets from a per-geometry base; an offset
+// of kOff is outside every range, so such a load returns 0 and such a store
+// is dropped by the hardware range check.  Every load and store of a plane
+// loop is issued by every lane, disabled ones with kOff, so the loop has no
+// branch around a memory operation and the wait counts stay exact.
+constexpr uint32_t kOff = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family format word
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ inline float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ inline float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
+}
+__device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)off, 0, 0);
+}
+// the same store, non-temporal when NTS (the gfx950 "nt" cache policy): for
+// grids whose populations do not fit the caches, the written plane is not
+// read again before a whole pass over memory, so keeping it cached is waste
+constexpr int kNontemporal = 2;
+template <bool NTS>
+__device__ inline void bstp(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)off, 0, NTS ? kNontemporal : 0);
+}
+// the 7 populations of the node at byte offset nb, or nothing (all zeros)
+// (kOff + 6 N4 stays below 2^32 because 7 N4 < 2^31, so a disabled base
+// keeps every population's offset out of range)
+__device__ inline void bload7(__amdgpu_buffer_rsrc_t r, uint32_t N4, bool on, uint32_t nb, float v[7]) {
+    const uint32_t base = on ? nb : kOff;
+#pragma unroll
+    for (int l = 0; l < 7; ++l) v[l] = bld(r, base + (uint32_t)l * N4);
+}
+
+// value beyond a wall: mirrored, odd for fixed walls
+__device__ inline float ghost(int wall, float v) { return wall == LBW_BC_FIXED ? -v : v; }
+
+// population that a wall returns into the opposite direction at the node:
+// bounce-back D f*_l, free f*_{lbar} (the node's own), fixed -f*_l
+__device__ inline float bounce(int wall, float damp, float out_l, float own_lb) {
+    return wall == LBW_BC_BOUNCEBACK ? damp * out_l : (wall == LBW_BC_FREE ? own_lb : -out_l);
+}
+
+// The links of one node: neighbour coordinate along each axis and direction
+// (-1 across a wall) and the wall code there.
+struct Links {
+    int jx_p, jx_m, jy_p, jy_m, jz_p, jz_m;
+    int wx_p, wx_m, wy_p, wy_m, wz_p, wz_m;
+};
+
+// The axis-1 part of the collision below, f*_3 and f*_4 (the only
+// coefficient it needs is c^2 Mhat11; its neighbours are those along axis 1).
+// collide() computes its f*_3 and f*_4 by calling this, so a kernel that
+// needs only these two gets the same bits.
+__device__ __forceinline__ void collide_axis1(float f3, float f4, float S, float cM11, float Syp, float Sym,
+                                              const Links& k, float c2, float& fs3, float& fs4) {
+#pragma clang fp contract(off)
+    const float A11p = cM11 * (k.jy_p >= 0 ? Syp : ghost(k.wy_p, S));
+    const float A11m = cM11 * (k.jy_m >= 0 ? Sym : ghost(k.wy_m, S));
+    const float K1 = (f3 - f4) - 0.25f * (A11p - A11m);
+    const float cs = c2 * S;
+    fs3 = cs + K1 - f3;
+    fs4 = cs - K1 - f4;
+}
+
+// Collision at one node (Sec. II evolution equation at tau = 1/2 with the
+// corrected equilibrium, Christoffel and metric-gradient forcing of
+// Sec. III), f* = 2 f^eq - f:
+//   A^{de} = c^2 S Mhat^{de}, mirrored beyond walls (odd for fixed walls),
+//   K_d = f_{+d} - f_{-d} - (c^2 / 2) S Gamh^d - (1/4) sum_e [A^{de}(x+e_e) - A^{de}(x-e_e)],
+//   f*_0 = 2 w_0 S - f_0, f*_{+-d} = c^2 S +- K_d - f_{+-d}.
+// fc: the node's populations; S their sum; e_lo / e_hi: the node's table
+// record {c^2 Mhat00, 02, 22, 11}, {c^2 Gamh0 / 2, c^2 Gamh2 / 2, 0, 0};
+// enp / enm: the low records of the axis-0 neighbours; ezp: that of the
+// axis-2 neighbour above; em: (c^2 Mhat02, c^2 Mhat22) of the one below;
+// Sx*, Sy*, Sp, Sm: S of the axis-0, axis-1 and axis-2 neighbours (read
+// only where the link exists).
+__device__ __forceinline__ void collide(const float (&fc)[7], float S, float4 e_lo, float4 e_hi, float4 enp,
+                                        float4 enm, float4 ezp, float2 em, float Sxp, float Sxm, float Syp,
+                                        float Sym, float Sp, float Sm, const Links& k, float c2, float two_w0,
+                                        float (&fs)[7]) {
+    // every product and sum rounded on its own (no fused multiply-add), so
+    // the result does not depend on how the surrounding kernel is compiled
+#pragma clang fp contract(off)
+    const float cM00 = e_lo.x, cM02 = e_lo.y, cM22 = e_lo.z, cM11 = e_lo.w;
+    const float hG0 = e_hi.x, hG2 = e_hi.y;
+    const float gxp = ghost(k.wx_p, S), gxm = ghost(k.wx_m, S);
+    const float A00p = k.jx_p >= 0 ? enp.x * Sxp : cM00 * gxp;
+    const float A20p = k.jx_p >= 0 ? enp.y * Sxp : cM02 * gxp;
+    const float A00m = k.jx_m >= 0 ? enm.x * Sxm : cM00 * gxm;
+    const float A20m = k.jx_m >= 0 ? enm.y * Sxm : cM02 * gxm;
+    float A22p, A22m, A02p, A02m;
+    if (k.jz_p >= 0) {
+        A02p = ezp.y * Sp;
+        A22p = ezp.z * Sp;
+    } else {
+        const float sg = ghost(k.wz_p, S);
+        A22p = cM22 * sg;
+        A02p = cM02 * sg;
+    }
+    if (k.jz_m >= 0) {
+        A02m = em.x * Sm;
+        A22m = em.y * Sm;
+    } else {
+        const float sg = ghost(k.wz_m, S);
+        A22m = cM22 * sg;
+        A02m = cM02 * sg;
+    }
+    const float K0 = (fc[1] - fc[2]) - hG0 * S - 0.25f * (A00p - A00m) - 0.25f * (A02p - A02m);
+    const float K2 = (fc[5] - fc[6]) - hG2 * S - 0.25f * ((A22p - A22m) + (A20p - A20m));
+    const float cs = c2 * S;
+    fs[0] = two_w0 * S - fc[0];
+    fs[1] = cs + K0 - fc[1];
+    fs[2] = cs - K0 - fc[2];
+    collide_axis1(fc[3], fc[4], S, cM11, Syp, Sym, k, c2, fs[3], fs[4]);
+    fs[5] = cs + K2 - fc[5];
+    fs[6] = cs - K2 - fc[6];
+}
+
+}  // namespace march
+}  // namespace lbw

@@ -32,22 +32,14 @@
 // Byte offsets are 32-bit: the library keeps 4 Q N below 2^31.
 #include <type_traits>
 
-#include "lbw_internal.h"
+#include "march_common.h"
 
 namespace lbw {
 namespace {
 
 constexpr int kBatchThreads = 256;
-constexpr int kXcds = 8;
 
-__device__ inline void load7(const float* __restrict__ f, uint32_t N, uint32_t n, float v[7]) {
-#pragma unroll
-    for (int l = 0; l < 7; ++l) v[l] = f[l * N + n];
-}
-
-__device__ inline float sum7(const float v[7]) {
-    return v[0] + v[1] + v[2] + v[3] + v[4] + v[5] + v[6];
-}
+using namespace march;
 
 struct TileGeom {
     int n0, n1, n2;
@@ -83,49 +75,12 @@ __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* 
     if (threadIdx.x == 0) *(volatile int64_t*)pr.tcount = t + 1;
 }
 
-// Buffer addressing: 32-bit byte offsets from a per-geometry base; an offset
-// of kOff is outside every range, so such a load returns 0 and such a store
-// is dropped by the hardware range check.  Every load and store of the plane
-// loop is issued by every lane, disabled ones with kOff, so the loop has no
-// branch around a memory operation and the wait counts stay exact.
-constexpr uint32_t kOff = 0x80000000u;
-constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit buffer, gfx9-family format word
-
-__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
-}
-__device__ inline float bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-}
-__device__ inline float4 bld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
-    return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
-}
-__device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)off, 0, 0);
-}
-// the 7 populations of the node at byte offset nb, or nothing (all zeros)
-// (kOff + 6 N4 stays below 2^32 because 7 N4 < 2^31, so a disabled base
-// keeps every population's offset out of range)
-__device__ inline void bload7(__amdgpu_buffer_rsrc_t r, uint32_t N4, bool on, uint32_t nb, float v[7]) {
-    const uint32_t base = on ? nb : kOff;
-#pragma unroll
-    for (int l = 0; l < 7; ++l) v[l] = bld(r, base + (uint32_t)l * N4);
-}
-
-// value beyond a wall: mirrored, odd for fixed walls
-__device__ inline float ghost(int wall, float v) { return wall == LBW_BC_FIXED ? -v : v; }
-
-__device__ inline float bounce(int wall, float damp, float out_l, float own_lb) {
-    return wall == LBW_BC_BOUNCEBACK ? damp * out_l : (wall == LBW_BC_FREE ? own_lb : -out_l);
-}
-
 // One tile of one geometry: columns [x0, x0 + TX) x [y0, y0 + TY), planes
 // [z0, z0 + lz).  fin/fout point at the geometry's own population block.
 // RT: the tile is g.rtx x g.rty columns instead (at most NT of them, with
 // 2 (rtx + rty) <= NT ring loaders and rtx + 2 <= NT row loaders, checked by
 // the host); TX = NT then only sizes the LDS arrays.
-template <int TX, int NT, bool ROW, bool RT = false>
+template <int TX, int NT, bool ROW, bool RT = false, bool NTS = false>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
                                            float* __restrict__ fout, float (&sS)[2][lds_s<TX, NT, RT>()],
                                            float4 (&sElo)[3][TX + 3], float4 (&sEhi)[3][TX + 3]) {
@@ -299,51 +254,25 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             const float S = Sc;
             const float4 e_lo = sElo[es][lx + 1];  // 00, 02, 22, 11
             const float4 e_hi = sEhi[es][lx + 1];  // g0/2, g2/2, 0, 0
-            const float cM00 = e_lo.x, cM02 = e_lo.y, cM22 = e_lo.z, cM11 = e_lo.w;
-            const float hG0 = e_hi.x, hG2 = e_hi.y;
-            float A22p, A22m, A02p, A02m;
             // axis-0/1 neighbours: read unconditionally (every index is inside
-            // the LDS arrays), then select the wall rule
-            const float4 enp = sElo[es][lx + 2];
-            const float4 enm = sElo[es][lx];
-            const float Sxp = L[my_lds + 1], Sxm = L[my_lds - 1];
-            const float Syp = L[my_lds + W], Sym = L[my_lds - W];
-            const float gxp = ghost(wx_p, S), gxm = ghost(wx_m, S);
-            const float A00p = jx_p >= 0 ? enp.x * Sxp : cM00 * gxp;
-            const float A20p = jx_p >= 0 ? enp.y * Sxp : cM02 * gxp;
-            const float A00m = jx_m >= 0 ? enm.x * Sxm : cM00 * gxm;
-            const float A20m = jx_m >= 0 ? enm.y * Sxm : cM02 * gxm;
-            const float A11p = cM11 * (jy_p >= 0 ? Syp : ghost(wy_p, S));
-            const float A11m = cM11 * (jy_m >= 0 ? Sym : ghost(wy_m, S));
-            if (jz_p >= 0) {
-                const float4 en = sElo[es1][lx + 1];
-                A02p = en.y * Sp;
-                A22p = en.z * Sp;
-            } else {
-                const float sg = ghost(wz_p, S);
-                A22p = cM22 * sg;
-                A02p = cM02 * sg;
-            }
-            if (jz_m >= 0) {
-                A02m = em.x * Sm;
-                A22m = em.y * Sm;
-            } else {
-                const float sg = ghost(wz_m, S);
-                A22m = cM22 * sg;
-                A02m = cM02 * sg;
-            }
-            const float K0 = (fc[1] - fc[2]) - hG0 * S - 0.25f * (A00p - A00m) - 0.25f * (A02p - A02m);
-            const float K1 = (fc[3] - fc[4]) - 0.25f * (A11p - A11m);
-            const float K2 = (fc[5] - fc[6]) - hG2 * S - 0.25f * ((A22p - A22m) + (A20p - A20m));
-            const float cs = c2 * S;
+            // the LDS arrays); collide() selects the wall rule
+            Links k;
+            k.jx_p = jx_p;
+            k.jx_m = jx_m;
+            k.jy_p = jy_p;
+            k.jy_m = jy_m;
+            k.jz_p = jz_p;
+            k.jz_m = jz_m;
+            k.wx_p = wx_p;
+            k.wx_m = wx_m;
+            k.wy_p = wy_p;
+            k.wy_m = wy_m;
+            k.wz_p = wz_p;
+            k.wz_m = wz_m;
             float fs[7];
-            fs[0] = two_w0 * S - fc[0];
-            fs[1] = cs + K0 - fc[1];
-            fs[2] = cs - K0 - fc[2];
-            fs[3] = cs + K1 - fc[3];
-            fs[4] = cs - K1 - fc[4];
-            fs[5] = cs + K2 - fc[5];
-            fs[6] = cs - K2 - fc[6];
+            collide(fc, S, e_lo, e_hi, sElo[es][lx + 2], sElo[es][lx], sElo[es1][lx + 1], em, L[my_lds + 1],
+                    L[my_lds - 1], L[my_lds + W], L[my_lds - W], Sp, Sm, k, c2, two_w0, fs);
+            const float cM02 = e_lo.y, cM22 = e_lo.z;
 
             // push with the wall rules: destination offset and value by select
             const uint32_t nb = col4 + (uint32_t)z * plane4;
@@ -391,13 +320,13 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             const float v4 = jy_m >= 0 ? fs[4] : bounce(wy_m, damp, fs[4], fs[3]);
             const float v5 = jz_p >= 0 ? fs[5] : bounce(wz_p, damp, fs[5], fs[6]);
             const float v6 = jz_m >= 0 ? fs[6] : bounce(wz_m, damp, fs[6], fs[5]);
-            bst(rout, active ? o0 : kOff, fs[0]);
-            bst(rout, active ? o1 : kOff, v1);
-            bst(rout, active ? o2 : kOff, v2);
-            bst(rout, active ? o3 : kOff, v3);
-            bst(rout, active ? o4 : kOff, v4);
-            bst(rout, active ? o5 : kOff, v5);
-            bst(rout, active ? o6 : kOff, v6);
+            bstp<NTS>(rout, active ? o0 : kOff, fs[0]);
+            bstp<NTS>(rout, active ? o1 : kOff, v1);
+            bstp<NTS>(rout, active ? o2 : kOff, v2);
+            bstp<NTS>(rout, active ? o3 : kOff, v3);
+            bstp<NTS>(rout, active ? o4 : kOff, v4);
+            bstp<NTS>(rout, active ? o5 : kOff, v5);
+            bstp<NTS>(rout, active ? o6 : kOff, v6);
             em = make_float2(cM02, cM22);
 
             if (more) {
@@ -424,7 +353,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
     }
 }
 
-template <int TX, int NT, bool ROW>
+template <int TX, int NT, bool ROW, bool NTS>
 __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
@@ -453,7 +382,7 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
     const int t_begin = (int)(plan.tiles * xcd / kXcds);
     const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
     for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
-        march_tile<TX, NT, ROW>(tg, tile, fin, fout, sS, sElo, sEhi);
+        march_tile<TX, NT, ROW, false, NTS>(tg, tile, fin, fout, sS, sElo, sEhi);
 }
 
 // Batch of geometries advanced by one launch: tiles of all geometries form
@@ -532,6 +461,11 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restr
 
 }  // namespace
 
+bool march_nts_default(const GeomDev& g) {
+    // two population buffers of 4 Q N bytes against the 256 MiB Infinity Cache
+    return 2.0 * 4.0 * (2 * g.dim + 1) * (double)g.N > 256.0 * 1024.0 * 1024.0;
+}
+
 int march_tx_for(int n0) { return n0 <= 16 ? 16 : (n0 <= 32 ? 32 : 64); }
 
 bool march_shape_ok(int tx, int ty) {
@@ -545,19 +479,24 @@ namespace {
 template <int TX, int NT>
 int blocks_per_cu_of() {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<TX, NT, false>, NT, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<TX, NT, false, false>, NT, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 template <int TX, int NT>
 void launch_of(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin, float* fout,
                hipStream_t st) {
-    // whole walled rows fit one tile: the variant with the axis-0 lane shift
-    if (g.n0 <= TX && g.bc_lo[0] != LBW_BC_PERIODIC)
-        hipLaunchKernelGGL((step_march_kernel<TX, NT, true>), dim3(plan.blocks), dim3(NT), 0, st, g, pr, plan, fin,
-                           fout);
+    // whole walled rows fit one tile: the variant with the axis-0 lane shift;
+    // non-temporal stores as the plan says
+    const bool row = g.n0 <= TX && g.bc_lo[0] != LBW_BC_PERIODIC;
+    const dim3 grid(plan.blocks), block(NT);
+    if (row && plan.nts)
+        hipLaunchKernelGGL((step_march_kernel<TX, NT, true, true>), grid, block, 0, st, g, pr, plan, fin, fout);
+    else if (row)
+        hipLaunchKernelGGL((step_march_kernel<TX, NT, true, false>), grid, block, 0, st, g, pr, plan, fin, fout);
+    else if (plan.nts)
+        hipLaunchKernelGGL((step_march_kernel<TX, NT, false, true>), grid, block, 0, st, g, pr, plan, fin, fout);
     else
-        hipLaunchKernelGGL((step_march_kernel<TX, NT, false>), dim3(plan.blocks), dim3(NT), 0, st, g, pr, plan, fin,
-                           fout);
+        hipLaunchKernelGGL((step_march_kernel<TX, NT, false, false>), grid, block, 0, st, g, pr, plan, fin, fout);
 }
 }  // namespace
 
@@ -646,6 +585,7 @@ hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_
 
 MarchPlan make_march_plan(const GeomDev& g, int tx, int ty, int lz, int blocks) {
     MarchPlan p{};
+    p.nts = march_nts_default(g);
     p.tx = tx;
     p.ty = ty;
     p.lz = lz < 1 ? 1 : lz;

@@ -1,0 +1,485 @@
+// Two time steps per pass of the D3Q7 z-march (temporal blocking).
+//
+// The one-step kernels read every population once and write it once per
+// step, 56 bytes per node update, and on grids that do not fit the caches
+// that is the whole cost.  This kernel advances a tile from t to t+2 in one
+// pass over memory, so the populations are read and written once per two
+// updates:
+//  - a workgroup of TX x (TY + 2) threads owns TY whole axis-0 rows (the
+//    grid's walled axis 0 fits one row of TX lanes) over a chunk of planes
+//    along axis 2;
+//  - step A (t -> t+1) runs plane by plane on the tile and one halo row on
+//    either side (TY + 2 rows), with the one-step kernel's data movement:
+//    the own column's populations of planes z and z+1 in registers (plane
+//    z+2 in flight), S of the plane staged in LDS for the axis-0 and axis-1
+//    neighbours.  Its post-collision populations are not stored: along
+//    axis 2 they stay in the thread that owns the column (a register carries
+//    the +e2 one to the next plane, the -e2 one completes the plane below),
+//    along axes 0 and 1 they are handed over through LDS.  The two rows
+//    beyond the halo rows send one population each into them (+e1 into the
+//    lower halo row, -e1 into the upper one); the first 2 TX threads load
+//    those rows and run their collision too, the next 2 TX load the rows
+//    beyond them for S only;
+//  - a plane's state at t+1 is complete once step A has passed the plane
+//    above it, and step B (t+1 -> t+2) also needs S(t+1) of the plane
+//    above, so step B runs two planes behind step A, on the tile's own rows,
+//    and pushes its populations to memory as the one-step kernel does;
+//  - per node both steps call collide() of march_common.h in the same
+//    order as a one-step launch would, so the result is that of two single
+//    steps, bit for bit;
+//  - probes: block 0 records time t from the input; the thread that owns a
+//    probe node records time t+1 from the state it assembled; the last
+//    workgroup to finish advances the step counter by two, so graph replays
+//    need no host input.
+// Chunks along axis 2 are extended by two planes of step A either side (the
+// state at t+1 of planes z0-1 and z1 is needed), which is the price of the
+// chunking besides the two halo rows.
+#include "march_common.h"
+
+namespace lbw {
+namespace {
+
+using namespace march;
+
+constexpr int kTileProbes = 16;
+
+template <int TX, int TY>
+struct M2 {
+    static constexpr int NT = TX * (TY + 2);
+    static constexpr int W = TX + 2;          // LDS row: one pad entry either side of the axis-0 row
+    static constexpr int SROWS = TY + 6;      // S(t) of extended rows -2 .. TY+3
+    static constexpr int XROWS = TY + 4;      // populations handed over by rows -1 .. TY+2
+    static constexpr int S1ROWS = TY + 2;     // S(t+1) of rows 0 .. TY+1
+};
+
+template <int TX, int TY>
+struct M2Lds {
+    float S[2][M2<TX, TY>::SROWS * M2<TX, TY>::W + 1];     // + a sink slot
+    float X[4][M2<TX, TY>::XROWS * M2<TX, TY>::W + 1];
+    float S1[2][M2<TX, TY>::S1ROWS * M2<TX, TY>::W + 1];
+    float4 Elo[8][M2<TX, TY>::W + 1];                      // coefficient rows, slot = plane & 7
+    float4 Ehi[8][M2<TX, TY>::W + 1];
+    float B[2][2][TY * TX + 1];                            // step B: +-e0 populations along the row (2 planes)
+    int pnode[kTileProbes], px[kTileProbes], py[kTileProbes], pz[kTileProbes];
+    int pcount;
+};
+
+__device__ inline int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+template <int TX, int TY>
+__device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& pr, int64_t t, const MarchPlan& plan,
+                                            int tile, const float* __restrict__ fin, float* __restrict__ fout,
+                                            M2Lds<TX, TY>& L) {
+    using C = M2<TX, TY>;
+    constexpr int W = C::W;
+    const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
+    const uint32_t N = (uint32_t)g.N;
+    const uint32_t plane = (uint32_t)n0 * (uint32_t)n1;
+    const float c2 = g.c2, two_w0 = g.two_w0, damp = g.damp;
+    const int lx = (int)(threadIdx.x % (unsigned)TX), ly = (int)(threadIdx.x / (unsigned)TX);
+    const int ty = tile % plan.nty, chunk = tile / plan.nty;
+    const int y0 = ty * TY, z0 = chunk * plan.lz;
+    if (z0 >= n2) return;  // uniform per block
+    const int z1 = min(z0 + plan.lz, n2);
+    const int hgt = min(TY, n1 - y0);
+    const bool perz = g.bc_lo[2] == LBW_BC_PERIODIC, pery = g.bc_lo[1] == LBW_BC_PERIODIC;
+    // step A runs on march planes [za0, za1); the march runs on [za0, z1 + 2)
+    const int za0 = perz ? z0 - 2 : max(z0 - 2, 0);
+    const int za1 = perz ? z1 + 2 : min(z1 + 2, n2);
+
+    // this thread's node: x = lx on the row of extended row ly (tile row ly - 1)
+    const int yr = y0 - 1 + ly;
+    const bool ypres = pery || (yr >= 0 && yr < n1);
+    const int ya = pery ? wrap(yr, n1) : yr;
+    const bool actA = lx < n0 && ypres;
+    const bool actB = actA && ly >= 1 && ly <= hgt;
+    Links kl{};
+    kl.jx_p = link_coord(lx, +1, n0, g.bc_lo[0], g.bc_hi[0], &kl.wx_p);
+    kl.jx_m = link_coord(lx, -1, n0, g.bc_lo[0], g.bc_hi[0], &kl.wx_m);
+    kl.jy_p = ypres ? link_coord(ya, +1, n1, g.bc_lo[1], g.bc_hi[1], &kl.wy_p) : -1;
+    kl.jy_m = ypres ? link_coord(ya, -1, n1, g.bc_lo[1], g.bc_hi[1], &kl.wy_m) : -1;
+    const uint32_t col4 = actA ? ((uint32_t)lx + (uint32_t)n0 * (uint32_t)ya) * 4u : 0u;
+
+    // ring loader: rows -1 and TY+2 (loaded and collided: they send +e1 / -e1
+    // into the halo rows), rows -2 and TY+3 (loaded for S only)
+    const int rid = (int)(threadIdx.x / (unsigned)TX);  // 0..3 for loaders
+    const int re = rid == 0 ? -1 : rid == 1 ? TY + 2 : rid == 2 ? -2 : TY + 3;
+    const int ryr = y0 - 1 + re;
+    const bool rpres = rid < 4 && (pery || (ryr >= 0 && ryr < n1));
+    const int rya = pery ? wrap(ryr, n1) : ryr;
+    const bool ring_on = rpres && lx < n0;
+    const bool ring_col = ring_on && rid < 2;  // collides its ring node
+    Links kr{};
+    kr.jx_p = kl.jx_p;
+    kr.jx_m = kl.jx_m;
+    kr.wx_p = kl.wx_p;
+    kr.wx_m = kl.wx_m;
+    kr.jy_p = rpres ? link_coord(rya, +1, n1, g.bc_lo[1], g.bc_hi[1], &kr.wy_p) : -1;
+    kr.jy_m = rpres ? link_coord(rya, -1, n1, g.bc_lo[1], g.bc_hi[1], &kr.wy_m) : -1;
+    const uint32_t ring4 = ring_on ? ((uint32_t)lx + (uint32_t)n0 * (uint32_t)rya) * 4u : 0u;
+    const int my_s = (ly + 2) * W + lx + 1;                  // own S(t) slot
+    const int ring_s = ring_on ? (re + 2) * W + lx + 1 : C::SROWS * W;
+    const int sinkS = C::SROWS * W;
+
+    // coefficient-row loader: thread t < n0 stages entry t (x = -1 and n0 are
+    // beyond the walls and never read)
+    const bool erow_on = (int)threadIdx.x < n0;
+
+    const uint32_t N4 = N * 4u, plane4 = plane * 4u;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(fin, 7u * N4);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(fout, 7u * N4);
+    const __amdgpu_buffer_rsrc_t rtab = make_rsrc(g.tab, (uint32_t)n0 * (uint32_t)n2 * 32u);
+
+    // march plane -> real plane (-1 beyond a wall); in the plane loop the
+    // real plane is carried along and offset by a few planes without a
+    // division (rstep)
+    auto rplane = [&](int z) -> int { return perz ? wrap(z, n2) : (z >= 0 && z < n2 ? z : -1); };
+    auto rstep = [&](int zr, int z, int d) -> int {
+        if (!perz) return z + d >= 0 && z + d < n2 ? z + d : -1;
+        int v = zr + d;
+        while (v >= n2) v -= n2;
+        while (v < 0) v += n2;
+        return v;
+    };
+    auto erow_r = [&](int zr, float4& lo, float4& hi) {
+        const bool on = erow_on && zr >= 0;
+        const uint32_t off = on ? (uint32_t)(threadIdx.x + n0 * zr) * 32u : kOff;
+        lo = bld4(rtab, off);
+        hi = bld4(rtab, on ? off + 16u : kOff);
+    };
+    auto stage_erow = [&](int z, const float4& lo, const float4& hi) {
+        if (erow_on) {
+            L.Elo[z & 7][threadIdx.x + 1] = lo;
+            L.Ehi[z & 7][threadIdx.x + 1] = hi;
+        }
+    };
+
+    // tile probes: those on the tile's own rows and planes record time t+1
+    if (threadIdx.x == 0) L.pcount = 0;
+    __syncthreads();
+    if (t + 1 >= 0 && t + 1 < pr.t_max) {
+        for (int p = threadIdx.x; p < pr.n; p += blockDim.x) {
+            const int64_t node = pr.nodes[p];
+            const int i0 = (int)(node % n0);
+            const int i1 = (int)((node / n0) % n1);
+            const int i2 = (int)(node / ((int64_t)n0 * n1));
+            if (i1 >= y0 && i1 < y0 + hgt && i2 >= z0 && i2 < z1) {
+                const int slot = atomicAdd(&L.pcount, 1);
+                if (slot < kTileProbes) {
+                    L.pnode[slot] = p;
+                    L.px[slot] = i0;
+                    L.py[slot] = i1;
+                    L.pz[slot] = i2;
+                }
+            }
+        }
+    }
+
+    // ---- prologue: planes za0 - 1 (S only) and za0 (own column, ring,
+    // staged S); coefficient rows za0 - 1 .. za0 + 1; in flight into the
+    // loop: own column of plane za0 + 1, ring of plane za0 + 1, coefficient
+    // row za0 + 2 ----
+    float fA[7], fB[7], fC[7], rA[7], rB[7], rC[7], tmp[7];
+    float Sm = 0.f, Sc = 0.f, Sp = 0.f;
+    {
+        const int zm = rplane(za0 - 1), zc = rplane(za0);
+        bload7(rin, N4, actA && zm >= 0, col4 + (uint32_t)zm * plane4, tmp);
+        bload7(rin, N4, actA && zc >= 0, col4 + (uint32_t)zc * plane4, fA);
+        bload7(rin, N4, ring_on && zc >= 0, ring4 + (uint32_t)zc * plane4, rA);
+        float4 a0, b0, a1, b1, a2, b2;
+        erow_r(rplane(za0 - 1), a0, b0);
+        erow_r(rplane(za0), a1, b1);
+        erow_r(rplane(za0 + 1), a2, b2);
+        Sm = sum7(tmp);
+        Sc = sum7(fA);
+        stage_erow(za0 - 1, a0, b0);
+        stage_erow(za0, a1, b1);
+        stage_erow(za0 + 1, a2, b2);
+        L.S[0][actA ? my_s : sinkS] = Sc;
+        L.S[0][ring_s] = sum7(rA);
+    }
+    {
+        // plane za1 itself is loaded where it exists: S(t) of the plane above
+        // the last step-A plane
+        const int zn = rplane(za0 + 1);
+        const bool on = za0 + 1 <= za1 && zn >= 0;
+        bload7(rin, N4, actA && on, col4 + (uint32_t)zn * plane4, fB);
+        bload7(rin, N4, ring_on && on, ring4 + (uint32_t)zn * plane4, rB);
+    }
+    float4 e_nlo, e_nhi;
+    erow_r(rplane(za0 + 2), e_nlo, e_nhi);
+    int zrr = rplane(za0);  // real plane of the march plane (carried along)
+
+    // state at t+1 of planes z-2 (for step B), z-1 and z (being assembled),
+    // and S(t+1) of planes z-3 .. z-1
+    float fa[7], fb[7], fz[7];
+#pragma unroll
+    for (int l = 0; l < 7; ++l) fa[l] = fb[l] = fz[l] = 0.f;
+    float carry5 = 0.f;
+    float S1a = 0.f, S1b = 0.f, S1c = 0.f;  // S(t+1) of planes z-3, z-2, z-1
+    // step B's +-e0 stores of the previous plane, done after the next barrier
+    // (the row hand-over through LDS then needs no barrier of its own)
+    bool pend = false;
+    uint32_t pend_nb = 0;
+    float pend_v1w = 0.f, pend_v2w = 0.f;
+    int pend_slot = 0;
+    const int bo = (ly - 1) * TX + lx;  // step B hand-over slot
+    auto flush_pending = [&]() {
+        const float* B0 = L.B[pend_slot][0];
+        const float* B1 = L.B[pend_slot][1];
+        const float from_left = B0[lx > 0 && actB ? bo - 1 : TY * TX];
+        const float from_right = B1[lx < TX - 1 && actB ? bo + 1 : TY * TX];
+        const float in1 = kl.jx_m >= 0 ? from_left : pend_v2w;
+        const float in2 = kl.jx_p >= 0 ? from_right : pend_v1w;
+        bst(rout, pend && actB ? 1u * N4 + pend_nb : kOff, in1);
+        bst(rout, pend && actB ? 2u * N4 + pend_nb : kOff, in2);
+    };
+
+    const int zend = z1 + 2;
+    // One march plane z: step A on z (when z < za1), completion of plane z-1,
+    // step B on z-2 (when it is one of the tile's planes).  f2 receives the
+    // state at t+1 of plane z, f1 holds plane z-1, f0 plane z-2; fc / fnx /
+    // fnn hold the own column at time t of planes z, z+1 and (loading) z+2,
+    // rc / rn / rnn the ring's; the caller rotates all of them by argument
+    // order (period three), so no register is copied.
+    auto march_plane = [&](float (&f0)[7], float (&f1)[7], float (&f2)[7], float (&fc)[7], float (&fnx)[7],
+                           float (&fnn)[7], float (&rc)[7], float (&rn)[7], float (&rnn)[7], int z) {
+        const int sb = (z - za0) & 1;
+        const bool doA = z < za1;
+        const int zr = zrr;
+        // loads consumed later: own column and ring of plane z+2 (S(t) of
+        // plane z+1 comes from fnx), coefficient row z+3
+        {
+            const int zq = rstep(zr, z, 2);
+            const bool on = z + 2 <= za1 && zq >= 0;
+            bload7(rin, N4, actA && on, col4 + (uint32_t)zq * plane4, fnn);
+            bload7(rin, N4, ring_on && on, ring4 + (uint32_t)zq * plane4, rnn);
+        }
+        float4 e3lo, e3hi;
+        erow_r(rstep(zr, z, 3), e3lo, e3hi);
+        Sp = sum7(fnx);
+        const float Srp = sum7(rn);
+        __syncthreads();  // S(t) of plane z, coefficient rows up to z+2, step B's hand-over visible
+        if (pend) flush_pending();  // uniform
+        pend = false;
+
+        if (doA) {
+            Links k = kl;
+            k.wz_p = k.wz_m = 0;
+            k.jz_p = zr >= 0 ? link_coord(zr, +1, n2, g.bc_lo[2], g.bc_hi[2], &k.wz_p) : -1;
+            k.jz_m = zr >= 0 ? link_coord(zr, -1, n2, g.bc_lo[2], g.bc_hi[2], &k.wz_m) : -1;
+            const float* Ls = L.S[sb];
+            const float4 e_lo = L.Elo[z & 7][lx + 1], e_hi = L.Ehi[z & 7][lx + 1];
+            const float4 enp = L.Elo[z & 7][lx + 2], enm = L.Elo[z & 7][lx];
+            const float4 ezp = L.Elo[(z + 1) & 7][lx + 1];
+            const float4 ezm = L.Elo[(z - 1) & 7][lx + 1];
+            float fs[7];
+            collide(fc, Sc, e_lo, e_hi, enp, enm, ezp, make_float2(ezm.y, ezm.z), Ls[my_s + 1], Ls[my_s - 1],
+                    Ls[my_s + W], Ls[my_s - W], Sp, Sm, k, c2, two_w0, fs);
+            const int xo = (ly + 1) * W + lx + 1;  // hand-over slot of row ly
+            L.X[0][xo] = fs[1];
+            L.X[1][xo] = fs[2];
+            L.X[2][xo] = fs[3];
+            L.X[3][xo] = fs[4];
+            // the ring rows -1 and TY+2 (threads of the first 2 TX, whole
+            // waves) send f*_3 (row -1, into row 0) and f*_4 (row TY+2, into
+            // row TY+1): the axis-1 part of their collision
+            if (threadIdx.x < 2 * TX) {
+                const int ri = (re + 2) * W + lx + 1;
+                float rs3, rs4;
+                collide_axis1(rc[3], rc[4], sum7(rc), e_lo.w, Ls[ri + W], Ls[ri - W], kr, c2, rs3, rs4);
+                const int ro = (re + 1) * W + lx + 1;
+                if (rid == 0) L.X[2][ring_col ? ro : C::XROWS * W] = rs3;
+                else L.X[3][ring_col ? ro : C::XROWS * W] = rs4;
+            }
+            __syncthreads();  // handed-over populations visible
+            f2[0] = fs[0];
+            f2[1] = k.jx_m >= 0 ? L.X[0][xo - 1] : bounce(k.wx_m, damp, fs[2], fs[1]);
+            f2[2] = k.jx_p >= 0 ? L.X[1][xo + 1] : bounce(k.wx_p, damp, fs[1], fs[2]);
+            f2[3] = k.jy_m >= 0 ? L.X[2][xo - W] : bounce(k.wy_m, damp, fs[4], fs[3]);
+            f2[4] = k.jy_p >= 0 ? L.X[3][xo + W] : bounce(k.wy_p, damp, fs[3], fs[4]);
+            f2[5] = k.jz_m >= 0 ? carry5 : bounce(k.wz_m, damp, fs[6], fs[5]);
+            f2[6] = k.jz_p >= 0 ? 0.f : bounce(k.wz_p, damp, fs[5], fs[6]);
+            if (k.jz_m >= 0) f1[6] = fs[6];
+            carry5 = fs[5];
+        }
+        // plane z-1 is complete: its S(t+1) for step B's neighbours
+        if (z - 1 >= za0 && z - 1 < za1) {
+            S1c = sum7(f1);
+            L.S1[(z - 1) & 1][actA ? ly * W + lx + 1 : C::S1ROWS * W] = S1c;
+        }
+
+        // step B on plane zb = z - 2
+        const int zb = z - 2;
+        if (zb >= z0 && zb < z1) {
+            const int zbr = rstep(zr, z, -2);
+            Links k = kl;
+            k.wz_p = k.wz_m = 0;
+            k.jz_p = link_coord(zbr, +1, n2, g.bc_lo[2], g.bc_hi[2], &k.wz_p);
+            k.jz_m = link_coord(zbr, -1, n2, g.bc_lo[2], g.bc_hi[2], &k.wz_m);
+            const float* L1 = L.S1[zb & 1];
+            // (threads off the tile's rows read row 1 instead: every index stays in the array)
+            const int s1 = (actB ? ly : 1) * W + lx + 1;
+            const float4 e_lo = L.Elo[zb & 7][lx + 1], e_hi = L.Ehi[zb & 7][lx + 1];
+            const float4 enp = L.Elo[zb & 7][lx + 2], enm = L.Elo[zb & 7][lx];
+            const float4 ezp = L.Elo[(zb + 1) & 7][lx + 1];
+            const float4 ezm = L.Elo[(zb - 1) & 7][lx + 1];
+            float fs[7];
+            collide(f0, S1b, e_lo, e_hi, enp, enm, ezp, make_float2(ezm.y, ezm.z), L1[s1 + 1], L1[s1 - 1],
+                    L1[s1 + W], L1[s1 - W], S1c, S1a, k, c2, two_w0, fs);
+            // probes at t+1 on this plane (the state f0 before step B)
+            if (L.pcount > 0) {
+                const int np = min(L.pcount, kTileProbes);
+                for (int i = 0; i < np; ++i) {
+                    if (actB && L.pz[i] == zbr && L.py[i] == ya && L.px[i] == lx) {
+                        double s = 0.0;
+                        for (int l = 0; l < 7; ++l) s += (double)f0[l];
+                        pr.trace[(t + 1) * pr.n + L.pnode[i]] = s / g.sqrtg[lx + (int64_t)n0 * zbr];
+                    }
+                }
+            }
+            // push: +-e0 along the row through LDS, stored after the next
+            // barrier (aligned stores); the rest to their destinations (or the
+            // wall rules) now
+            pend_slot = zb & 1;
+            L.B[pend_slot][0][actB ? bo : TY * TX] = fs[1];
+            L.B[pend_slot][1][actB ? bo : TY * TX] = fs[2];
+            const uint32_t nb = col4 + (uint32_t)zbr * plane4;
+            pend = true;
+            pend_nb = nb;
+            pend_v1w = bounce(k.wx_p, damp, fs[1], fs[2]);  // +e0 at the far wall, returned as -e0
+            pend_v2w = bounce(k.wx_m, damp, fs[2], fs[1]);  // -e0 at the near wall, returned as +e0
+            const uint32_t o3 = k.jy_p >= 0 ? 3u * N4 + nb + (uint32_t)((k.jy_p - ya) * n0) * 4u : 4u * N4 + nb;
+            const uint32_t o4 = k.jy_m >= 0 ? 4u * N4 + nb + (uint32_t)((k.jy_m - ya) * n0) * 4u : 3u * N4 + nb;
+            const uint32_t o5 = k.jz_p >= 0 ? 5u * N4 + col4 + (uint32_t)k.jz_p * plane4 : 6u * N4 + nb;
+            const uint32_t o6 = k.jz_m >= 0 ? 6u * N4 + col4 + (uint32_t)k.jz_m * plane4 : 5u * N4 + nb;
+            const float v3 = k.jy_p >= 0 ? fs[3] : bounce(k.wy_p, damp, fs[3], fs[4]);
+            const float v4 = k.jy_m >= 0 ? fs[4] : bounce(k.wy_m, damp, fs[4], fs[3]);
+            const float v5 = k.jz_p >= 0 ? fs[5] : bounce(k.wz_p, damp, fs[5], fs[6]);
+            const float v6 = k.jz_m >= 0 ? fs[6] : bounce(k.wz_m, damp, fs[6], fs[5]);
+            bst(rout, actB ? nb : kOff, fs[0]);
+            bst(rout, actB ? o3 : kOff, v3);
+            bst(rout, actB ? o4 : kOff, v4);
+            bst(rout, actB ? o5 : kOff, v5);
+            bst(rout, actB ? o6 : kOff, v6);
+        }
+        S1a = S1b;
+        S1b = S1c;
+
+        // stage S(t) of plane z+1 and the coefficient row z+2 for the next
+        // march plane (their slots were last read two barriers ago)
+        if (z + 1 < zend) {
+            L.S[sb ^ 1][actA ? my_s : sinkS] = Sp;
+            L.S[sb ^ 1][ring_s] = Srp;
+            stage_erow(z + 2, e_nlo, e_nhi);
+        }
+        e_nlo = e3lo;
+        e_nhi = e3hi;
+        Sm = Sc;
+        Sc = Sp;
+        zrr = rstep(zr, z, 1);
+    };
+    for (int z = za0;;) {
+        if (z >= zend) break;
+        march_plane(fa, fb, fz, fA, fB, fC, rA, rB, rC, z);
+        if (++z >= zend) break;
+        march_plane(fb, fz, fa, fB, fC, fA, rB, rC, rA, z);
+        if (++z >= zend) break;
+        march_plane(fz, fa, fb, fC, fA, fB, rC, rA, rB, z);
+        ++z;
+    }
+    __syncthreads();  // the last plane's hand-over visible
+    if (pend) flush_pending();
+    __syncthreads();  // LDS reuse by the next tile
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__(TX * (TY + 2)) void step_march2_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
+                                                                    const float* __restrict__ fin,
+                                                                    float* __restrict__ fout) {
+    __shared__ M2Lds<TX, TY> L;
+    const int64_t t = *(volatile const int64_t*)pr.tcount;
+    if (blockIdx.x == 0 && t >= 0 && t < pr.t_max) {
+        // time t from the input
+        for (int p = threadIdx.x; p < pr.n; p += blockDim.x) {
+            const int64_t node = pr.nodes[p];
+            double s = 0.0;
+            for (int l = 0; l < 7; ++l) s += (double)fin[l * g.N + node];
+            pr.trace[t * pr.n + p] = s / g.sqrtg[sg_index(g, node)];
+        }
+    }
+    const int xcd = blockIdx.x % kXcds;
+    const int per_xcd_blocks = gridDim.x / kXcds;
+    const int t_begin = (int)(plan.tiles * xcd / kXcds);
+    const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
+    for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
+        march2_tile<TX, TY>(g, pr, t, plan, tile, fin, fout, L);
+    // the last workgroup to finish advances the step counter by two (every
+    // workgroup read it before counting itself done)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(pr.tdone, 1u);
+        if (prev == gridDim.x - 1) {
+            *(volatile int64_t*)pr.tcount = t + 2;
+            *(volatile unsigned*)pr.tdone = 0u;
+            __threadfence();
+        }
+    }
+}
+
+template <int TX, int TY>
+int blocks_per_cu2() {
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march2_kernel<TX, TY>, TX * (TY + 2), 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+}  // namespace
+
+bool march2_shape_ok(int tx, int ty) {
+    // 768 threads: the shapes whose registers fit three waves per SIMD
+    // without spilling (taller tiles spill at four)
+    return (tx == 96 && ty == 6) || (tx == 128 && ty == 4);
+}
+
+bool march2_fits(const GeomDev& g, int tx) {
+    return g.dim == 3 && !g.sg_node && g.n0 <= tx && g.bc_lo[0] != LBW_BC_PERIODIC;
+}
+
+int march2_tile_probes() { return kTileProbes; }
+
+int march2_blocks_per_cu(int tx, int ty) {
+    return tx == 96 ? blocks_per_cu2<96, 6>() : blocks_per_cu2<128, 4>();
+}
+
+MarchPlan make_march2_plan(const GeomDev& g, int tx, int ty, int lz, int blocks) {
+    MarchPlan p{};
+    p.tx = tx;
+    p.ty = ty;
+    p.lz = lz < 1 ? 1 : lz;
+    p.ntx = 1;
+    p.nty = (g.n1 + ty - 1) / ty;
+    p.nchunks = (g.n2 + p.lz - 1) / p.lz;
+    p.tiles = (int64_t)p.nty * p.nchunks;
+    int b = blocks < kXcds ? kXcds : blocks;
+    b = (b / kXcds) * kXcds;
+    const int64_t cap = ((p.tiles + kXcds - 1) / kXcds) * kXcds;
+    if (b > cap) b = (int)cap;
+    if (b < kXcds) b = kXcds;
+    p.blocks = b;
+    return p;
+}
+
+hipError_t launch_step_march2(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
+                              float* fout, hipStream_t st) {
+    if (!march2_shape_ok(plan.tx, plan.ty) || !march2_fits(g, plan.tx) || !pr.tdone) return hipErrorInvalidValue;
+    const dim3 grid(plan.blocks), block(plan.tx * (plan.ty + 2));
+    if (plan.tx == 96)
+        hipLaunchKernelGGL((step_march2_kernel<96, 6>), grid, block, 0, st, g, pr, plan, fin, fout);
+    else
+        hipLaunchKernelGGL((step_march2_kernel<128, 4>), grid, block, 0, st, g, pr, plan, fin, fout);
+    return hipGetLastError();
+}
+
+}  // namespace lbw
