@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & % HBM peak; shape-spectra/sec batched+surrogate vs plain LBM"
 HBM_PEAK_GBS = 8000.0
 # committed counter summaries per configuration, and the kernel sources they cover
-_MARCH = ("step_march.hip", "step.hip", "lbw_internal.h")
+_MARCH = ("step_march.hip", "march_common.h", "step.hip", "lbw_internal.h")
 TRAFFIC = {1: ("traffic_step_cylinder_128x128x256.txt", _MARCH),
            2: ("traffic_step_horn_128x128x512.txt", _MARCH),
            3: ("traffic_step_torus_96x256x512.txt", _MARCH),
