@@ -4,8 +4,14 @@ against the FP64 reference with BF16 rounding at the same points.
 Bars: the two sides round the same values to BF16, but a value computed in
 FP32 on the device and in FP64 on the host can land on different sides of a
 BF16 rounding boundary (probability ~1e-5 per value, error 2^-8 relative
-when it happens), so tensors are compared in relative L2 (outputs 2e-3,
-gradients 1e-2) and the loss to 1e-4.
+when it happens).  The 3-256-256-256-10 network at batch 512 holds about
+1.3e5 BF16 activations per layer, so a few such flips per layer are
+expected, each moving the relative L2 of a tensor by about
+2^-8 / sqrt(1.3e5) ~ 1e-5; measured over three seeds: outputs <= 7.4e-5,
+gradients <= 3.2e-4 (a bias row).  Tensors are therefore held to relative
+L2 2e-4 (outputs) and 1e-3 (gradients), the loss to 1e-4; a 1 %-scale
+mistake (a transposed stride, a dropped bias row sum) fails them tenfold.
+The small networks have no flips at these seeds and agree to ~3e-8.
 """
 import sys
 
@@ -49,7 +55,7 @@ def test_forward_matches_reference(widths, B):
     say("mlp forward", widths, B)
     y = net.forward(x).cpu().numpy()
     yr, _ = ref.forward(p, widths, x)
-    assert rel(y, yr) <= 2e-3
+    assert rel(y, yr) <= 2e-4
     assert np.array_equal(net.get_params(), p.astype(np.float32))
 
 
@@ -65,9 +71,9 @@ def test_gradients_match_reference(widths, B):
     for l in range(len(widths) - 1):
         nW = widths[l] * widths[l + 1]
         nb = widths[l + 1]
-        assert rel(g[off: off + nW], gr[off: off + nW]) <= 1e-2, ("W", l)
+        assert rel(g[off: off + nW], gr[off: off + nW]) <= 1e-3, ("W", l)
         off += nW
-        assert rel(g[off: off + nb], gr[off: off + nb]) <= 1e-2, ("b", l)
+        assert rel(g[off: off + nb], gr[off: off + nb]) <= 1e-3, ("b", l)
         off += nb
 
 
