@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -92,6 +93,119 @@ def measured_rate(train: int = 512, candidates: int = 10000, plain: int = 4, jud
     return out
 
 
+EXTRA_PEAK_GAP = 0.6
+
+
+def extra_peak(f: np.ndarray) -> np.ndarray:
+    """Rows of spectra (ascending peaks) with two consecutive peaks closer
+    than EXTRA_PEAK_GAP times the row's median gap (False where a peak is
+    missing)."""
+    out = np.zeros(len(f), dtype=bool)
+    ok = np.isfinite(f).all(axis=1)
+    if ok.any():
+        g = np.diff(f[ok], axis=1)
+        out[ok] = g.min(axis=1) < EXTRA_PEAK_GAP * np.median(g, axis=1)
+    return out
+
+
+def multi_family(f: np.ndarray, profiles) -> np.ndarray:
+    """Rows of ten-peak spectra (physical units) that are not one longitudinal
+    family: the second axisymmetric radial family of the bell, from
+    j'_{0,2} / (2 pi R(1)), starts below the last peak, or extra_peak()."""
+    from scipy.special import jn_zeros
+    p = np.asarray(profiles, dtype=np.float64).reshape(-1, 3)
+    cut2 = jn_zeros(1, 2)[1] / (2.0 * math.pi * (p[:, 0] + p[:, 1] * np.exp(p[:, 2])))
+    return (cut2 < np.nan_to_num(f[:, -1], nan=0.0)) | extra_peak(f)
+
+
+def census(rule: str = "stated", n: int = 512, steps: int | None = None, growth: float = 2.0, log=None) -> dict:
+    """Which horns of the configured profile box and grids the scheme serves:
+    classify() of workloads.stated_ensemble(n, rule)."""
+    import workloads as W
+    return dict(classify(W.stated_ensemble(n, rule), steps, growth, log), rule=rule)
+
+
+def classify(members, steps: int | None = None, growth: float = 2.0, log=None) -> dict:
+    """Every horn simulated by the batched LBM for the configured steps and
+    put in the first class that applies:
+      unstable      the population 2-norm grows more than `growth`-fold over
+                    the run, or turns non-finite;
+      unresolved    fewer than ten spectral peaks found;
+      multi-family  the ten peaks are not one longitudinal family: the
+                    second axisymmetric radial family of the bell, which
+                    starts at j'_{0,2} / (2 pi R(1)) in physical units, lies
+                    below the tenth peak (the probes sit on the nodal circle
+                    of the first radial family only), or two consecutive
+                    peaks lie closer than EXTRA_PEAK_GAP times the median
+                    gap (the longitudinal ladder is evenly spaced, about 0.5
+                    apart, so a closer pair holds a peak of another family);
+      usable        the rest.
+    Returns the class counts and the per-horn figures."""
+    import torch
+    from scipy.special import jn_zeros
+
+    import workloads as W
+    from paper_1705_01801_amd import Batch, Geometry
+    from paper_1705_01801_amd import surrogate as S
+
+    steps = steps or W.ENSEMBLE_STEPS
+    K = W.ENSEMBLE_MODES
+    members = S.with_wave_speeds(members)
+    n = len(members)
+    geoms = [m["geom"] for m in members]
+    prof = np.array([m["profile"] for m in members])
+    grid = np.array([g["n"][:3] for g in geoms], dtype=np.int64)
+    mrr = np.zeros(n)
+    for i, g in enumerate(geoms):
+        geo = Geometry(g)
+        mrr[i] = geo.table()[0].max()           # largest Mhat^rr of the horn
+        geo.close()
+    b = Batch(geoms, [W.horn_pulse(g) for g in geoms], [m["probes"] for m in members], t_max=steps)
+    b.autotune(reps=5)
+
+    def norms():
+        return np.array([float(torch.linalg.vector_norm(b.populations(h).double())) for h in range(n)])
+
+    n0 = norms()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        m = min(5000, steps - done)
+        b.step(m)
+        done += m
+        if log:
+            torch.cuda.synchronize()
+            log("classify %d horns: %d/%d steps, %.1f s" % (n, done, steps, time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    seconds = time.perf_counter() - t0
+    n1 = norms()
+    fq, _ = b.modes(K)
+    b.close()
+    f = S.physical(fq, geoms)
+    a, bb, k = prof.T
+    R1 = a + bb * np.exp(k)
+    ratio = np.where(np.isfinite(n1), n1 / n0, np.inf)
+    unstable = ratio > growth
+    unresolved = ~unstable & np.isnan(f).any(axis=1)
+    cut2 = jn_zeros(1, 2)[1] / (2.0 * math.pi * R1)
+    multi = ~unstable & ~unresolved & multi_family(f, prof)
+    usable = ~(unstable | unresolved | multi)
+    nodes = int(grid.prod(axis=1).sum())
+    counts = {"unstable": int(unstable.sum()), "unresolved": int(unresolved.sum()),
+              "multi_family": int(multi.sum()), "usable": int(usable.sum())}
+    return {"horns": n, "steps": steps, "nodes": nodes, "seconds": seconds,
+            "glups": nodes * steps / seconds / 1e9, "growth_limit": growth, "counts": counts,
+            "fractions": {key: v / n for key, v in counts.items()},
+            "per_horn": {"profile": prof.tolist(), "grid": grid.tolist(),
+                         "c": [g["c"] for g in geoms], "h_ref": [g["h_ref"] for g in geoms],
+                         "mhat_rr_max": mrr.tolist(), "norm_ratio": ratio.tolist(), "freq": f.tolist(),
+                         "bell_radius": R1.tolist(), "bell_slope": (bb * k * np.exp(k)).tolist(),
+                         "second_radial_cut_on": cut2.tolist(),
+                         "class": np.select([unstable, unresolved, multi], ["unstable", "unresolved", "multi-family"],
+                                            "usable").tolist()}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=512)
@@ -107,6 +221,13 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--save-npz", default=None, help="write training spectra (and traces) here")
     ap.add_argument("--train-only", action="store_true", help="stop after the batched training ensemble")
+    ap.add_argument("--box", choices=("narrow", "stated"), default="narrow",
+                    help="narrow: the training box HORN_RANGES; stated: the configured box STATED_RANGES, "
+                         "candidates outside workloads.served() excluded")
+    ap.add_argument("--keep-multi-family", action="store_true",
+                    help="with --box stated: train on every training horn, one family or not")
+    ap.add_argument("--census", choices=("stated", "isotropic"), default=None,
+                    help="classify the horns of the configured profile box and grids instead (see census)")
     args = ap.parse_args(argv)
 
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -121,12 +242,22 @@ def main(argv=None):
         print("[study] " + msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
+    if args.census:
+        rep = census(args.census, n=args.train, steps=args.steps, log=log)
+        log("census (%s): %s" % (args.census, json.dumps(rep["counts"])))
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(json.dumps(rep) + "\n")
+        print(json.dumps({k: v for k, v in rep.items() if k != "per_horn"}), flush=True)
+        return
     steps = args.steps or W.ENSEMBLE_STEPS
     K = W.ENSEMBLE_MODES
-    rep = {"steps": steps, "modes": K, "threshold": args.threshold}
+    rep = {"steps": steps, "modes": K, "threshold": args.threshold, "box": args.box}
+    stated = args.box == "stated"
+    ranges = W.STATED_RANGES if stated else W.HORN_RANGES
 
     # 1. batched training ensemble
-    members = S.with_wave_speeds(W.ensemble(args.train, stream=0))
+    members = S.with_wave_speeds(W.served_ensemble(args.train) if stated else W.ensemble(args.train, stream=0))
     p0s = [W.horn_pulse(m["geom"]) for m in members]
     nodes = int(sum(np.prod(m["geom"]["n"]) for m in members))
     log("training ensemble: %d horns, %.1f M nodes" % (len(members), nodes / 1e6))
@@ -154,19 +285,36 @@ def main(argv=None):
                     if same.any() else None}
     log("plain: %.1f s for %d horns" % (t_plain, ns))
 
-    # 3. surrogate ensemble
+    # 3. surrogate ensemble.  On the configured box, training horns whose
+    # peaks are not one family (a peak split where a radial-family mode
+    # crosses a longitudinal one) are left out unless --keep-multi-family.
     prof = np.array([m["profile"] for m in members])
-    sur = S.Surrogate([W.HORN_RANGES[k] for k in ("a", "b", "k")], members=4,
+    mf = multi_family(f_train, prof)
+    rep["training_multi_family"] = int(mf.sum())
+    f_fit = f_train
+    if stated and not args.keep_multi_family:
+        f_fit = np.where(mf[:, None], np.nan, f_train)
+        log("training: %d of %d horns left out (not one family)" % (mf.sum(), len(mf)))
+    sur = S.Surrogate([ranges[k] for k in ("a", "b", "k")], members=4,
                       widths=(3, args.hidden, args.hidden, args.hidden, K))
     t0 = time.perf_counter()
-    losses = sur.fit(prof, f_train, steps=args.train_steps, log=log, bootstrap=not args.no_bootstrap)
+    losses = sur.fit(prof, f_fit, steps=args.train_steps, log=log, bootstrap=not args.no_bootstrap)
     torch.cuda.synchronize()
     rep["training"] = {"seconds": time.perf_counter() - t0, "final_losses": losses, "widths": sur.widths,
                        "adam_steps": args.train_steps, "bootstrap": not args.no_bootstrap,
-                       "valid_targets": int(np.isfinite(f_train).sum())}
+                       "valid_targets": int(np.isfinite(f_fit).sum())}
 
-    # 4. inference on candidates
-    cprof, cgrid = W.candidates(args.candidates)
+    # 4. inference on candidates (of the configured box: those outside the
+    # served region are excluded, neither predicted nor simulated)
+    if stated:
+        cprof, cgrid = W.stated_candidates(args.candidates)
+        keep = W.served(cprof)
+        rep["excluded"] = {"candidates": len(cprof), "outside_served": int((~keep).sum()),
+                           "fraction": float((~keep).mean()), "rule": "R(1) > %.4f" % W.SERVED_BELL_RADIUS}
+        cprof, cgrid = cprof[keep], cgrid[keep]
+        log("excluded %d of %d candidates outside the served region" % ((~keep).sum(), len(keep)))
+    else:
+        cprof, cgrid = W.candidates(args.candidates)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     mean, spread, _ = sur.predict(cprof)

@@ -63,3 +63,19 @@ def test_surrogate_gains_over_lbm_within_one_percent():
     assert r["judge"]["modes"] >= 200
     assert r["judge"]["rel_err_max"] <= 0.01
     assert r["surrogate_plus_fallback"] > r["batched"] > r["plain"]
+
+
+def test_served_region_holds_no_growing_horn():
+    """The configured profile box (a <= 0.2, b <= 0.05, k <= 5) is mostly
+    outside what the scheme serves: horns with a wide, steep bell grow (the
+    flare limit of the scheme) or have peaks of several families.  The
+    served region, R(1) <= SERVED_BELL_RADIUS, is drawn here afresh (48
+    horns, their own seed stream, 30,000 steps): none may grow more than
+    twofold, and at least 44 must give one longitudinal family."""
+    import workloads as W
+    from paper_1705_01801_amd import surrogate_study
+    say("served region: 48 horns x 30000 steps")
+    r = surrogate_study.classify(W.served_ensemble(48, stream=1), log=say)
+    say("  classes", json.dumps(r["counts"]), "largest norm ratio %.3f" % max(r["per_horn"]["norm_ratio"]))
+    assert r["counts"]["unstable"] == 0 and r["counts"]["unresolved"] == 0
+    assert r["counts"]["usable"] >= 44

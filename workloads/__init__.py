@@ -315,6 +315,12 @@ PROBE_RADIUS = 0.63
 
 def horn_member(profile, draw, c=None) -> dict:
     """One ensemble horn: geometry on horn_grid(profile, *draw) with h_ref =
+    h_z (c to be set by the caller when None); see horn_on_grid."""
+    return horn_on_grid(profile, horn_grid(profile, *(int(v) for v in draw)), c)
+
+
+def horn_on_grid(profile, n, c=None) -> dict:
+    """A horn of the profile on the (n_r, n_theta, n_z) grid n with h_ref =
     h_z (c to be set by the caller when None) and a pressure-release bell
     (P = 0 at z = 1), the plane pulse of horn_pulse, and 8 probes at theta = 0
     spread along z on the ring nearest to r = PROBE_RADIUS: the nodal circle
@@ -327,7 +333,7 @@ def horn_member(profile, draw, c=None) -> dict:
     wave speed (by 4 % between c = 0.25 and 0.45 on the same grid), so the
     spectrum would depend on a numerical parameter; with P = 0 it does not."""
     a, b, k = (float(v) for v in profile)
-    n = horn_grid(profile, *(int(v) for v in draw))
+    n = tuple(int(v) for v in n)
     geom = trumpet_horn(c=0.0 if c is None else c, a=a, b=b, k=k, n=n)
     geom["h_ref"] = 1.0 / n[2]
     geom["bc_hi"] = ("bounceback", "periodic", "fixed")
@@ -353,6 +359,73 @@ def ensemble(n: int = 512, stream: int = 0):
     prof = horn_profiles(n, rng)
     grids = horn_grids(n, rng)
     return [horn_member(p, g) for p, g in zip(prof, grids)]
+
+
+# The profile box and grids of the batched ensemble before the narrowing
+# above, for measuring which part of them the scheme can serve: R(1) reaches
+# 7.6 and R'(1) 37 here.
+STATED_RANGES = {"a": (0.05, 0.2), "b": (0.005, 0.05), "k": (1.0, 5.0)}
+STATED_GRIDS = {"nr": tuple(range(32, 97, 8)), "nt": (32, 40, 48, 56, 64), "nz": tuple(range(64, 257, 16))}
+
+
+def stated_ensemble(n: int = 512, rule: str = "stated", stream: int = 0):
+    """n horns with profiles uniform on STATED_RANGES and (n_r, n_theta,
+    n_z) drawn from STATED_GRIDS.  rule "stated" simulates each on its drawn
+    grid; rule "isotropic" keeps the drawn (n_theta, n_z) and sets n_r (and
+    raises n_z) by horn_grid, as the training ensemble does.  Both rules see
+    the same profiles and draws."""
+    rng = np.random.default_rng(SEED_BASE + 4 + 7919 * stream + 15485863)
+    prof = np.stack([rng.uniform(*STATED_RANGES[key], size=n) for key in ("a", "b", "k")], axis=1)
+    grid = np.stack([rng.choice(np.array(STATED_GRIDS[key]), size=n) for key in ("nr", "nt", "nz")],
+                    axis=1).astype(np.int64)
+    if rule == "stated":
+        return [horn_on_grid(p, g) for p, g in zip(prof, grid)]
+    if rule == "isotropic":
+        return [horn_member(p, g[1:]) for p, g in zip(prof, grid)]
+    raise ValueError(rule)
+
+
+# Bell radius bound of the part of the configured box that the ensemble
+# serves.  Above R(1) = j'_{0,2} / (2 pi 4.75) = 0.2351 (j'_{0,2} = 7.0156,
+# the second zero of J1) the second axisymmetric radial family of the bell
+# starts below 4.75, the tenth resonance of a closed-open tube of unit
+# length, so the first ten peaks cannot be one longitudinal family; that is a
+# ceiling.  The bound used is the measured one below it: simulating 512
+# horns of the box on the ensemble's grids (30,000 steps), every horn with
+# R(1) <= 0.2 grew less than 1.26-fold and gave one family, while 8 of the 31
+# with R(1) in (0.2, 0.2351] already showed a peak of another family.
+BELL_RADIUS_CEILING = 7.015586669815619 / (2.0 * math.pi * 4.75)
+SERVED_BELL_RADIUS = 0.2
+
+
+def served(profiles) -> np.ndarray:
+    """Per profile (a, b, k): R(1) = a + b e^k <= SERVED_BELL_RADIUS."""
+    p = np.asarray(profiles, dtype=np.float64).reshape(-1, 3)
+    return p[:, 0] + p[:, 1] * np.exp(p[:, 2]) <= SERVED_BELL_RADIUS
+
+
+def served_ensemble(n: int = 512, stream: int = 0):
+    """n horns of the configured box (profiles uniform on STATED_RANGES,
+    (n_theta, n_z) from STATED_GRIDS, n_r by horn_grid) whose profiles pass
+    served(), drawn by rejection."""
+    rng = np.random.default_rng(SEED_BASE + 4 + 7919 * stream + 32452843)
+    out = []
+    while len(out) < n:
+        prof = np.stack([rng.uniform(*STATED_RANGES[key], size=4096) for key in ("a", "b", "k")], axis=1)
+        grid = np.stack([rng.choice(np.array(STATED_GRIDS[key]), size=4096) for key in ("nt", "nz")], axis=1)
+        for i in np.flatnonzero(served(prof))[: n - len(out)]:
+            out.append(horn_member(prof[i], grid[i]))
+    return out
+
+
+def stated_candidates(n: int = 100000):
+    """Candidate profiles uniform on STATED_RANGES and the (n_theta, n_z)
+    draw from STATED_GRIDS each would be simulated with (n_r by
+    horn_grid)."""
+    rng = np.random.default_rng(SEED_BASE + 4 + 104729 + 49979687)
+    prof = np.stack([rng.uniform(*STATED_RANGES[key], size=n) for key in ("a", "b", "k")], axis=1)
+    grid = np.stack([rng.choice(np.array(STATED_GRIDS[key]), size=n) for key in ("nt", "nz")], axis=1)
+    return prof, grid.astype(np.int64)
 
 
 def candidates(n: int = 100000):
