@@ -1,6 +1,8 @@
 // C-ABI for batches of D3Q7 geometries advanced by one launch per step.
+#include <algorithm>
 #include <cmath>
 #include <map>
+#include <utility>
 #include <vector>
 
 #include "host_util.h"
@@ -16,6 +18,9 @@ struct lbw_batch {
     float* tab32 = nullptr;
     std::vector<lbw::BatchItem> items;
     lbw::BatchItem* d_items = nullptr;
+    std::vector<int32_t> tile_item;     // geometry of every tile of the current plan
+    int32_t* d_tile_item = nullptr;
+    int64_t tile_item_cap = 0;          // entries allocated at d_tile_item
     int tx = 32, lz = 16, blocks = 8;
     int section_nt = 0;  // > 0: whole-row tiles of this many threads (tx unused)
     int64_t tiles = 0;
@@ -43,12 +48,15 @@ struct lbw_batch {
 
 namespace {
 
+constexpr int kXcdsBatch = 8;  // the batch kernel cuts its tile list into one range per XCD
+
 void release(lbw_batch* b) {
     for (auto& gx : b->graph)
         if (gx) (void)hipGraphExecDestroy(gx);
     (void)hipFree(b->tab64);
     (void)hipFree(b->tab32);
     (void)hipFree(b->d_items);
+    (void)hipFree(b->d_tile_item);
     (void)hipFree(b->d_nodes);
     (void)hipFree(b->d_tcount);
     (void)hipFree(b->d_scratch_count);
@@ -100,8 +108,25 @@ hipError_t build_items(lbw_batch* b) {
     }
     b->tiles = tile;
     b->plan_version += 1;
-    hipError_t e = hipMemcpyAsync(b->d_items, b->items.data(), sizeof(lbw::BatchItem) * b->n, hipMemcpyHostToDevice,
-                                  b->stream);
+    // tile -> geometry table (the kernel reads one entry per tile instead of
+    // searching the geometry list)
+    b->tile_item.resize((size_t)tile);
+    for (int h = 0; h < b->n; ++h)
+        std::fill(b->tile_item.begin() + b->items[h].tile_begin,
+                  b->tile_item.begin() + b->items[h].tile_begin + b->items[h].tiles, (int32_t)h);
+    hipError_t e = hipSuccess;
+    if (tile > b->tile_item_cap) {
+        (void)hipFree(b->d_tile_item);
+        b->d_tile_item = nullptr;
+        b->tile_item_cap = 0;
+        e = hipMalloc((void**)&b->d_tile_item, sizeof(int32_t) * (size_t)tile);
+        if (e != hipSuccess) return e;
+        b->tile_item_cap = tile;
+    }
+    e = hipMemcpyAsync(b->d_items, b->items.data(), sizeof(lbw::BatchItem) * b->n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && tile > 0)
+        e = hipMemcpyAsync(b->d_tile_item, b->tile_item.data(), sizeof(int32_t) * (size_t)tile,
+                           hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     return e;
 }
@@ -123,7 +148,8 @@ hipError_t launch_batch(lbw_batch* b, const lbw::BatchProbeArgs& bp, const float
         const hipError_t e = lbw::launch_sources(b->d_src, b->n_src, b->d_tcount, const_cast<float*>(fin), st);
         if (e != hipSuccess) return e;
     }
-    return lbw::launch_step_batch(b->d_items, b->n, b->tiles, b->tx, b->section_nt, b->blocks, bp, fin, fout, st);
+    return lbw::launch_step_batch(b->d_items, b->d_tile_item, b->n, b->tiles, b->tx, b->section_nt, b->blocks, bp,
+                                  fin, fout, st);
 }
 
 hipError_t build_graph(lbw_batch* b, int from) {
@@ -198,6 +224,58 @@ double lane_slots(const lbw_batch* b, int tile_x) {
                  (double)d.n[2];
     }
     return slots;
+}
+
+// Tiles of the whole batch for TX-wide tiles (tile_x > 0) or whole-row
+// tiles of nt threads (tile_x = 0) and chunks of lz planes.
+int64_t batch_tiles(const lbw_batch* b, int tile_x, int nt, int lz) {
+    int64_t tiles = 0;
+    for (int h = 0; h < b->n; ++h) {
+        const lbw_geometry_desc& d = b->d[h];
+        int64_t per_plane;
+        if (tile_x == 0) {
+            const int r = lbw::batch_row_tile(d.n[0], d.n[1], nt);
+            if (r == 0) return 0;
+            per_plane = (d.n[1] + r - 1) / r;
+        } else {
+            const int ty = 256 / tile_x;
+            per_plane = (int64_t)((d.n[0] + tile_x - 1) / tile_x) * ((d.n[1] + ty - 1) / ty);
+        }
+        tiles += per_plane * ((d.n[2] + lz - 1) / lz);
+    }
+    return tiles;
+}
+
+// Chunk lengths the tuner times: 4, 8, 16, 32, 64 and the four others with
+// the lowest modelled cost, rounds x (lz + 2) plane steps.  rounds is the
+// most tiles one of `blocks` persistent workgroups walks (the tiles are cut
+// into one contiguous range per XCD, shared by that XCD's blocks) and the 2
+// planes stand for a tile's prologue.  On small batches the fixed lengths can
+// leave a last round in which most workgroups idle (476 pipes of 20 x 5 x
+// 100 with chunks of 16: 3332 tiles on 1536 workgroups, 3 rounds where 2.2
+// would do); the model finds the lengths that avoid it.
+std::vector<int> lz_candidates(const lbw_batch* b, int tile_x, int nt, int blocks) {
+    std::vector<int> out = {4, 8, 16, 32, 64};
+    const int64_t per_xcd = blocks / kXcdsBatch > 0 ? blocks / kXcdsBatch : 1;
+    std::vector<std::pair<double, int>> cost;
+    for (int lz = 4; lz <= 64; ++lz) {
+        const int64_t tiles = batch_tiles(b, tile_x, nt, lz);
+        if (tiles == 0) return out;
+        const int64_t per_range = (tiles + kXcdsBatch - 1) / kXcdsBatch;
+        const int64_t rounds = (per_range + per_xcd - 1) / per_xcd;
+        cost.emplace_back((double)rounds * (lz + 2), lz);
+    }
+    std::stable_sort(cost.begin(), cost.end(),
+                     [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first < y.first; });
+    int added = 0;
+    for (const auto& c : cost) {
+        if (added == 4) break;
+        if (std::find(out.begin(), out.end(), c.second) == out.end()) {
+            out.push_back(c.second);
+            ++added;
+        }
+    }
+    return out;
 }
 
 int set_config(lbw_batch* b, int tile_x, int chunk_z, int blocks) {
@@ -425,7 +503,7 @@ int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us) {
         if (err != hipSuccess) break;
         if (tx == 0 && row_nt == 0) continue;
         const int bpc = tx == 0 ? lbw::batch_section_blocks_per_cu(row_nt) : lbw::batch_blocks_per_cu(tx);
-        for (int lz : {4, 8, 16, 32, 64}) {
+        for (int lz : lz_candidates(b, tx, row_nt, cus * bpc)) {
             for (int mult : {1, 2}) {
                 if (set_config(b, tx, lz, mult * cus * bpc) != LBW_OK) {
                     err = hipErrorUnknown;

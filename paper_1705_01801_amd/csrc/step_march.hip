@@ -394,7 +394,8 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
 // cross-section when it fits), for geometries whose rows a TX-wide tile
 // would split or leave mostly idle; TX = NT then only sizes the LDS arrays.
 template <int TX, int NT, bool SECTION>
-__global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restrict__ items, int n_items,
+__global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restrict__ items,
+                                                         const int32_t* __restrict__ tile_item, int n_items,
                                                          int64_t tiles_total, BatchProbeArgs bp,
                                                          const float* __restrict__ fin, float* __restrict__ fout) {
     __shared__ float sS[2][lds_s<TX, NT, SECTION>()];
@@ -422,18 +423,9 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restr
     const int per_xcd_blocks = gridDim.x / kXcds;
     const int64_t t_begin = tiles_total * xcd / kXcds;
     const int64_t t_end = tiles_total * (xcd + 1) / kXcds;
-    int h = 0;
     for (int64_t tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks) {
-        // geometry owning this tile (tiles ascend, so search upward from the last one)
-        if (!(tile >= items[h].tile_begin && tile < items[h].tile_begin + items[h].tiles)) {
-            int lo = 0, hi = n_items - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) / 2;
-                if (items[mid].tile_begin <= tile) lo = mid;
-                else hi = mid - 1;
-            }
-            h = lo;
-        }
+        const int h = tile_item[tile];  // geometry owning this tile
+        if (h < 0 || h >= n_items) continue;  // inconsistent table: skip
         const BatchItem& it = items[h];
         if (tile < it.tile_begin || tile >= it.tile_begin + it.tiles) continue;  // inconsistent table: skip
         TileGeom tg;
@@ -560,26 +552,27 @@ int batch_section_blocks_per_cu(int nt) {
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-hipError_t launch_step_batch(const BatchItem* items, int n_items, int64_t tiles_total, int tx, int section_nt,
-                             int blocks, const BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st) {
+hipError_t launch_step_batch(const BatchItem* items, const int32_t* tile_item, int n_items, int64_t tiles_total,
+                             int tx, int section_nt, int blocks, const BatchProbeArgs& bp, const float* fin,
+                             float* fout, hipStream_t st) {
     if (section_nt == 128)
-        hipLaunchKernelGGL((step_batch_kernel<128, 128, true>), dim3(blocks), dim3(128), 0, st, items, n_items,
-                           tiles_total, bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<128, 128, true>), dim3(blocks), dim3(128), 0, st, items, tile_item,
+                           n_items, tiles_total, bp, fin, fout);
     else if (section_nt == 256)
-        hipLaunchKernelGGL((step_batch_kernel<256, 256, true>), dim3(blocks), dim3(256), 0, st, items, n_items,
-                           tiles_total, bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<256, 256, true>), dim3(blocks), dim3(256), 0, st, items, tile_item,
+                           n_items, tiles_total, bp, fin, fout);
     else if (section_nt == 512)
-        hipLaunchKernelGGL((step_batch_kernel<512, 512, true>), dim3(blocks), dim3(512), 0, st, items, n_items,
-                           tiles_total, bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<512, 512, true>), dim3(blocks), dim3(512), 0, st, items, tile_item,
+                           n_items, tiles_total, bp, fin, fout);
     else if (tx == 16)
         hipLaunchKernelGGL((step_batch_kernel<16, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
-                           items, n_items, tiles_total, bp, fin, fout);
+                           items, tile_item, n_items, tiles_total, bp, fin, fout);
     else if (tx == 32)
         hipLaunchKernelGGL((step_batch_kernel<32, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
-                           items, n_items, tiles_total, bp, fin, fout);
+                           items, tile_item, n_items, tiles_total, bp, fin, fout);
     else
         hipLaunchKernelGGL((step_batch_kernel<64, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
-                           items, n_items, tiles_total, bp, fin, fout);
+                           items, tile_item, n_items, tiles_total, bp, fin, fout);
     return hipGetLastError();
 }
 
