@@ -41,8 +41,15 @@ struct lbw_batch {
     size_t mode_work_bytes = 0;
     double* mode_out = nullptr;
     int mode_k = 0;
-    lbw::SourceEntry* d_src = nullptr;  // driven sources, imposed before every step
+    // driven nodes, imposed by the step kernel as it loads them: all
+    // geometries' entries, and per geometry with driven nodes a map from each
+    // node of its driven planes to its entry (or -1); per geometry the count,
+    // the first and last driven plane and the map offset
+    lbw::BatchSource* d_src = nullptr;
+    int32_t* d_src_map = nullptr;
     int n_src = 0;
+    std::vector<int> src_count, src_zlo, src_zhi;
+    std::vector<uint32_t> src_map_off;
     double* d_amp = nullptr;            // response intensities (P)
 };
 
@@ -63,6 +70,7 @@ void release(lbw_batch* b) {
     (void)hipFree(b->mode_work);
     (void)hipFree(b->mode_out);
     (void)hipFree(b->d_src);
+    (void)hipFree(b->d_src_map);
     (void)hipFree(b->d_amp);
     delete b;
 }
@@ -105,6 +113,10 @@ hipError_t build_items(lbw_batch* b) {
         it.sg_off = (uint32_t)(b->tab64_off[h] + 7 * (b->rec_off[h + 1] - b->rec_off[h]));
         it.probe_off = (uint32_t)b->probe_off[h];
         it.n_probes = (int)(b->probe_off[h + 1] - b->probe_off[h]);
+        it.src_count = b->src_count[h];
+        it.src_zlo = b->src_zlo[h];
+        it.src_zhi = b->src_zhi[h];
+        it.src_map = b->src_map_off[h];
     }
     b->tiles = tile;
     b->plan_version += 1;
@@ -140,14 +152,15 @@ lbw::BatchProbeArgs probe_args(lbw_batch* b, bool record) {
     bp.tcount = record ? b->d_tcount : b->d_scratch_count;
     bp.sqrtg = b->tab64;
     bp.tab4 = reinterpret_cast<const float4*>(b->tab32);
+    bp.src = b->n_src > 0 ? b->d_src : nullptr;
+    bp.src_map = b->n_src > 0 ? b->d_src_map : nullptr;
     return bp;
 }
 
-hipError_t launch_batch(lbw_batch* b, const lbw::BatchProbeArgs& bp, const float* fin, float* fout, hipStream_t st) {
-    if (b->n_src > 0 && bp.tcount == b->d_tcount) {
-        const hipError_t e = lbw::launch_sources(b->d_src, b->n_src, b->d_tcount, const_cast<float*>(fin), st);
-        if (e != hipSuccess) return e;
-    }
+// One step.  The counter bank is the step's parity, which is that of the
+// buffer read: b->cur flips with every step, from 0 at step 0.
+hipError_t launch_batch(lbw_batch* b, lbw::BatchProbeArgs bp, const float* fin, float* fout, hipStream_t st) {
+    bp.parity = fin == b->f[1] ? 1 : 0;
     return lbw::launch_step_batch(b->d_items, b->d_tile_item, b->n, b->tiles, b->tx, b->section_nt, b->blocks, bp,
                                   fin, fout, st);
 }
@@ -359,16 +372,20 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
     b->t_max = b->P > 0 ? t_max : 0;
     b->trace = trace;
     b->items.resize(n);
+    b->src_map_off.assign(n, 0);
+    b->src_count.assign(n, 0);
+    b->src_zlo.assign(n, 0);
+    b->src_zhi.assign(n, 0);
     hipError_t e = hipMalloc(&b->tab64, sizeof(double) * b->tab64_off[n]);
     if (e == hipSuccess) e = hipMalloc(&b->tab32, sizeof(float) * lbw::kTabF32 * b->rec_off[n]);
     if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(lbw::BatchItem) * n);
-    if (e == hipSuccess) e = hipMalloc(&b->d_tcount, sizeof(int64_t) * n);
-    if (e == hipSuccess) e = hipMalloc(&b->d_scratch_count, sizeof(int64_t) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_tcount, sizeof(int64_t) * 2 * n);
+    if (e == hipSuccess) e = hipMalloc(&b->d_scratch_count, sizeof(int64_t) * 2 * n);
     if (e == hipSuccess && b->P > 0) e = hipMalloc(&b->d_nodes, sizeof(int64_t) * b->P);
     if (e == hipSuccess && b->P > 0)
         e = hipMemcpyAsync(b->d_nodes, probes, sizeof(int64_t) * b->P, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(b->d_tcount, 0, sizeof(int64_t) * n, b->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(b->d_scratch_count, 0, sizeof(int64_t) * n, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_tcount, 0, sizeof(int64_t) * 2 * n, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_scratch_count, 0, sizeof(int64_t) * 2 * n, b->stream);
     for (int h = 0; h < n && e == hipSuccess; ++h) {
         const int64_t E = b->rec_off[h + 1] - b->rec_off[h];
         double* t64 = b->tab64 + b->tab64_off[h];
@@ -635,36 +652,78 @@ int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* ge
                 "lbw_batch_set_sources");
     }
     HIP_TRY(hipStreamSynchronize(b->stream), "lbw_batch_set_sources");
-    std::vector<lbw::SourceEntry> host((size_t)n);
-    for (int i = 0; i < n; ++i) {
+    // sorted by (geometry, node); a node listed twice in one geometry is an error
+    std::vector<int> order((size_t)n);
+    for (int i = 0; i < n; ++i) order[(size_t)i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        return geom[x] != geom[y] ? geom[x] < geom[y] : nodes[x] < nodes[y];
+    });
+    for (int j = 1; j < n; ++j) {
+        const int x = order[(size_t)j - 1], y = order[(size_t)j];
+        if (geom[x] == geom[y] && nodes[x] == nodes[y])
+            return fail(LBW_EINVAL, "sources %d and %d drive the same node", x, y);
+    }
+    std::vector<lbw::BatchSource> host((size_t)n);
+    std::vector<int> count((size_t)b->n, 0), zlo((size_t)b->n, 0), zhi((size_t)b->n, 0);
+    for (int j = 0; j < n; ++j) {
+        const int i = order[(size_t)j];
         const int h = geom[i];
         const lbw_geometry_desc& d = b->d[h];
         const int64_t n0 = d.n[0], plane = n0 * d.n[1];
-        const int64_t N = b->node_off[h + 1] - b->node_off[h];
         const double sq = sg[h][(size_t)(nodes[i] % n0 + n0 * (nodes[i] / plane))];
         const double c2 = lbw::lattice_c2(d);
-        lbw::SourceEntry e{};
-        e.f_off = (uint64_t)(7 * b->node_off[h] + nodes[i]);
-        e.N = (uint32_t)N;
-        e.q = 7;
-        e.counter = h;
+        lbw::BatchSource e{};
+        e.node = (uint32_t)nodes[i];
         e.kind = kind ? kind[i] : 0;
         e.a0 = e.kind ? amplitude[i] * 0.5 * sq : amplitude[i] * (1.0 - 3.0 * c2) * sq;
         e.a1 = e.kind ? 0.5 * c2 : amplitude[i] * 0.5 * c2 * sq;
         e.omega = omega[i];
-        host[(size_t)i] = e;
+        host[(size_t)j] = e;
+        const int z = (int)(nodes[i] / plane);
+        if (count[(size_t)h] == 0) zlo[(size_t)h] = z;
+        zhi[(size_t)h] = z;
+        count[(size_t)h] += 1;
+    }
+    // node -> entry maps over each geometry's driven planes
+    std::vector<uint32_t> map_off((size_t)b->n, 0);
+    int64_t map_len = 0;
+    for (int h = 0; h < b->n; ++h) {
+        if (count[(size_t)h] == 0) continue;
+        const int64_t plane = (int64_t)b->d[h].n[0] * b->d[h].n[1];
+        if (map_len > 0x7fffffffLL) return fail(LBW_EINVAL, "driven planes too large for the source map");
+        map_off[(size_t)h] = (uint32_t)map_len;
+        map_len += plane * (zhi[(size_t)h] - zlo[(size_t)h] + 1);
+    }
+    if (map_len > 0x7fffffffLL) return fail(LBW_EINVAL, "driven planes too large for the source map");
+    std::vector<int32_t> map((size_t)map_len, -1);
+    for (int j = 0; j < n; ++j) {
+        const int i = order[(size_t)j];
+        const int h = geom[i];
+        const int64_t plane = (int64_t)b->d[h].n[0] * b->d[h].n[1];
+        map[(size_t)(map_off[(size_t)h] + nodes[i] - plane * zlo[(size_t)h])] = j;
     }
     drop_graphs(b);
     (void)hipFree(b->d_src);
+    (void)hipFree(b->d_src_map);
     b->d_src = nullptr;
+    b->d_src_map = nullptr;
     b->n_src = 0;
     if (n > 0) {
-        HIP_TRY(hipMalloc((void**)&b->d_src, sizeof(lbw::SourceEntry) * n), "lbw_batch_set_sources");
-        HIP_TRY(hipMemcpyAsync(b->d_src, host.data(), sizeof(lbw::SourceEntry) * n, hipMemcpyHostToDevice, b->stream),
+        HIP_TRY(hipMalloc((void**)&b->d_src, sizeof(lbw::BatchSource) * n), "lbw_batch_set_sources");
+        HIP_TRY(hipMalloc((void**)&b->d_src_map, sizeof(int32_t) * (size_t)map_len), "lbw_batch_set_sources");
+        HIP_TRY(hipMemcpyAsync(b->d_src, host.data(), sizeof(lbw::BatchSource) * n, hipMemcpyHostToDevice, b->stream),
                 "lbw_batch_set_sources");
-        HIP_TRY(hipStreamSynchronize(b->stream), "lbw_batch_set_sources");
+        HIP_TRY(hipMemcpyAsync(b->d_src_map, map.data(), sizeof(int32_t) * (size_t)map_len, hipMemcpyHostToDevice,
+                               b->stream),
+                "lbw_batch_set_sources");
         b->n_src = n;
     }
+    b->src_count = count;
+    b->src_zlo = zlo;
+    b->src_zhi = zhi;
+    b->src_map_off = map_off;
+    // the tile list carries the ranges (and waits for the copy above)
+    HIP_TRY(build_items(b), "lbw_batch_set_sources");
     return LBW_OK;
 }
 

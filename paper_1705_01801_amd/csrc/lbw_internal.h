@@ -130,15 +130,37 @@ struct BatchItem {
     uint32_t sg_off;     // first double in the batch sqrt(g) array
     uint32_t probe_off;  // first probe (global numbering; trace column)
     int n_probes;
+    int src_count;             // driven nodes of this geometry (0: none)
+    int src_zlo, src_zhi;      // planes (axis 2) of the first and last driven node
+    uint32_t src_map;          // first entry of this geometry's map in BatchProbeArgs::src_map
+};
+// One driven node of a batch geometry (Sec. IV.A / IV.C sources), imposed
+// by the step kernel on the populations it loads: kind 0 pressure (a0 =
+// amplitude w_0 sqrt(g), a1 = amplitude w sqrt(g)), kind 1 + a flux along
+// axis a (a0 = amplitude sqrt(g) / 2, a1 = w); drive_node has the rules.
+struct BatchSource {
+    uint32_t node;   // node index within its geometry
+    int32_t kind;
+    double a0, a1, omega;
 };
 struct BatchProbeArgs {
     const int64_t* nodes;  // device, all probes, node index within its geometry
     double* trace;         // device, t_max rows of `stride` doubles
     int64_t stride;        // total probes (trace row length)
     int64_t t_max;
-    int64_t* tcount;       // device, one step counter per geometry
+    // device, two banks of one step counter per geometry: a launch reads
+    // bank `parity` (the time of its sources and trace row) and its probe
+    // blocks write time + 1 into the other bank, so no block of a launch
+    // reads a counter that another block of it changes
+    int64_t* tcount;
+    int parity;
     const double* sqrtg;   // device, batch sqrt(g) array
     const float4* tab4;    // device, batch float table (2 float4 per record)
+    const BatchSource* src;  // device, driven nodes of all geometries (NULL: none)
+    // device, per geometry with driven nodes: for every node of planes
+    // src_zlo .. src_zhi (plane-major, as the populations) its entry in src,
+    // or -1
+    const int32_t* src_map;
 };
 int batch_blocks_per_cu(int tx);
 // Rows per whole-row tile of nt threads (128, 256 or 512) for an n0 x n1

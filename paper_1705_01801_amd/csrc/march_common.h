@@ -53,6 +53,39 @@ __device__ inline void bload7(__amdgpu_buffer_rsrc_t r, uint32_t N4, bool on, ui
     for (int l = 0; l < 7; ++l) v[l] = bld(r, base + (uint32_t)l * N4);
 }
 
+// Driven node at time t (the sources of Sec. IV.A and IV.C): v holds the
+// node's Q populations as loaded and receives the imposed ones.  With
+// s = sin(omega t):
+//   kind 0 (pressure, at rest): v_0 = a0 s, v_l = a1 s;
+//   kind 1 + a (flux along axis a, S = sum_l v_l kept, summed in double):
+//   v_0 = (1 - (Q - 1) a1) S, v_l = a1 S plus or minus a0 s on the two links
+//   of axis a and a1 S on the others.
+// Every kernel that imposes a source calls this, so a driven node gets the
+// same bits whichever kernel imposes it.
+template <int Q>
+__device__ inline void drive_node(int kind, double a0, double a1, double omega, int64_t t, float (&v)[Q]) {
+#pragma clang fp contract(off)
+    const double s = sin(omega * (double)t);
+    if (kind == 0) {
+        v[0] = (float)(a0 * s);
+        const float u = (float)(a1 * s);
+#pragma unroll
+        for (int l = 1; l < Q; ++l) v[l] = u;
+        return;
+    }
+    double S = 0.0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) S += (double)v[l];
+    const double h = a0 * s;
+    v[0] = (float)((1.0 - (Q - 1) * a1) * S);
+#pragma unroll
+    for (int l = 1; l < Q; ++l) {
+        double val = a1 * S;
+        if ((l - 1) / 2 == kind - 1) val += (l & 1) ? h : -h;
+        v[l] = (float)val;
+    }
+}
+
 // value beyond a wall: mirrored, odd for fixed walls
 __device__ inline float ghost(int wall, float v) { return wall == LBW_BC_FIXED ? -v : v; }
 

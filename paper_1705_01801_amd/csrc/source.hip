@@ -3,41 +3,32 @@
 // function of time, and the largest pressure seen at a probe once the driven
 // field is steady, which the paper's frequency sweeps plot against the drive
 // frequency).
-#include "lbw_internal.h"
+#include "march_common.h"
 
 namespace lbw {
 namespace {
 
-// One thread per source node, v = sin(omega t) with t read from the node's
-// step counter.  Pressure (kind 0): the populations are put at rest at the
-// pressure amplitude v (a0, a1 hold amplitude w_0 sqrt(g) and amplitude
-// w sqrt(g)).  Flux along axis a (kind 1 + a): the node keeps its zeroth
-// moment S and takes the equilibrium whose first moment is sqrt(g) times
-// amplitude v along a, f_l = w_l S plus or minus a0 v on the two links of
-// axis a (a0 = amplitude sqrt(g) / 2, a1 = w, w_0 = 1 - (q - 1) w).
+// One thread per source node, imposed at the time read from the node's step
+// counter by drive_node (pressure kind 0, flux along axis a kind 1 + a; a0,
+// a1 as in SourceEntry).
+template <int Q>
+__device__ void drive_entry(const SourceEntry& s, int64_t t, float* __restrict__ p) {
+    float v[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) v[l] = p[(uint64_t)l * s.N];
+    march::drive_node<Q>(s.kind, s.a0, s.a1, s.omega, t, v);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) p[(uint64_t)l * s.N] = v[l];
+}
+
 __global__ void source_kernel(const SourceEntry* __restrict__ src, int n, const int64_t* __restrict__ counters,
                               float* __restrict__ f) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const SourceEntry s = src[i];
     const int64_t t = counters[s.counter];
-    const double v = sin(s.omega * (double)t);
-    float* p = f + s.f_off;
-    if (s.kind == 0) {
-        p[0] = (float)(s.a0 * v);
-        const float u = (float)(s.a1 * v);
-        for (int l = 1; l < s.q; ++l) p[(uint64_t)l * s.N] = u;
-        return;
-    }
-    double S = 0.0;
-    for (int l = 0; l < s.q; ++l) S += (double)p[(uint64_t)l * s.N];
-    const double h = s.a0 * v;
-    p[0] = (float)((1.0 - (s.q - 1) * s.a1) * S);
-    for (int l = 1; l < s.q; ++l) {
-        double val = s.a1 * S;
-        if ((l - 1) / 2 == s.kind - 1) val += (l & 1) ? h : -h;
-        p[(uint64_t)l * s.N] = (float)val;
-    }
+    if (s.q == 5) drive_entry<5>(s, t, f + s.f_off);
+    else drive_entry<7>(s, t, f + s.f_off);
 }
 
 // NaN-propagating maximum of |x|

@@ -49,7 +49,32 @@ struct TileGeom {
     const float4* tab4;
     int ntx, nty, lz;
     int rtx, rty;  // tile width and height when they are run-time values
+    // driven nodes of the geometry (batch tiles): src_count of them on planes
+    // src_zlo .. src_zhi, imposed at time src_t; src_map holds, for each node
+    // of those planes (plane-major), its entry in src or -1
+    const BatchSource* src;
+    const int32_t* src_map;
+    int src_count, src_zlo, src_zhi;
+    int64_t src_t;
 };
+
+// Imposes the driven value on populations v of the node in column `col` of
+// plane z, loaded by this lane (on), when that node is driven.  The plane
+// test is uniform, so tiles and planes without driven nodes skip it; a
+// driven plane costs one map load per lane.
+template <bool SRC>
+__device__ __forceinline__ void drive_loaded(const TileGeom& g, int z, bool on, uint32_t col, float (&v)[7]) {
+    if constexpr (SRC) {
+        if (g.src_count > 0 && z >= g.src_zlo && z <= g.src_zhi) {
+            const uint32_t plane = (uint32_t)g.n0 * (uint32_t)g.n1;
+            const int hit = on ? g.src_map[(uint32_t)(z - g.src_zlo) * plane + col] : -1;
+            if (hit >= 0) {
+                const BatchSource e = g.src[hit];
+                drive_node<7>(e.kind, e.a0, e.a1, e.omega, g.src_t, v);
+            }
+        }
+    }
+}
 
 // LDS floats per S slot: the tile plus its one-node ring (and a sink slot).
 // With a run-time tile of at most NT columns the ring-padded tile and every
@@ -79,8 +104,10 @@ __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* 
 // [z0, z0 + lz).  fin/fout point at the geometry's own population block.
 // RT: the tile is g.rtx x g.rty columns instead (at most NT of them, with
 // 2 (rtx + rty) <= NT ring loaders and rtx + 2 <= NT row loaders, checked by
-// the host); TX = NT then only sizes the LDS arrays.
-template <int TX, int NT, bool ROW, bool RT = false, bool NTS = false>
+// the host); TX = NT then only sizes the LDS arrays.  SRC: driven nodes
+// (g.src) are imposed on every population set as it is loaded (own column,
+// ring), before any use, as if imposed in memory before the step.
+template <int TX, int NT, bool ROW, bool RT = false, bool NTS = false, bool SRC = false>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
                                            float* __restrict__ fout, float (&sS)[2][lds_s<TX, NT, RT>()],
                                            float4 (&sElo)[3][TX + 3], float4 (&sEhi)[3][TX + 3]) {
@@ -190,6 +217,9 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             const float4 b1 = bld4(rtab, e1_on ? (uint32_t)(erow_x + n0 * zp0) * 32u + 16u : kOff);
             float rz[7];
             bload7(rin, N4, ring_on, ring4 + (uint32_t)z0 * plane4, rz);
+            drive_loaded<SRC>(g, zm0, m_on, col, tmp);
+            drive_loaded<SRC>(g, z0, active, col, fc);
+            drive_loaded<SRC>(g, z0, ring_on, ring_col, rz);
             Sm = sum7(tmp);
             em = make_float2(e.y, e.z);
             Sc = sum7(fc);
@@ -247,6 +277,9 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             e2[1] = bld4(rtab, e3_on ? eoff + 16u : kOff);
             bload7(rin, N4, active && zq >= 0, col4 + (uint32_t)zq * plane4, fnn);
             bload7(rin, N4, ring_on && more2, ring4 + (uint32_t)zq * plane4, r2);
+            // plane z+1 (own column; ring below) as loaded one step ago:
+            // driven nodes imposed before their first use (fnx becomes fc)
+            drive_loaded<SRC>(g, jz_p, active && jz_p >= 0, col, fnx);
             Sp = sum7(fnx);  // S of plane z+1 (zeros when there is none: then unused)
             __syncthreads();
 
@@ -330,6 +363,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             em = make_float2(cM02, cM22);
 
             if (more) {
+                drive_loaded<SRC>(g, jz_p, ring_on, ring_col, r1);
                 // disabled lanes write the sink slot past the end (never read)
                 sS[sb ^ 1][ring_on ? ring_lds : kSinkS] = sum7(r1);
                 sElo[es2][e_on ? (int)threadIdx.x : TXr + 2] = e1[0];
@@ -377,6 +411,10 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
     tg.ntx = plan.ntx;
     tg.nty = plan.nty;
     tg.lz = plan.lz;
+    tg.src = nullptr;
+    tg.src_map = nullptr;
+    tg.src_count = tg.src_zlo = tg.src_zhi = 0;
+    tg.src_t = 0;
     const int xcd = blockIdx.x % kXcds;
     const int per_xcd_blocks = gridDim.x / kXcds;
     const int t_begin = (int)(plan.tiles * xcd / kXcds);
@@ -401,23 +439,40 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restr
     __shared__ float sS[2][lds_s<TX, NT, SECTION>()];
     __shared__ float4 sElo[3][TX + 3];
     __shared__ float4 sEhi[3][TX + 3];
+    // this launch's time per geometry: bank `parity`, which no block of it
+    // writes (the probe blocks below write the other bank)
+    const int64_t* __restrict__ t_now = bp.tcount + (size_t)bp.parity * n_items;
+    int64_t* t_next = bp.tcount + (size_t)(bp.parity ^ 1) * n_items;
     for (int h = blockIdx.x; h < n_items; h += gridDim.x) {
         const BatchItem& it = items[h];
-        const int64_t t = *(volatile const int64_t*)(bp.tcount + h);
-        __syncthreads();
+        const int64_t t = t_now[h];
         if (t >= 0 && t < bp.t_max) {
             const float* f = fin + it.f_off;
+            TileGeom pg;
+            pg.n0 = it.n0;
+            pg.n1 = it.n1;
+            pg.src = bp.src;
+            pg.src_map = bp.src_map + it.src_map;
+            pg.src_count = bp.src ? it.src_count : 0;
+            pg.src_zlo = it.src_zlo;
+            pg.src_zhi = it.src_zhi;
+            pg.src_t = t;
             for (int p = threadIdx.x; p < it.n_probes; p += blockDim.x) {
                 const uint32_t node = (uint32_t)bp.nodes[it.probe_off + p];
-                double s = 0.0;
-                for (int l = 0; l < 7; ++l) s += (double)f[l * it.N + node];
+                float v[7];
+                for (int l = 0; l < 7; ++l) v[l] = f[l * it.N + node];
                 const uint32_t i0 = node % (uint32_t)it.n0;
                 const uint32_t i2 = node / ((uint32_t)it.n0 * (uint32_t)it.n1);
+                // a driven probe node reads its driven value (per lane: not
+                // every lane of the block holds a probe)
+                if (pg.src_count > 0 && (int)i2 >= it.src_zlo && (int)i2 <= it.src_zhi)
+                    drive_loaded<true>(pg, (int)i2, true, node - i2 * ((uint32_t)it.n0 * (uint32_t)it.n1), v);
+                double s = 0.0;
+                for (int l = 0; l < 7; ++l) s += (double)v[l];
                 bp.trace[t * bp.stride + it.probe_off + p] = s / bp.sqrtg[it.sg_off + i0 + (uint32_t)it.n0 * i2];
             }
         }
-        __syncthreads();
-        if (threadIdx.x == 0) *(volatile int64_t*)(bp.tcount + h) = t + 1;
+        if (threadIdx.x == 0) t_next[h] = t + 1;
     }
     const int xcd = blockIdx.x % kXcds;
     const int per_xcd_blocks = gridDim.x / kXcds;
@@ -446,8 +501,14 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restr
         tg.lz = it.lz;
         tg.rtx = it.n0;
         tg.rty = it.rty;
-        march_tile<TX, NT, true, SECTION>(tg, (int)(tile - it.tile_begin), fin + it.f_off, fout + it.f_off, sS, sElo,
-                                          sEhi);
+        tg.src = bp.src;
+        tg.src_map = bp.src_map + it.src_map;
+        tg.src_count = bp.src ? it.src_count : 0;  // (a list being replaced leaves no entries)
+        tg.src_zlo = it.src_zlo;
+        tg.src_zhi = it.src_zhi;
+        tg.src_t = t_now[h];
+        march_tile<TX, NT, true, SECTION, false, true>(tg, (int)(tile - it.tile_begin), fin + it.f_off,
+                                                       fout + it.f_off, sS, sElo, sEhi);
     }
 }
 

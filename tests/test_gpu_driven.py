@@ -8,8 +8,10 @@ keeps populations in FP32, so fields and traces are compared with the field
 tolerance of the undriven parity tests (relative L2 1e-5); a probe on a
 source node must read the imposed value to FP32 rounding; a batch of copies
 driven at different frequencies must match each copy driven alone bit for
-bit (same per-node arithmetic, same source kernel), and graph replay must
-match step-by-step launches.
+bit (same per-node arithmetic; the batch step imposes the sources as it
+loads the populations, a single run by a kernel of its own, both through
+the same per-node rule), and graph replay must match step-by-step
+launches.
 """
 import sys
 
@@ -231,6 +233,54 @@ def test_batch_autotune_with_sources_changes_nothing():
     assert np.array_equal(out[0][1], out[1][1])
 
 
+def test_driven_nodes_anywhere_in_the_tile_walk():
+    """Driven nodes are imposed by the batch step on the populations it
+    loads: on a node's own column, on the ring of a neighbouring tile, at a
+    chunk's first and last planes and across the periodic axis-2 seam.  A
+    torus (periodic axes 1 and 2) and a cylinder with driven nodes scattered
+    over every plane, pressure and flux kinds, several on probe nodes, give
+    the same bits as each copy driven alone, on four launch shapes."""
+    rng = np.random.default_rng(17)
+    geoms = [W.torus(scale=16), cyl()[0], W.torus(scale=16)]
+    N = [W.num_nodes(g) for g in geoms]
+    srcs, kinds, omegas, probes = [], [-1, 2, 1], [0.07, 0.05, 0.12], []
+    for g, n in zip(geoms, N):
+        n0, n1, n2 = g["n"]
+        plane = n0 * n1
+        # two nodes on every plane (ring positions included: x = 0, n0 - 1;
+        # y = 0, n1 - 1) and the whole first and last planes' x = 0 column
+        nodes = set()
+        for z in range(n2):
+            nodes.update(int(v) for v in rng.choice(plane, size=2, replace=False) + z * plane)
+        for z in (0, n2 - 1):
+            nodes.update(z * plane + n0 * y for y in range(n1))
+        nodes = np.array(sorted(nodes), dtype=np.int64)
+        srcs.append(nodes)
+        probes.append(np.concatenate([nodes[:3], rng.choice(n, size=3, replace=False)]))
+    T = 120
+    singles = []
+    for h, g in enumerate(geoms):
+        sim = lbw.Simulation(lbw.Geometry(g), np.zeros(N[h]), probes[h], t_max=T)
+        sim.set_sources(srcs[h], 0.6, omegas[h], None if kinds[h] < 0 else kinds[h])
+        sim.step(T)
+        singles.append((sim.populations().cpu().numpy(), sim.probe()))
+    for shape in (None, (16, 5, 0), (32, 3, 0), (64, 32, 0)):
+        b = lbw.Batch(geoms, [np.zeros(n) for n in N], probes, t_max=T)
+        if shape is not None:
+            b.set_step_config(*shape)
+        b.set_graph_block(8)
+        which = np.repeat(np.arange(len(geoms)), [len(x) for x in srcs])
+        b.set_sources(np.concatenate(srcs), which, 0.6, np.repeat(omegas, [len(x) for x in srcs]),
+                      np.repeat(kinds, [len(x) for x in srcs]))
+        say("driven nodes everywhere, launch shape", b.step_config())
+        b.step(T)
+        trace = b.probe()
+        for h in range(len(geoms)):
+            assert np.array_equal(b.populations(h).cpu().numpy(), singles[h][0]), (shape, h)
+            cols = slice(int(b.probe_offsets[h]), int(b.probe_offsets[h + 1]))
+            assert np.array_equal(trace[:, cols], singles[h][1]), (shape, h)
+
+
 def test_source_errors():
     geom, src, probes = cyl()
     N = W.num_nodes(geom)
@@ -262,6 +312,9 @@ def test_source_errors():
         b.set_sources([N], [1], 1.0, 0.1)
     with pytest.raises(lbw.LbwError):
         b.set_sources([0], [1], 1.0, 0.1, flux_axis=3)
+    with pytest.raises(lbw.LbwError):
+        b.set_sources([5, 3, 5], [1, 1, 1], 1.0, 0.1)   # node 5 of geometry 1 twice
+    b.set_sources([5, 5], [0, 1], 1.0, 0.1)             # the same node of two geometries
 
 
 def test_pipe_sweep_point_full_size():
