@@ -99,7 +99,7 @@ def source_nodes(geom, source: str):
 
 
 def run(points: int = 119, steps: int = W.PIPE_STEPS, plain: int = 4, ends=("fixed", "free"),
-        sources=("ring",)) -> dict:
+        sources=("ring",), launch=None) -> dict:
     """The sweep: one batch with a copy of the pipe per (source, open end,
     drive frequency); returns the measurements and the peak comparison
     (response[source][end]).  The points run one at a time repeat the first
@@ -121,7 +121,10 @@ def run(points: int = 119, steps: int = W.PIPE_STEPS, plain: int = 4, ends=("fix
             om.append(np.full(sn.size, w))
             axis.append(np.full(sn.size, ax))
     b.set_sources(np.concatenate(nodes), np.concatenate(which), 1.0, np.concatenate(om), np.concatenate(axis))
-    b.autotune(reps=10)                          # launch shape only: results are the same for every shape
+    if launch:                                   # launch shape only: results are the same for every shape
+        b.set_step_config(*launch)
+    else:
+        b.autotune(reps=10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(T)
@@ -133,7 +136,7 @@ def run(points: int = 119, steps: int = W.PIPE_STEPS, plain: int = 4, ends=("fix
     rep = {"workload": "driven pipe 20x5x100 (r, theta, z), %s source, c %.2f, damping %.2f"
                        % (" and ".join(sources), W.PIPE_C, W.PIPE_DAMP),
            "points": len(geoms), "omegas": [float(omegas[0]), float(omegas[-1]), len(omegas)], "steps": T,
-           "nodes": int(N * len(geoms)),
+           "nodes": int(N * len(geoms)), "launch": list(b.step_config()),
            "batched": {"seconds": t_step + t_amp, "step_seconds": t_step,
                        "points_per_s": len(geoms) / (t_step + t_amp),
                        "glups": N * len(geoms) * T / t_step / 1e9}}
@@ -265,13 +268,17 @@ def main():
     ap.add_argument("--plain", type=int, default=4, help="sweep points also run one at a time")
     ap.add_argument("--sources", default="ring,plate", help="comma-separated: ring, plate")
     ap.add_argument("--torus", action="store_true", help="the torus sweep instead of the pipe's")
+    ap.add_argument("--launch", default=None,
+                    help="tile_x,chunk_z,blocks of the batch step (pipe sweep; default: tuned)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     torch.cuda.set_device(0)
     if args.torus:
         rep = run_torus(args.points or 499, args.steps or W.TORUS_STEPS)
     else:
-        rep = run(args.points or 119, args.steps or W.PIPE_STEPS, args.plain, sources=tuple(args.sources.split(",")))
+        launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+        rep = run(args.points or 119, args.steps or W.PIPE_STEPS, args.plain, sources=tuple(args.sources.split(",")),
+                  launch=launch)
     line = json.dumps(rep)
     print(line, flush=True)
     if args.out:
