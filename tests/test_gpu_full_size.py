@@ -92,12 +92,15 @@ def test_full_torus_configured_run_growth_bounded():
     """The torus configuration is not exactly neutral (its phi axis has
     Mhat^phiphi >> 1 near rho_min with a phi-dependent Christoffel force):
     the oracle on the 4x coarser grid grows 6369-fold over the configured
-    40,000 steps (2.2e-4 per step), and the rate falls about sixfold per
-    refinement, so on the full grid it is expected near 6e-6 per step,
-    about 1.3-fold over the run.  The full 96 x 256 x 512 torus in the
-    benchmark's launch shape runs the 40,000 steps with every probe value
-    finite and the population norm growing by at most 2x (rate <= 1.7e-5
-    per step)."""
+    40,000 steps (2.2e-4 per step).  On the full 96 x 256 x 512 grid, in the
+    benchmark's launch shape, the population norm (every 4000 steps, against
+    the start) falls to 0.70 as the smoothed initial field spreads, stays
+    there to 28,000 steps, then a growing mode takes over: 0.73, 0.88 and
+    1.61 at 32,000, 36,000 and 40,000 steps, about 1.5e-4 per step at the
+    end, close to the coarse grid's rate.  The configured run stays within
+    2x and finite; a run much longer than the configured one would not.
+    Every launch shape gives the same bits, so these figures are those of
+    any tuned run."""
     import torch
     w = W.workload(3)
     steps = w["steps"]
