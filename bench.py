@@ -84,7 +84,7 @@ def cpu_baseline(w, steps):
 INFINITY_CACHE_BYTES = 256 * 2 ** 20
 
 
-def time_config(config, steps, warmup, launch="auto"):
+def time_config(config, steps, warmup, launch="auto", two_step=None):
     """Runs one configuration's full step (probes recorded) after tuning the
     launch shape, timed with HIP events on the stream the library launches
     on; returns the numbers the JSON line reports."""
@@ -106,6 +106,9 @@ def time_config(config, steps, warmup, launch="auto"):
     else:
         g.set_step_config(*(int(v) for v in launch.split(",")))
         tuned_us = float("nan")
+    if two_step and not general:
+        # a fixed two-steps-per-launch shape (for profiling that kernel)
+        g.set_step2_config(*(int(v) for v in two_step.split(",")))
     tile = g.step_config()
     two = g.step2_config() if not general else (0, 0, 0, 0)
     log("bench: %s, %d nodes, warmup %d, steps %d, launch shape %s, two-step %s (tuner %.2f us per step)"
@@ -129,7 +132,9 @@ def time_config(config, steps, warmup, launch="auto"):
     working_set = (2 * 28 + (36 if general else 0)) * N
     out = {"workload": w["name"], "nodes": N, "ms_per_step": round(ms_per_step, 5),
            "mlups": round(N * steps / (ms / 1e3) / 1e6, 1), "achieved_gbs": round(achieved, 1),
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(config),
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           # the committed counters are the one-step kernel's
+           "traffic": None if two[0] else read_traffic(config),
            "residency": "infinity-cache" if working_set <= INFINITY_CACHE_BYTES else "hbm",
            "working_set_bytes": working_set, "probes": int(len(w["probes"])), "c": geom["c"],
            "launch": {"tile_x": tile[0], "tile_y": tile[1], "chunk_z": tile[2], "blocks": tile[3],
@@ -195,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="auto",
                     help="'auto' (autotune) or TILE_X,TILE_Y,CHUNK_Z,BLOCKS to fix the step kernel's launch shape")
+    ap.add_argument("--two-step", default=None,
+                    help="TILE_X,TILE_Y,CHUNK_Z,BLOCKS: run two steps per launch with this shape (headline only)")
     ap.add_argument("--config", type=int, default=3, choices=(1, 2, 3, 4),
                     help="3-D workload of the headline: 3 torus 96x256x512 (the largest single-GPU one), "
                          "1 cylinder 128x128x256, 2 horn 128x128x512, 4 duct 128x128x128 given by its metric")
@@ -215,7 +222,7 @@ def main():
     import torch
 
     torch.cuda.set_device(0)
-    head, w = time_config(args.config, args.steps, args.warmup, args.launch)
+    head, w = time_config(args.config, args.steps, args.warmup, args.launch, args.two_step)
     N = head["nodes"]
     copy_gbs = copy_ceiling(N)
     out = {
