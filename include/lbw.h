@@ -366,10 +366,11 @@ int lbw_batch_get_step_config(lbw_batch_t b, int* tile_x, int* chunk_z, int* blo
 /* Times launch shapes (whole-row tiles when the batch allows them, tile_x
  * 16, 32 and 64; chunk_z 4, 8, 16, 32, 64 and, per tile kind, the four
  * other lengths in 4..64 whose tile count spreads best over the resident
- * workgroups; one or two waves of resident workgroups) with reps steps each
- * on scratch buffers, recording no probes
- * and leaving populations, step count and trace untouched, and keeps the
- * fastest; best_us (may be NULL) receives its microseconds per step.
+ * workgroups; one or two waves of resident workgroups; then the best shape
+ * with the other population store policy: non-temporal stores, the default
+ * when the two population buffers exceed 256 MiB, or cached ones) with reps
+ * steps each on scratch buffers, recording no probes and leaving
+ * populations, step count and trace untouched, and keeps the fastest; best_us (may be NULL) receives its microseconds per step.
  * Synchronises.  Errors: LBW_EINVAL (NULL batch, reps < 1), LBW_ENOMEM,
  * LBW_EDEVICE (the previous shape is kept). */
 int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us);

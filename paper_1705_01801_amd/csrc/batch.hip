@@ -23,6 +23,7 @@ struct lbw_batch {
     int64_t tile_item_cap = 0;          // entries allocated at d_tile_item
     int tx = 32, lz = 16, blocks = 8;
     int section_nt = 0;  // > 0: whole-row tiles of this many threads (tx unused)
+    bool nts = false;    // non-temporal population stores (default: the buffers exceed the Infinity Cache)
     int64_t tiles = 0;
     int plan_version = 0;
     float* f[2] = {nullptr, nullptr};
@@ -161,8 +162,8 @@ lbw::BatchProbeArgs probe_args(lbw_batch* b, bool record) {
 // buffer read: b->cur flips with every step, from 0 at step 0.
 hipError_t launch_batch(lbw_batch* b, lbw::BatchProbeArgs bp, const float* fin, float* fout, hipStream_t st) {
     bp.parity = fin == b->f[1] ? 1 : 0;
-    return lbw::launch_step_batch(b->d_items, b->d_tile_item, b->n, b->tiles, b->tx, b->section_nt, b->blocks, bp,
-                                  fin, fout, st);
+    return lbw::launch_step_batch(b->d_items, b->d_tile_item, b->n, b->tiles, b->tx, b->section_nt, b->blocks, b->nts,
+                                  bp, fin, fout, st);
 }
 
 hipError_t build_graph(lbw_batch* b, int from) {
@@ -369,6 +370,7 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
     }
     b->f[0] = f_a;
     b->f[1] = f_b;
+    b->nts = 2.0 * 28.0 * (double)b->node_off[n] > 256.0 * 1024.0 * 1024.0;
     b->t_max = b->P > 0 ? t_max : 0;
     b->trace = trace;
     b->items.resize(n);
@@ -516,6 +518,22 @@ int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us) {
     float best_ms = 1e30f;
     float* other = b->f[1 - b->cur];
     const int row_nt = section_threads(b);
+    // reps steps of the current configuration on the scratch buffers
+    auto time_current = [&]() -> float {
+        float* bufs[2] = {other, tmp};
+        int w = 0;
+        if (err == hipSuccess) err = launch_batch(b, bp, b->f[b->cur], other, b->stream);
+        for (int r = 0; r < 2 && err == hipSuccess; ++r, w ^= 1)
+            err = launch_batch(b, bp, bufs[w], bufs[w ^ 1], b->stream);
+        if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r, w ^= 1)
+            err = launch_batch(b, bp, bufs[w], bufs[w ^ 1], b->stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
     for (int tx : {0, 16, 32, 64}) {  // 0: whole-row tiles, when every geometry's rows fit them
         if (err != hipSuccess) break;
         if (tx == 0 && row_nt == 0) continue;
@@ -526,18 +544,7 @@ int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us) {
                     err = hipErrorUnknown;
                     break;
                 }
-                float* bufs[2] = {other, tmp};
-                int w = 0;
-                if (err == hipSuccess) err = launch_batch(b, bp, b->f[b->cur], other, b->stream);
-                for (int r = 0; r < 2 && err == hipSuccess; ++r, w ^= 1)
-                    err = launch_batch(b, bp, bufs[w], bufs[w ^ 1], b->stream);
-                if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
-                for (int r = 0; r < reps && err == hipSuccess; ++r, w ^= 1)
-                    err = launch_batch(b, bp, bufs[w], bufs[w ^ 1], b->stream);
-                if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
-                if (err == hipSuccess) err = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                const float ms = time_current();
                 if (err != hipSuccess) break;
                 if (ms < best_ms) {
                     best_ms = ms;
@@ -547,6 +554,15 @@ int lbw_batch_autotune(lbw_batch_t b, int reps, double* best_us) {
                 }
             }
         }
+    }
+    // the best shape with the other store policy (non-temporal stores pay
+    // where the populations do not fit the caches, and cost where they do)
+    if (err == hipSuccess && set_config(b, best_tx, best_lz, best_blocks) == LBW_OK) {
+        const bool policy = b->nts;
+        b->nts = !policy;
+        const float ms = time_current();
+        if (!(err == hipSuccess && ms < best_ms)) b->nts = policy;
+        else best_ms = ms;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

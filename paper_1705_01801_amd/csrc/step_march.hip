@@ -431,7 +431,7 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
 // tile n0 x rty, rty rows chosen per geometry by the host; the whole
 // cross-section when it fits), for geometries whose rows a TX-wide tile
 // would split or leave mostly idle; TX = NT then only sizes the LDS arrays.
-template <int TX, int NT, bool SECTION>
+template <int TX, int NT, bool SECTION, bool NTS>
 __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restrict__ items,
                                                          const int32_t* __restrict__ tile_item, int n_items,
                                                          int64_t tiles_total, BatchProbeArgs bp,
@@ -507,8 +507,8 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restr
         tg.src_zlo = it.src_zlo;
         tg.src_zhi = it.src_zhi;
         tg.src_t = t_now[h];
-        march_tile<TX, NT, true, SECTION, false, true>(tg, (int)(tile - it.tile_begin), fin + it.f_off,
-                                                       fout + it.f_off, sS, sElo, sEhi);
+        march_tile<TX, NT, true, SECTION, NTS, true>(tg, (int)(tile - it.tile_begin), fin + it.f_off,
+                                                     fout + it.f_off, sS, sElo, sEhi);
     }
 }
 
@@ -589,11 +589,11 @@ hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchP
 int batch_blocks_per_cu(int tx) {
     int nb = 0;
     hipError_t e =
-        tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<16, kBatchThreads, false>,
+        tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<16, kBatchThreads, false, false>,
                                                                   kBatchThreads, 0)
-        : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32, kBatchThreads, false>,
+        : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32, kBatchThreads, false, false>,
                                                                   kBatchThreads, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64, kBatchThreads, false>,
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64, kBatchThreads, false, false>,
                                                                   kBatchThreads, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
@@ -607,33 +607,46 @@ int batch_row_tile(int n0, int n1, int nt) {
 int batch_section_blocks_per_cu(int nt) {
     int nb = 0;
     hipError_t e =
-        nt == 128   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<128, 128, true>, 128, 0)
-        : nt == 256 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<256, 256, true>, 256, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<512, 512, true>, 512, 0);
+        nt == 128   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<128, 128, true, false>, 128, 0)
+        : nt == 256 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<256, 256, true, false>, 256, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<512, 512, true, false>, 512, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-hipError_t launch_step_batch(const BatchItem* items, const int32_t* tile_item, int n_items, int64_t tiles_total,
-                             int tx, int section_nt, int blocks, const BatchProbeArgs& bp, const float* fin,
-                             float* fout, hipStream_t st) {
+namespace {
+template <bool NTS>
+void launch_batch_of(const BatchItem* items, const int32_t* tile_item, int n_items, int64_t tiles_total, int tx,
+                     int section_nt, int blocks, const BatchProbeArgs& bp, const float* fin, float* fout,
+                     hipStream_t st) {
+    const dim3 grid(blocks);
     if (section_nt == 128)
-        hipLaunchKernelGGL((step_batch_kernel<128, 128, true>), dim3(blocks), dim3(128), 0, st, items, tile_item,
-                           n_items, tiles_total, bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<128, 128, true, NTS>), grid, dim3(128), 0, st, items, tile_item, n_items,
+                           tiles_total, bp, fin, fout);
     else if (section_nt == 256)
-        hipLaunchKernelGGL((step_batch_kernel<256, 256, true>), dim3(blocks), dim3(256), 0, st, items, tile_item,
-                           n_items, tiles_total, bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<256, 256, true, NTS>), grid, dim3(256), 0, st, items, tile_item, n_items,
+                           tiles_total, bp, fin, fout);
     else if (section_nt == 512)
-        hipLaunchKernelGGL((step_batch_kernel<512, 512, true>), dim3(blocks), dim3(512), 0, st, items, tile_item,
-                           n_items, tiles_total, bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<512, 512, true, NTS>), grid, dim3(512), 0, st, items, tile_item, n_items,
+                           tiles_total, bp, fin, fout);
     else if (tx == 16)
-        hipLaunchKernelGGL((step_batch_kernel<16, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
-                           items, tile_item, n_items, tiles_total, bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<16, kBatchThreads, false, NTS>), grid, dim3(kBatchThreads), 0, st, items,
+                           tile_item, n_items, tiles_total, bp, fin, fout);
     else if (tx == 32)
-        hipLaunchKernelGGL((step_batch_kernel<32, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
-                           items, tile_item, n_items, tiles_total, bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<32, kBatchThreads, false, NTS>), grid, dim3(kBatchThreads), 0, st, items,
+                           tile_item, n_items, tiles_total, bp, fin, fout);
     else
-        hipLaunchKernelGGL((step_batch_kernel<64, kBatchThreads, false>), dim3(blocks), dim3(kBatchThreads), 0, st,
-                           items, tile_item, n_items, tiles_total, bp, fin, fout);
+        hipLaunchKernelGGL((step_batch_kernel<64, kBatchThreads, false, NTS>), grid, dim3(kBatchThreads), 0, st, items,
+                           tile_item, n_items, tiles_total, bp, fin, fout);
+}
+}  // namespace
+
+hipError_t launch_step_batch(const BatchItem* items, const int32_t* tile_item, int n_items, int64_t tiles_total,
+                             int tx, int section_nt, int blocks, bool nts, const BatchProbeArgs& bp, const float* fin,
+                             float* fout, hipStream_t st) {
+    if (nts)
+        launch_batch_of<true>(items, tile_item, n_items, tiles_total, tx, section_nt, blocks, bp, fin, fout, st);
+    else
+        launch_batch_of<false>(items, tile_item, n_items, tiles_total, tx, section_nt, blocks, bp, fin, fout, st);
     return hipGetLastError();
 }
 
