@@ -394,10 +394,13 @@ int lbw_batch_modes(lbw_batch_t b, int k, double* freq_out, double* power_out);
  * at node nodes[i] of geometry geom[i] with its own amplitude[i], omega[i]
  * and kind[i] (NULL kind: all LBW_SOURCE_PRESSURE), so one batch can sweep
  * many drive frequencies, and both source kinds, over copies of a geometry;
- * t is that geometry's step count.  The batch step imposes them itself, on
- * the populations it loads (no separate launch, nothing written to the
- * input buffer), with the same per-node arithmetic as lbw_set_sources, so a
- * driven copy in a batch and the same copy driven alone give the same bits.
+ * t is that geometry's step count.  Where the driven nodes lie on few planes
+ * (from each geometry's first to last driven plane, at most an eighth of the
+ * batch's planes in all) the batch step imposes them itself, on the
+ * populations it loads (nothing written to the input buffer); otherwise a
+ * launch of their own does, before every step.  Both use the per-node
+ * arithmetic of lbw_set_sources, so a driven copy in a batch and the same
+ * copy driven alone give the same bits.
  * All arrays are host memory of n entries, read during the call; n = 0
  * removes the sources.  Waits for the stream.  Errors: LBW_EINVAL (n < 0,
  * NULL nodes, geom, amplitude or omega with n > 0, a geometry index or node

@@ -49,6 +49,10 @@ struct lbw_batch {
     lbw::BatchSource* d_src = nullptr;
     int32_t* d_src_map = nullptr;
     int n_src = 0;
+    // or, where driven nodes span many planes, imposed by a launch of their
+    // own before every step (one entry per driven node)
+    lbw::SourceEntry* d_entries = nullptr;
+    int n_entries = 0;
     std::vector<int> src_count, src_zlo, src_zhi;
     std::vector<uint32_t> src_map_off;
     double* d_amp = nullptr;            // response intensities (P)
@@ -72,6 +76,7 @@ void release(lbw_batch* b) {
     (void)hipFree(b->mode_out);
     (void)hipFree(b->d_src);
     (void)hipFree(b->d_src_map);
+    (void)hipFree(b->d_entries);
     (void)hipFree(b->d_amp);
     delete b;
 }
@@ -162,6 +167,12 @@ lbw::BatchProbeArgs probe_args(lbw_batch* b, bool record) {
 // buffer read: b->cur flips with every step, from 0 at step 0.
 hipError_t launch_batch(lbw_batch* b, lbw::BatchProbeArgs bp, const float* fin, float* fout, hipStream_t st) {
     bp.parity = fin == b->f[1] ? 1 : 0;
+    if (b->n_entries > 0 && bp.tcount == b->d_tcount) {
+        // sources imposed in memory before the step, at this step's time
+        const hipError_t e = lbw::launch_sources(b->d_entries, b->n_entries, b->d_tcount + (size_t)bp.parity * b->n,
+                                                 const_cast<float*>(fin), st);
+        if (e != hipSuccess) return e;
+    }
     return lbw::launch_step_batch(b->d_items, b->d_tile_item, b->n, b->tiles, b->tx, b->section_nt, b->blocks, b->nts,
                                   bp, fin, fout, st);
 }
@@ -700,6 +711,51 @@ int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* ge
         zhi[(size_t)h] = z;
         count[(size_t)h] += 1;
     }
+    // Imposed by the step kernel as it loads the populations (a map lookup
+    // on every plane of a geometry's driven span) when the driven spans are
+    // a small part of the batch's planes; else by a launch of their own.
+    // Both use drive_node, so the results are the same bits.
+    int64_t span = 0, planes = 0;
+    for (int h = 0; h < b->n; ++h) {
+        planes += b->d[h].n[2];
+        if (count[(size_t)h] > 0) span += zhi[(size_t)h] - zlo[(size_t)h] + 1;
+    }
+    const bool fused = span * 8 <= planes;
+    drop_graphs(b);
+    (void)hipFree(b->d_entries);
+    b->d_entries = nullptr;
+    b->n_entries = 0;
+    if (n > 0 && !fused) {
+        std::vector<lbw::SourceEntry> ent((size_t)n);
+        for (int j = 0; j < n; ++j) {
+            const int i = order[(size_t)j];
+            const int h = geom[i];
+            lbw::SourceEntry e{};
+            e.f_off = (uint64_t)(7 * b->node_off[h] + nodes[i]);
+            e.N = (uint32_t)(b->node_off[h + 1] - b->node_off[h]);
+            e.q = 7;
+            e.counter = h;
+            e.kind = host[(size_t)j].kind;
+            e.a0 = host[(size_t)j].a0;
+            e.a1 = host[(size_t)j].a1;
+            e.omega = host[(size_t)j].omega;
+            ent[(size_t)j] = e;
+        }
+        (void)hipFree(b->d_src);
+        (void)hipFree(b->d_src_map);
+        b->d_src = nullptr;
+        b->d_src_map = nullptr;
+        b->n_src = 0;
+        std::fill(count.begin(), count.end(), 0);
+        b->src_count = count;
+        HIP_TRY(hipMalloc((void**)&b->d_entries, sizeof(lbw::SourceEntry) * n), "lbw_batch_set_sources");
+        HIP_TRY(hipMemcpyAsync(b->d_entries, ent.data(), sizeof(lbw::SourceEntry) * n, hipMemcpyHostToDevice,
+                               b->stream),
+                "lbw_batch_set_sources");
+        b->n_entries = n;
+        HIP_TRY(build_items(b), "lbw_batch_set_sources");
+        return LBW_OK;
+    }
     // node -> entry maps over each geometry's driven planes
     std::vector<uint32_t> map_off((size_t)b->n, 0);
     int64_t map_len = 0;
@@ -718,7 +774,6 @@ int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* ge
         const int64_t plane = (int64_t)b->d[h].n[0] * b->d[h].n[1];
         map[(size_t)(map_off[(size_t)h] + nodes[i] - plane * zlo[(size_t)h])] = j;
     }
-    drop_graphs(b);
     (void)hipFree(b->d_src);
     (void)hipFree(b->d_src_map);
     b->d_src = nullptr;

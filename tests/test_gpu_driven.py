@@ -8,10 +8,10 @@ keeps populations in FP32, so fields and traces are compared with the field
 tolerance of the undriven parity tests (relative L2 1e-5); a probe on a
 source node must read the imposed value to FP32 rounding; a batch of copies
 driven at different frequencies must match each copy driven alone bit for
-bit (same per-node arithmetic; the batch step imposes the sources as it
-loads the populations, a single run by a kernel of its own, both through
-the same per-node rule), and graph replay must match step-by-step
-launches.
+bit (same per-node arithmetic; a batch imposes the sources in its step
+kernel as it loads the populations, or by a launch of their own where they
+span most planes, a single run by that launch, all through the same
+per-node rule), and graph replay must match step-by-step launches.
 """
 import sys
 
@@ -233,13 +233,18 @@ def test_batch_autotune_with_sources_changes_nothing():
     assert np.array_equal(out[0][1], out[1][1])
 
 
-def test_driven_nodes_anywhere_in_the_tile_walk():
-    """Driven nodes are imposed by the batch step on the populations it
-    loads: on a node's own column, on the ring of a neighbouring tile, at a
-    chunk's first and last planes and across the periodic axis-2 seam.  A
-    torus (periodic axes 1 and 2) and a cylinder with driven nodes scattered
-    over every plane, pressure and flux kinds, several on probe nodes, give
-    the same bits as each copy driven alone, on four launch shapes."""
+@pytest.mark.parametrize("spread", ["every_plane", "two_planes"])
+def test_driven_nodes_anywhere_in_the_tile_walk(spread):
+    """A batch imposes its sources either in the step kernel, on the
+    populations it loads (where the driven planes are a small part of the
+    batch's planes: a node's own column, the ring of a neighbouring tile, a
+    chunk's first and last planes, the periodic axis-2 seam), or by a launch
+    of their own before every step (where they span most planes).  A torus
+    (periodic axes 1 and 2) and a cylinder with driven nodes scattered over
+    every plane (the separate launch), or over the two planes either side of
+    a chunk boundary (the step kernel), pressure and flux kinds, several on
+    probe nodes, give the same bits as each copy driven alone, on four
+    launch shapes."""
     rng = np.random.default_rng(17)
     geoms = [W.torus(scale=16), cyl()[0], W.torus(scale=16)]
     N = [W.num_nodes(g) for g in geoms]
@@ -247,12 +252,14 @@ def test_driven_nodes_anywhere_in_the_tile_walk():
     for g, n in zip(geoms, N):
         n0, n1, n2 = g["n"]
         plane = n0 * n1
-        # two nodes on every plane (ring positions included: x = 0, n0 - 1;
-        # y = 0, n1 - 1) and the whole first and last planes' x = 0 column
+        zs = range(n2) if spread == "every_plane" else (n2 // 2 - 1, n2 // 2)
+        # two nodes on each chosen plane (ring positions included: x = 0,
+        # n0 - 1; y = 0, n1 - 1) and the whole x = 0 column of the first and
+        # last chosen planes
         nodes = set()
-        for z in range(n2):
+        for z in zs:
             nodes.update(int(v) for v in rng.choice(plane, size=2, replace=False) + z * plane)
-        for z in (0, n2 - 1):
+        for z in (zs[0], zs[-1]):
             nodes.update(z * plane + n0 * y for y in range(n1))
         nodes = np.array(sorted(nodes), dtype=np.int64)
         srcs.append(nodes)
@@ -272,7 +279,7 @@ def test_driven_nodes_anywhere_in_the_tile_walk():
         which = np.repeat(np.arange(len(geoms)), [len(x) for x in srcs])
         b.set_sources(np.concatenate(srcs), which, 0.6, np.repeat(omegas, [len(x) for x in srcs]),
                       np.repeat(kinds, [len(x) for x in srcs]))
-        say("driven nodes everywhere, launch shape", b.step_config())
+        say("driven nodes", spread, "launch shape", b.step_config())
         b.step(T)
         trace = b.probe()
         for h in range(len(geoms)):
