@@ -215,7 +215,7 @@ def main():
                     help="drive frequencies in the driven-pipe sweep leg (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (the slab decomposition that "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (the slab decomposition that "
               "would shard a grid is described in the design notes); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
