@@ -130,7 +130,12 @@ def classify(members, steps: int | None = None, growth: float = 2.0, log=None) -
     put in the first class that applies:
       unstable      the population 2-norm grows more than `growth`-fold over
                     the run, or turns non-finite;
-      unresolved    fewer than ten spectral peaks found;
+      unresolved    fewer than ten spectral peaks found, or the first
+                    usable spectral frequency, 16 / (nfft c h_ref) in
+                    physical units, above 0.25, the lowest resonance of a
+                    closed-open tube of unit length (flare only raises it):
+                    the run is too short in physical time to see the
+                    fundamental;
       multi-family  the ten peaks are not one longitudinal family: the
                     second axisymmetric radial family of the bell, which
                     starts at j'_{0,2} / (2 pi R(1)) in physical units, lies
@@ -187,7 +192,9 @@ def classify(members, steps: int | None = None, growth: float = 2.0, log=None) -
     R1 = a + bb * np.exp(k)
     ratio = np.where(np.isfinite(n1), n1 / n0, np.inf)
     unstable = ratio > growth
-    unresolved = ~unstable & np.isnan(f).any(axis=1)
+    nfft = 4 * (1 << int(math.ceil(math.log2(steps))))
+    f_lo = 16.0 / (nfft * np.array([g["c"] for g in geoms]) * np.array([g["h_ref"] for g in geoms]))
+    unresolved = ~unstable & (np.isnan(f).any(axis=1) | (f_lo > 0.25))
     cut2 = jn_zeros(1, 2)[1] / (2.0 * math.pi * R1)
     multi = ~unstable & ~unresolved & multi_family(f, prof)
     usable = ~(unstable | unresolved | multi)
@@ -200,6 +207,7 @@ def classify(members, steps: int | None = None, growth: float = 2.0, log=None) -
             "per_horn": {"profile": prof.tolist(), "grid": grid.tolist(),
                          "c": [g["c"] for g in geoms], "h_ref": [g["h_ref"] for g in geoms],
                          "mhat_rr_max": mrr.tolist(), "norm_ratio": ratio.tolist(), "freq": f.tolist(),
+                         "first_usable_frequency": f_lo.tolist(),
                          "bell_radius": R1.tolist(), "bell_slope": (bb * k * np.exp(k)).tolist(),
                          "second_radial_cut_on": cut2.tolist(),
                          "class": np.select([unstable, unresolved, multi], ["unstable", "unresolved", "multi-family"],
@@ -226,7 +234,7 @@ def main(argv=None):
                          "candidates outside workloads.served() excluded")
     ap.add_argument("--keep-multi-family", action="store_true",
                     help="with --box stated: train on every training horn, one family or not")
-    ap.add_argument("--census", choices=("stated", "isotropic"), default=None,
+    ap.add_argument("--census", choices=("stated", "stated_short", "isotropic"), default=None,
                     help="classify the horns of the configured profile box and grids instead (see census)")
     args = ap.parse_args(argv)
 

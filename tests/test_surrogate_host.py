@@ -72,8 +72,12 @@ def test_served_region_and_stated_draws():
     assert len(ms) == 64 and W.served([m["profile"] for m in ms]).all()
     st = W.stated_ensemble(16, "stated")
     iso = W.stated_ensemble(16, "isotropic")
-    for s, i in zip(st, iso):
-        assert s["profile"] == i["profile"]
+    short = W.stated_ensemble(16, "stated_short")
+    for s, i, sh in zip(st, iso, short):
+        assert s["profile"] == i["profile"] == sh["profile"] and s["geom"]["n"] == sh["geom"]["n"]
+        nr, _, nz = sh["geom"]["n"]
+        link = W.shortest_radial_link(sh["profile"]) * 0.95 / nr
+        assert sh["geom"]["h_ref"] == min(link, 1.0 / nz) and s["geom"]["h_ref"] == 1.0 / nz
         nr, nt, nz = s["geom"]["n"]
         assert nr in W.STATED_GRIDS["nr"] and nt in W.STATED_GRIDS["nt"] and nz in W.STATED_GRIDS["nz"]
         assert i["geom"]["n"][1] == nt and i["geom"]["n"][2] >= nz

@@ -319,9 +319,10 @@ def horn_member(profile, draw, c=None) -> dict:
     return horn_on_grid(profile, horn_grid(profile, *(int(v) for v in draw)), c)
 
 
-def horn_on_grid(profile, n, c=None) -> dict:
+def horn_on_grid(profile, n, c=None, h_ref=None) -> dict:
     """A horn of the profile on the (n_r, n_theta, n_z) grid n with h_ref =
-    h_z (c to be set by the caller when None) and a pressure-release bell
+    h_z unless given (c to be set by the caller when None) and a
+    pressure-release bell
     (P = 0 at z = 1), the plane pulse of horn_pulse, and 8 probes at theta = 0
     spread along z on the ring nearest to r = PROBE_RADIUS: the nodal circle
     of the first radial mode of a hard-walled duct (J0 vanishes at
@@ -335,7 +336,7 @@ def horn_on_grid(profile, n, c=None) -> dict:
     a, b, k = (float(v) for v in profile)
     n = tuple(int(v) for v in n)
     geom = trumpet_horn(c=0.0 if c is None else c, a=a, b=b, k=k, n=n)
-    geom["h_ref"] = 1.0 / n[2]
+    geom["h_ref"] = 1.0 / n[2] if h_ref is None else float(h_ref)
     geom["bc_hi"] = ("bounceback", "periodic", "fixed")
     if c is None:
         geom["c"] = None
@@ -371,15 +372,20 @@ STATED_GRIDS = {"nr": tuple(range(32, 97, 8)), "nt": (32, 40, 48, 56, 64), "nz":
 def stated_ensemble(n: int = 512, rule: str = "stated", stream: int = 0):
     """n horns with profiles uniform on STATED_RANGES and (n_r, n_theta,
     n_z) drawn from STATED_GRIDS.  rule "stated" simulates each on its drawn
-    grid; rule "isotropic" keeps the drawn (n_theta, n_z) and sets n_r (and
-    raises n_z) by horn_grid, as the training ensemble does.  Both rules see
-    the same profiles and draws."""
+    grid with h_ref = h_z; rule "stated_short" on its drawn grid with h_ref
+    the shortest link, min(shortest radial link, h_z), as the benchmark horn
+    (no radial link shorter than the lattice unit); rule "isotropic" keeps
+    the drawn (n_theta, n_z) and sets n_r (and raises n_z) by horn_grid, as
+    the training ensemble does.  All rules see the same profiles and draws."""
     rng = np.random.default_rng(SEED_BASE + 4 + 7919 * stream + 15485863)
     prof = np.stack([rng.uniform(*STATED_RANGES[key], size=n) for key in ("a", "b", "k")], axis=1)
     grid = np.stack([rng.choice(np.array(STATED_GRIDS[key]), size=n) for key in ("nr", "nt", "nz")],
                     axis=1).astype(np.int64)
     if rule == "stated":
         return [horn_on_grid(p, g) for p, g in zip(prof, grid)]
+    if rule == "stated_short":
+        return [horn_on_grid(p, g, h_ref=min(shortest_radial_link(p) * 0.95 / g[0], 1.0 / g[2]))
+                for p, g in zip(prof, grid)]
     if rule == "isotropic":
         return [horn_member(p, g[1:]) for p, g in zip(prof, grid)]
     raise ValueError(rule)
