@@ -721,6 +721,18 @@ int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* ge
         if (count[(size_t)h] > 0) span += zhi[(size_t)h] - zlo[(size_t)h] + 1;
     }
     const bool fused = span * 8 <= planes;
+    // node -> entry maps over each geometry's driven planes (sized and
+    // checked before anything of the batch changes)
+    std::vector<uint32_t> map_off((size_t)b->n, 0);
+    int64_t map_len = 0;
+    for (int h = 0; fused && h < b->n; ++h) {
+        if (count[(size_t)h] == 0) continue;
+        const int64_t plane = (int64_t)b->d[h].n[0] * b->d[h].n[1];
+        if (map_len > 0x7fffffffLL) return fail(LBW_EINVAL, "driven planes too large for the source map");
+        map_off[(size_t)h] = (uint32_t)map_len;
+        map_len += plane * (zhi[(size_t)h] - zlo[(size_t)h] + 1);
+    }
+    if (map_len > 0x7fffffffLL) return fail(LBW_EINVAL, "driven planes too large for the source map");
     drop_graphs(b);
     (void)hipFree(b->d_entries);
     b->d_entries = nullptr;
@@ -756,17 +768,6 @@ int lbw_batch_set_sources(lbw_batch_t b, const int64_t* nodes, const int32_t* ge
         HIP_TRY(build_items(b), "lbw_batch_set_sources");
         return LBW_OK;
     }
-    // node -> entry maps over each geometry's driven planes
-    std::vector<uint32_t> map_off((size_t)b->n, 0);
-    int64_t map_len = 0;
-    for (int h = 0; h < b->n; ++h) {
-        if (count[(size_t)h] == 0) continue;
-        const int64_t plane = (int64_t)b->d[h].n[0] * b->d[h].n[1];
-        if (map_len > 0x7fffffffLL) return fail(LBW_EINVAL, "driven planes too large for the source map");
-        map_off[(size_t)h] = (uint32_t)map_len;
-        map_len += plane * (zhi[(size_t)h] - zlo[(size_t)h] + 1);
-    }
-    if (map_len > 0x7fffffffLL) return fail(LBW_EINVAL, "driven planes too large for the source map");
     std::vector<int32_t> map((size_t)map_len, -1);
     for (int j = 0; j < n; ++j) {
         const int i = order[(size_t)j];
