@@ -6,6 +6,7 @@ repository root (one process per case, CPU only):
 
     python tests/golden/make_goldens.py full 1 2 3     # 1000 steps, full grids
     python tests/golden/make_goldens.py modes 1 2 3    # 4x coarser grids, configured step counts
+    python tests/golden/make_goldens.py ensemble 80 222 # training-ensemble horns, configured run
 
 Files (numpy .npz, no pickled objects):
 
@@ -19,7 +20,13 @@ Files (numpy .npz, no pickled objects):
 * ``modes_<name>_coarse4.npz``: ``freq``, ``power`` (the first 10 spectral
   peaks of the probe traces by the oracle's extractor, cycles per step),
   ``steps``, ``input_digest``, and ``norm`` (L2 norm of the populations at
-  t = 0 and at the end).
+  t = 0 and at the end);
+* ``ensemble_<i>.npz``: horn i of the training ensemble on its own grid,
+  with c = 0.9 of the frozen-coefficient stability bound computed from the
+  oracle's coefficients (c^2 rounded down to a multiple of 2^-16), run from
+  the plane pulse for the configured 30,000 steps: ``c``, ``freq`` and
+  ``power`` (the first 10 spectral peaks of its 8 probes, cycles per step),
+  ``trace`` (every 10th row of the probe traces), ``input_digest``.
 """
 from __future__ import annotations
 
@@ -78,6 +85,47 @@ def make_full(idx: int):
     print("full %s: %d steps in %.0f s" % (w["name"], FULL_STEPS, time.time() - t0), flush=True)
 
 
+ENSEMBLE_TRACE_STRIDE = 10
+
+
+def ensemble_path(i: int) -> str:
+    return os.path.join(HERE, "ensemble_%d.npz" % i)
+
+
+def stability_bound(o) -> float:
+    """2 / sqrt(max over nodes of sum_d B_d), B_d = 4 for m_d <= 1 and
+    (1 + m_d)^2 / m_d otherwise, m_d = Mhat^dd plus |Mhat^02| on axes 0
+    and 2: the frozen-coefficient bound of the tau = 1/2 scheme."""
+    tot = np.zeros(o.N)
+    for a in range(o.dim):
+        m = o.Mhat[a] + (np.abs(o.Mhat[4]) if o.dim == 3 and a in (0, 2) else 0.0)
+        tot += np.where(m <= 1.0, 4.0, (1.0 + m) ** 2 / np.maximum(m, 1e-300))
+    return 2.0 / float(np.sqrt(tot.max()))
+
+
+def ensemble_member(i: int):
+    """Horn i of the training ensemble with its wave speed, pulse and probes."""
+    m = W.ensemble(512)[i]
+    geom = dict(m["geom"], c=0.1)
+    cmax = stability_bound(oracle.Oracle(geom))   # Mhat does not depend on c
+    c2 = np.floor((0.9 * cmax) ** 2 * 65536.0) / 65536.0
+    geom["c"] = float(np.sqrt(c2))
+    return dict(geom=geom, P0=W.horn_pulse(geom), probes=np.asarray(m["probes"], dtype=np.int64))
+
+
+def make_ensemble(i: int):
+    w = ensemble_member(i)
+    o = oracle.Oracle(w["geom"])
+    f = o.init(w["P0"])
+    t0 = time.time()
+    _, trace = o.run(f, W.ENSEMBLE_STEPS, w["probes"])
+    freq, power = oracle.modes(trace, W.ENSEMBLE_MODES)
+    np.savez(ensemble_path(i), c=np.array(w["geom"]["c"]), freq=freq, power=power,
+             trace=trace[::ENSEMBLE_TRACE_STRIDE], input_digest=np.array(input_digest(w)))
+    print("ensemble horn %d %s c %.6f: %d steps in %.0f s, freq %s" % (
+        i, w["geom"]["n"], w["geom"]["c"], W.ENSEMBLE_STEPS, time.time() - t0, freq), flush=True)
+
+
 def make_modes(idx: int):
     w = W.workload(idx, scale=COARSE)
     o = oracle.Oracle(w["geom"])
@@ -95,4 +143,4 @@ def make_modes(idx: int):
 if __name__ == "__main__":
     what = sys.argv[1]
     for i in (int(v) for v in sys.argv[2:]):
-        (make_full if what == "full" else make_modes)(i)
+        {"full": make_full, "modes": make_modes, "ensemble": make_ensemble}[what](i)

@@ -8,7 +8,9 @@ runs only the FP64 oracle on the seeded inputs of ``workloads``:
   probe traces (every probe, every step), the populations at 65,536 seeded
   nodes, and sum sqrt(g) P before and after;
 * the same three on grids 4x coarser per axis, run for their configured
-  step counts (20,000 / 50,000 / 40,000): the first ten spectral peaks.
+  step counts (20,000 / 50,000 / 40,000): the first ten spectral peaks;
+* two horns of the training ensemble over the configured 30,000 steps: the
+  first ten spectral peaks and every 10th probe-trace row.
 
 The GPU runs in the launch shape the benchmark uses (the tuner's choice)
 and must match: traces within 1e-5 max|trace|, sampled populations within
@@ -117,3 +119,45 @@ def test_full_torus_configured_run_growth_bounded():
     tr = sim.probe()                                       # raises on a non-finite value
     assert tr.shape == (steps, len(w["probes"]))
     assert max(ratios) <= 2.0, ratios
+
+
+ENSEMBLE_IDS = (80, 222)
+
+
+def test_ensemble_horns_configured_run_match_stored_oracle():
+    """Horns 80 (k = 1.95) and 222 (k = 1.03) of the training ensemble,
+    16 x 32 x 144 each, in one batch in the launch shape the batch tuner
+    picks, over the configured 30,000 steps, against the stored oracle runs.
+    The library's own wave speed (0.9 of its stability bound, c^2 rounded
+    down to a multiple of 2^-16, as the study chooses it) must equal the one
+    the oracle's coefficients give; the first ten spectral peaks must be the
+    same peaks within 1e-5 relative; every 10th trace row within
+    30,000 x 6e-8 = 1.8e-3 of max|trace| (FP32 rounding of 6e-8 per step,
+    accumulating at most linearly over the run)."""
+    from paper_1705_01801_amd import surrogate as S
+    refs = [np.load(G.ensemble_path(i)) for i in ENSEMBLE_IDS]
+    ws = [G.ensemble_member(i) for i in ENSEMBLE_IDS]
+    for w, ref in zip(ws, refs):
+        assert str(ref["input_digest"]) == G.input_digest(w), "stored oracle run is for other inputs"
+        assert S.wave_speed(dict(w["geom"], c=None)) == float(ref["c"]) == w["geom"]["c"]
+    steps = W.ENSEMBLE_STEPS
+    say("ensemble horns", ENSEMBLE_IDS, steps, "steps")
+    b = lbw.Batch([w["geom"] for w in ws], [w["P0"] for w in ws], [w["probes"] for w in ws], t_max=steps)
+    b.autotune(reps=5)
+    say("  launch shape", b.step_config())
+    b.step(steps)
+    freq, _ = b.modes(W.ENSEMBLE_MODES)
+    trace = b.probe()
+    for h, ref in enumerate(refs):
+        fo = ref["freq"]
+        ok = ~np.isnan(fo)
+        assert ok.sum() == W.ENSEMBLE_MODES
+        assert np.array_equal(ok, ~np.isnan(freq[h]))
+        assert np.abs(freq[h][ok] / fo[ok] - 1.0).max() <= 1e-5, (freq[h], fo)
+        cols = slice(int(b.probe_offsets[h]), int(b.probe_offsets[h + 1]))
+        tr = trace[::G.ENSEMBLE_TRACE_STRIDE, cols]
+        say("  horn %d: peaks within %.1e, trace within %.1e of max" % (
+            ENSEMBLE_IDS[h], np.abs(freq[h][ok] / fo[ok] - 1.0).max(),
+            np.abs(tr - ref["trace"]).max() / np.abs(ref["trace"]).max()))
+        assert np.abs(tr - ref["trace"]).max() <= 1.8e-3 * np.abs(ref["trace"]).max()
+    b.close()
