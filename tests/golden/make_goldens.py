@@ -7,6 +7,8 @@ repository root (one process per case, CPU only):
     python tests/golden/make_goldens.py full 1 2 3     # 1000 steps, full grids
     python tests/golden/make_goldens.py modes 1 2 3    # 4x coarser grids, configured step counts
     python tests/golden/make_goldens.py ensemble 80 222 # training-ensemble horns, configured run
+    python tests/golden/make_goldens.py full 4          # the duct given by its metric, 1000 steps
+    python tests/golden/make_goldens.py sweep 0         # one torus sweep point, full length
 
 Files (numpy .npz, no pickled objects):
 
@@ -26,7 +28,12 @@ Files (numpy .npz, no pickled objects):
   oracle's coefficients (c^2 rounded down to a multiple of 2^-16), run from
   the plane pulse for the configured 30,000 steps: ``c``, ``freq`` and
   ``power`` (the first 10 spectral peaks of its 8 probes, cycles per step),
-  ``trace`` (every 10th row of the probe traces), ``input_digest``.
+  ``trace`` (every 10th row of the probe traces), ``input_digest``;
+* ``sweep_torus_small_ring.npz``: one point of the torus sweep (the small
+  ring driven at omega = 0.071 rad/step from rest) over the sweep's full
+  length: ``trace`` (every 10th row), ``amplitude`` (largest |P| per probe
+  over the second half), ``nodes`` / ``f`` (populations at 16,384 seeded
+  nodes at the end, float32), ``sources``, ``omega``, ``input_digest``.
 """
 from __future__ import annotations
 
@@ -53,7 +60,10 @@ COARSE = 4
 
 def input_digest(w) -> str:
     h = hashlib.sha256()
-    h.update(json.dumps(w["geom"], sort_keys=True, default=float).encode())
+    geom = {k: v for k, v in w["geom"].items() if k != "coeffs"}
+    h.update(json.dumps(geom, sort_keys=True, default=float).encode())
+    if "coeffs" in w["geom"]:                     # a geometry given by its metric: the per-node planes
+        h.update(np.ascontiguousarray(w["geom"]["coeffs"], dtype=np.float64).tobytes())
     h.update(np.ascontiguousarray(w["P0"], dtype=np.float64).tobytes())
     h.update(np.ascontiguousarray(w["probes"], dtype=np.int64).tobytes())
     return h.hexdigest()
@@ -64,8 +74,12 @@ def sample_nodes(idx: int, N: int) -> np.ndarray:
     return np.sort(rng.choice(N, size=min(SAMPLE, N), replace=False)).astype(np.int64)
 
 
+def full_name(idx: int) -> str:
+    return "general_duct_d3q7_128x128x128" if idx == 4 else W.NAMES[idx]
+
+
 def full_path(idx: int) -> str:
-    return os.path.join(HERE, "full_%s_%d.npz" % (W.NAMES[idx], FULL_STEPS))
+    return os.path.join(HERE, "full_%s_%d.npz" % (full_name(idx), FULL_STEPS))
 
 
 def modes_path(idx: int) -> str:
@@ -73,7 +87,7 @@ def modes_path(idx: int) -> str:
 
 
 def make_full(idx: int):
-    w = W.workload(idx)
+    w = W.general_workload() if idx == 4 else W.workload(idx)
     o = oracle.Oracle(w["geom"])
     f = o.init(w["P0"])
     inv0 = o.invariant(f)
@@ -126,6 +140,38 @@ def make_ensemble(i: int):
         i, w["geom"]["n"], w["geom"]["c"], W.ENSEMBLE_STEPS, time.time() - t0, freq), flush=True)
 
 
+SWEEP_OMEGA = 0.071
+SWEEP_SAMPLE = 16384
+
+
+def sweep_path() -> str:
+    return os.path.join(HERE, "sweep_torus_small_ring.npz")
+
+
+def sweep_inputs():
+    """The torus sweep's geometry, its small-ring source nodes and probes
+    (the sweep's probe and two next to the ring), from rest."""
+    geom = W.driven_torus()
+    ring = np.asarray(W.torus_sources(geom)["small_ring"], dtype=np.int64)
+    probes = np.concatenate([W.torus_probes(geom), ring[[3, 10]] + 2]).astype(np.int64)
+    return dict(geom=geom, P0=np.zeros(W.num_nodes(geom)), probes=probes), ring
+
+
+def make_sweep(_=0):
+    w, ring = sweep_inputs()
+    o = oracle.Oracle(w["geom"])
+    f = o.init(w["P0"])
+    T = W.TORUS_STEPS
+    t0 = time.time()
+    _, trace = o.run(f, T, w["probes"], sources=ring, amplitude=1.0, omega=SWEEP_OMEGA)
+    rng = np.random.default_rng(W.SEED_BASE + 2000)
+    nodes = np.sort(rng.choice(o.N, size=SWEEP_SAMPLE, replace=False)).astype(np.int64)
+    np.savez(sweep_path(), trace=trace[::ENSEMBLE_TRACE_STRIDE], amplitude=o.amplitude(trace, T // 2, T),
+             nodes=nodes, f=f[:, nodes].astype(np.float32), sources=ring, omega=np.array(SWEEP_OMEGA),
+             steps=np.array(T), input_digest=np.array(input_digest(w)))
+    print("torus sweep point omega %.3f: %d steps in %.0f s" % (SWEEP_OMEGA, T, time.time() - t0), flush=True)
+
+
 def make_modes(idx: int):
     w = W.workload(idx, scale=COARSE)
     o = oracle.Oracle(w["geom"])
@@ -143,4 +189,4 @@ def make_modes(idx: int):
 if __name__ == "__main__":
     what = sys.argv[1]
     for i in (int(v) for v in sys.argv[2:]):
-        {"full": make_full, "modes": make_modes, "ensemble": make_ensemble}[what](i)
+        {"full": make_full, "modes": make_modes, "ensemble": make_ensemble, "sweep": make_sweep}[what](i)

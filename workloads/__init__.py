@@ -600,12 +600,19 @@ def general_at(q, **embedding) -> np.ndarray:
     return np.stack([np.asarray(p, dtype=np.float64).reshape(-1) for p in planes])
 
 
+# Wave speed of the duct: about 0.3 with c^2 a multiple of 2^-16, exact in
+# FP32 like every configured wave speed (with c = 0.3 itself the FP32 step
+# runs at a c^2 4e-8 off the FP64 one, and the fields drift apart linearly in
+# time: 1.9e-5 of the largest probe value after 1000 steps on 128^3 nodes).
+DUCT_C = math.sqrt(5898.0 / 65536.0)
+
+
 def general_duct(n=(64, 64, 64), c: float | None = None, **embedding) -> dict:
     """The duct on a lattice of n nodes, q in [0, 1]^3, reflecting walls on
     every face (closed: sum sqrt(g) P is conserved); h_ref = 1 / n0."""
     geom = dict(kind="general", dim=3, n=tuple(n), qmin=(0.0, 0.0, 0.0), qmax=(1.0, 1.0, 1.0),
                 bc_lo=("bounceback",) * 3, bc_hi=("bounceback",) * 3, h_ref=1.0 / n[0],
-                c=0.3 if c is None else c, damp=1.0, params=(), embedding=dict(embedding))
+                c=DUCT_C if c is None else c, damp=1.0, params=(), embedding=dict(embedding))
     return geom
 
 
