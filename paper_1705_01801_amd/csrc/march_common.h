@@ -86,6 +86,16 @@ __device__ inline void drive_node(int kind, double a0, double a1, double omega, 
     }
 }
 
+// bload7 with the non-temporal hint when NTL
+template <bool NTL>
+__device__ inline void bload7p(__amdgpu_buffer_rsrc_t r, uint32_t N4, bool on, uint32_t nb, float v[7]) {
+    const uint32_t base = on ? nb : kOff;
+#pragma unroll
+    for (int l = 0; l < 7; ++l)
+        v[l] = __int_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(r, (int)(base + (uint32_t)l * N4), 0, NTL ? kNontemporal : 0));
+}
+
 // value beyond a wall: mirrored, odd for fixed walls
 __device__ inline float ghost(int wall, float v) { return wall == LBW_BC_FIXED ? -v : v; }
 

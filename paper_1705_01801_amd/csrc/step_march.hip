@@ -106,8 +106,10 @@ __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* 
 // 2 (rtx + rty) <= NT ring loaders and rtx + 2 <= NT row loaders, checked by
 // the host); TX = NT then only sizes the LDS arrays.  SRC: driven nodes
 // (g.src) are imposed on every population set as it is loaded (own column,
-// ring), before any use, as if imposed in memory before the step.
-template <int TX, int NT, bool ROW, bool RT = false, bool NTS = false, bool SRC = false>
+// ring), before any use, as if imposed in memory before the step.  NTS:
+// population stores non-temporal; NTL: the own column's loads too (its
+// planes are read once per pass; the ring's are read again by neighbours).
+template <int TX, int NT, bool ROW, bool RT = false, bool NTS = false, bool SRC = false, bool NTL = false>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
                                            float* __restrict__ fout, float (&sS)[2][lds_s<TX, NT, RT>()],
                                            float4 (&sElo)[3][TX + 3], float4 (&sEhi)[3][TX + 3]) {
@@ -209,7 +211,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             const bool m_on = active && zm0 >= 0;
             bload7(rin, N4, m_on, col4 + (uint32_t)zm0 * plane4, tmp);
             const float4 e = bld4(rtab, m_on ? (uint32_t)(x + n0 * zm0) * 32u : kOff);
-            bload7(rin, N4, active, col4 + (uint32_t)z0 * plane4, fc);
+            bload7p<NTL>(rin, N4, active, col4 + (uint32_t)z0 * plane4, fc);
             const bool e0_on = erow_on, e1_on = erow_on && zp0 >= 0;
             const float4 a0 = bld4(rtab, e0_on ? (uint32_t)(erow_x + n0 * z0) * 32u : kOff);
             const float4 b0 = bld4(rtab, e0_on ? (uint32_t)(erow_x + n0 * z0) * 32u + 16u : kOff);
@@ -236,7 +238,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
         }
         float rA[7], rB[7], rC[7];  // ring populations: plane z+1 (loaded one step ago), plane z+2 (loading)
         float4 eA[2], eB[2], eC[2];  // coefficient rows: plane z+2 (loaded one step ago), plane z+3 (loading)
-        bload7(rin, N4, active && zp0 >= 0, col4 + (uint32_t)zp0 * plane4, fnx);
+        bload7p<NTL>(rin, N4, active && zp0 >= 0, col4 + (uint32_t)zp0 * plane4, fnx);
         bload7(rin, N4, ring_on && z0 + 1 < z1, ring4 + (uint32_t)zp0 * plane4, rA);
         {
             int w = 0;
@@ -275,7 +277,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             const uint32_t eoff = (uint32_t)(erow_x + n0 * z3) * 32u;
             e2[0] = bld4(rtab, e3_on ? eoff : kOff);
             e2[1] = bld4(rtab, e3_on ? eoff + 16u : kOff);
-            bload7(rin, N4, active && zq >= 0, col4 + (uint32_t)zq * plane4, fnn);
+            bload7p<NTL>(rin, N4, active && zq >= 0, col4 + (uint32_t)zq * plane4, fnn);
             bload7(rin, N4, ring_on && more2, ring4 + (uint32_t)zq * plane4, r2);
             // plane z+1 (own column; ring below) as loaded one step ago:
             // driven nodes imposed before their first use (fnx becomes fc)
@@ -420,7 +422,7 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
     const int t_begin = (int)(plan.tiles * xcd / kXcds);
     const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
     for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
-        march_tile<TX, NT, ROW, false, NTS>(tg, tile, fin, fout, sS, sElo, sEhi);
+        march_tile<TX, NT, ROW, false, NTS, false, NTS>(tg, tile, fin, fout, sS, sElo, sEhi);
 }
 
 // Batch of geometries advanced by one launch: tiles of all geometries form
