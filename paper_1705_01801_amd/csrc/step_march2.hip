@@ -66,6 +66,24 @@ struct M2Lds {
 
 __device__ inline int wrap(int i, int n) { return ((i % n) + n) % n; }
 
+// The lane's link data passed through an empty asm statement once per plane:
+// the compiler then derives the lane masks it selects with where they are
+// used, instead of keeping some thirty of them in scalar registers for the
+// whole march (more than the scalar file holds: the rest would be spilled
+// to vector lanes and read back twice per use).
+__device__ __forceinline__ void opaque_xy(Links& k) {
+    asm volatile("" : "+v"(k.jx_p), "+v"(k.jx_m), "+v"(k.jy_p), "+v"(k.jy_m), "+v"(k.wx_p), "+v"(k.wx_m),
+                 "+v"(k.wy_p), "+v"(k.wy_m));
+}
+__device__ __forceinline__ void opaque_y(Links& k) {
+    asm volatile("" : "+v"(k.jy_p), "+v"(k.jy_m), "+v"(k.wy_p), "+v"(k.wy_m));
+}
+__device__ __forceinline__ bool opaque_bool(bool b) {
+    int v = b;
+    asm volatile("" : "+v"(v));
+    return v != 0;
+}
+
 template <int TX, int TY>
 __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& pr, int64_t t, const MarchPlan& plan,
                                             int tile, const float* __restrict__ fin, float* __restrict__ fout,
@@ -131,15 +149,25 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     const __amdgpu_buffer_rsrc_t rtab = make_rsrc(g.tab, (uint32_t)n0 * (uint32_t)n2 * 32u);
 
     // march plane -> real plane (-1 beyond a wall); in the plane loop the
-    // real plane is carried along and offset by a few planes without a
-    // division (rstep)
+    // real planes of z - 2, z, z + 2 and z + 3 are carried along and
+    // advanced by one plane each (radv: one compare and select, no division)
     auto rplane = [&](int z) -> int { return perz ? wrap(z, n2) : (z >= 0 && z < n2 ? z : -1); };
-    auto rstep = [&](int zr, int z, int d) -> int {
-        if (!perz) return z + d >= 0 && z + d < n2 ? z + d : -1;
-        int v = zr + d;
-        while (v >= n2) v -= n2;
-        while (v < 0) v += n2;
-        return v;
+    // r: real plane of march plane zn - 1; returns that of zn
+    auto radv = [&](int r, int zn) -> int {
+        const int up = r + 1 == n2 ? 0 : r + 1;
+        return perz ? up : (zn >= 0 && zn < n2 ? zn : -1);
+    };
+    // axis-2 links of real plane r (as link_coord gives them), from the two
+    // ends' rules computed once
+    const int bz_lo = g.bc_lo[2], bz_hi = g.bc_hi[2];
+    const int jzp_end = bz_hi == LBW_BC_PERIODIC ? 0 : -1, wzp_end = bz_hi == LBW_BC_PERIODIC ? 0 : bz_hi;
+    const int jzm_end = bz_lo == LBW_BC_PERIODIC ? n2 - 1 : -1, wzm_end = bz_lo == LBW_BC_PERIODIC ? 0 : bz_lo;
+    auto zlinks = [&](int r, Links& k) {
+        const bool up = r + 1 < n2, dn = r > 0;
+        k.jz_p = up ? r + 1 : jzp_end;
+        k.wz_p = up ? 0 : wzp_end;
+        k.jz_m = dn ? r - 1 : jzm_end;
+        k.wz_m = dn ? 0 : wzm_end;
     };
     auto erow_r = [&](int zr, float4& lo, float4& hi) {
         const bool on = erow_on && zr >= 0;
@@ -175,6 +203,9 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         }
     }
 
+    __syncthreads();  // the tile's probe list complete
+    const int tile_probes = __builtin_amdgcn_readfirstlane(min(L.pcount, kTileProbes));
+
     // ---- prologue: planes za0 - 1 (S only) and za0 (own column, ring,
     // staged S); coefficient rows za0 - 1 .. za0 + 1; in flight into the
     // loop: own column of plane za0 + 1, ring of plane za0 + 1, coefficient
@@ -208,7 +239,8 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     }
     float4 e_nlo, e_nhi;
     erow_r(rplane(za0 + 2), e_nlo, e_nhi);
-    int zrr = rplane(za0);  // real plane of the march plane (carried along)
+    // real planes of march planes z, z + 2, z + 3 and z - 2 (carried along)
+    int zrr = rplane(za0), zr2 = rplane(za0 + 2), zr3 = rplane(za0 + 3), zrb = rplane(za0 - 2);
 
     // state at t+1 of planes z-2 (for step B), z-1 and z (being assembled),
     // and S(t+1) of planes z-3 .. z-1
@@ -224,15 +256,15 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     float pend_v1w = 0.f, pend_v2w = 0.f;
     int pend_slot = 0;
     const int bo = (ly - 1) * TX + lx;  // step B hand-over slot
-    auto flush_pending = [&]() {
+    auto flush_pending = [&](const Links& k, bool onB) {
         const float* B0 = L.B[pend_slot][0];
         const float* B1 = L.B[pend_slot][1];
         const float from_left = B0[lx > 0 && actB ? bo - 1 : TY * TX];
         const float from_right = B1[lx < TX - 1 && actB ? bo + 1 : TY * TX];
-        const float in1 = kl.jx_m >= 0 ? from_left : pend_v2w;
-        const float in2 = kl.jx_p >= 0 ? from_right : pend_v1w;
-        bst(rout, pend && actB ? 1u * N4 + pend_nb : kOff, in1);
-        bst(rout, pend && actB ? 2u * N4 + pend_nb : kOff, in2);
+        const float in1 = k.jx_m >= 0 ? from_left : pend_v2w;
+        const float in2 = k.jx_p >= 0 ? from_right : pend_v1w;
+        bst(rout, pend && onB ? 1u * N4 + pend_nb : kOff, in1);
+        bst(rout, pend && onB ? 2u * N4 + pend_nb : kOff, in2);
     };
 
     const int zend = z1 + 2;
@@ -247,27 +279,30 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         const int sb = (z - za0) & 1;
         const bool doA = z < za1;
         const int zr = zrr;
+        Links kp = kl, krp = kr;
+        opaque_xy(kp);
+        opaque_y(krp);
+        const bool pA = opaque_bool(actA), pB = opaque_bool(actB), pR = opaque_bool(ring_on);
         // loads consumed later: own column and ring of plane z+2 (S(t) of
         // plane z+1 comes from fnx), coefficient row z+3
         {
-            const int zq = rstep(zr, z, 2);
+            const int zq = zr2;
             const bool on = z + 2 <= za1 && zq >= 0;
-            bload7(rin, N4, actA && on, col4 + (uint32_t)zq * plane4, fnn);
-            bload7(rin, N4, ring_on && on, ring4 + (uint32_t)zq * plane4, rnn);
+            bload7(rin, N4, pA && on, col4 + (uint32_t)zq * plane4, fnn);
+            bload7(rin, N4, pR && on, ring4 + (uint32_t)zq * plane4, rnn);
         }
         float4 e3lo, e3hi;
-        erow_r(rstep(zr, z, 3), e3lo, e3hi);
+        erow_r(zr3, e3lo, e3hi);
         Sp = sum7(fnx);
         const float Srp = sum7(rn);
         __syncthreads();  // S(t) of plane z, coefficient rows up to z+2, step B's hand-over visible
-        if (pend) flush_pending();  // uniform
+        if (pend) flush_pending(kp, pB);  // uniform
         pend = false;
 
         if (doA) {
-            Links k = kl;
-            k.wz_p = k.wz_m = 0;
-            k.jz_p = zr >= 0 ? link_coord(zr, +1, n2, g.bc_lo[2], g.bc_hi[2], &k.wz_p) : -1;
-            k.jz_m = zr >= 0 ? link_coord(zr, -1, n2, g.bc_lo[2], g.bc_hi[2], &k.wz_m) : -1;
+            // (a step-A plane is always a real one: zr >= 0)
+            Links k = kp;
+            zlinks(zr, k);
             const float* Ls = L.S[sb];
             const float4 e_lo = L.Elo[z & 7][lx + 1], e_hi = L.Ehi[z & 7][lx + 1];
             const float4 enp = L.Elo[z & 7][lx + 2], enm = L.Elo[z & 7][lx];
@@ -284,13 +319,16 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             // the ring rows -1 and TY+2 (threads of the first 2 TX, whole
             // waves) send f*_3 (row -1, into row 0) and f*_4 (row TY+2, into
             // row TY+1): the axis-1 part of their collision
-            if (threadIdx.x < 2 * TX) {
+            // (2 TX is a multiple of 64: whole waves, tested as such)
+            if (__builtin_amdgcn_readfirstlane((int)threadIdx.x) < 2 * TX) {
                 const int ri = (re + 2) * W + lx + 1;
                 float rs3, rs4;
-                collide_axis1(rc[3], rc[4], sum7(rc), e_lo.w, Ls[ri + W], Ls[ri - W], kr, c2, rs3, rs4);
+                collide_axis1(rc[3], rc[4], sum7(rc), e_lo.w, Ls[ri + W], Ls[ri - W], krp, c2, rs3, rs4);
                 const int ro = (re + 1) * W + lx + 1;
-                if (rid == 0) L.X[2][ring_col ? ro : C::XROWS * W] = rs3;
-                else L.X[3][ring_col ? ro : C::XROWS * W] = rs4;
+                // (row -1 sends f*_3 through X[2], row TY+2 f*_4 through X[3];
+                // one store by index, no branch)
+                constexpr int xs = C::XROWS * W + 1;
+                (&L.X[0][0])[(rid == 0 ? 2 * xs : 3 * xs) + (ring_col ? ro : C::XROWS * W)] = rid == 0 ? rs3 : rs4;
             }
             __syncthreads();  // handed-over populations visible
             f2[0] = fs[0];
@@ -312,11 +350,9 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         // step B on plane zb = z - 2
         const int zb = z - 2;
         if (zb >= z0 && zb < z1) {
-            const int zbr = rstep(zr, z, -2);
-            Links k = kl;
-            k.wz_p = k.wz_m = 0;
-            k.jz_p = link_coord(zbr, +1, n2, g.bc_lo[2], g.bc_hi[2], &k.wz_p);
-            k.jz_m = link_coord(zbr, -1, n2, g.bc_lo[2], g.bc_hi[2], &k.wz_m);
+            const int zbr = zrb;
+            Links k = kp;
+            zlinks(zbr, k);
             const float* L1 = L.S1[zb & 1];
             // (threads off the tile's rows read row 1 instead: every index stays in the array)
             const int s1 = (actB ? ly : 1) * W + lx + 1;
@@ -328,9 +364,8 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             collide(f0, S1b, e_lo, e_hi, enp, enm, ezp, make_float2(ezm.y, ezm.z), L1[s1 + 1], L1[s1 - 1],
                     L1[s1 + W], L1[s1 - W], S1c, S1a, k, c2, two_w0, fs);
             // probes at t+1 on this plane (the state f0 before step B)
-            if (L.pcount > 0) {
-                const int np = min(L.pcount, kTileProbes);
-                for (int i = 0; i < np; ++i) {
+            if (tile_probes > 0) {
+                for (int i = 0; i < tile_probes; ++i) {
                     if (actB && L.pz[i] == zbr && L.py[i] == ya && L.px[i] == lx) {
                         double s = 0.0;
                         for (int l = 0; l < 7; ++l) s += (double)f0[l];
@@ -357,11 +392,11 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             const float v4 = k.jy_m >= 0 ? fs[4] : bounce(k.wy_m, damp, fs[4], fs[3]);
             const float v5 = k.jz_p >= 0 ? fs[5] : bounce(k.wz_p, damp, fs[5], fs[6]);
             const float v6 = k.jz_m >= 0 ? fs[6] : bounce(k.wz_m, damp, fs[6], fs[5]);
-            bst(rout, actB ? nb : kOff, fs[0]);
-            bst(rout, actB ? o3 : kOff, v3);
-            bst(rout, actB ? o4 : kOff, v4);
-            bst(rout, actB ? o5 : kOff, v5);
-            bst(rout, actB ? o6 : kOff, v6);
+            bst(rout, pB ? nb : kOff, fs[0]);
+            bst(rout, pB ? o3 : kOff, v3);
+            bst(rout, pB ? o4 : kOff, v4);
+            bst(rout, pB ? o5 : kOff, v5);
+            bst(rout, pB ? o6 : kOff, v6);
         }
         S1a = S1b;
         S1b = S1c;
@@ -377,7 +412,10 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         e_nhi = e3hi;
         Sm = Sc;
         Sc = Sp;
-        zrr = rstep(zr, z, 1);
+        zrr = radv(zr, z + 1);
+        zr2 = radv(zr2, z + 3);
+        zr3 = radv(zr3, z + 4);
+        zrb = radv(zrb, z - 1);
     };
     for (int z = za0;;) {
         if (z >= zend) break;
@@ -389,7 +427,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         ++z;
     }
     __syncthreads();  // the last plane's hand-over visible
-    if (pend) flush_pending();
+    if (pend) flush_pending(kl, actB);
     __syncthreads();  // LDS reuse by the next tile
 }
 
