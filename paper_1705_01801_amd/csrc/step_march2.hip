@@ -237,8 +237,12 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         bload7(rin, N4, actA && on, col4 + (uint32_t)zn * plane4, fB);
         bload7(rin, N4, ring_on && on, ring4 + (uint32_t)zn * plane4, rB);
     }
-    float4 e_nlo, e_nhi;
-    erow_r(rplane(za0 + 2), e_nlo, e_nhi);
+    // coefficient rows in flight: eA holds row za0 + 2 for the first plane;
+    // each plane stages the row loaded one plane earlier and loads the next
+    // into the following slot (period three, by argument order, so no
+    // register holding a load in flight is ever copied)
+    float4 eA[2], eB[2], eC[2];
+    erow_r(rplane(za0 + 2), eA[0], eA[1]);
     // real planes of march planes z, z + 2, z + 3 and z - 2 (carried along)
     int zrr = rplane(za0), zr2 = rplane(za0 + 2), zr3 = rplane(za0 + 3), zrb = rplane(za0 - 2);
 
@@ -275,7 +279,8 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     // rc / rn / rnn the ring's; the caller rotates all of them by argument
     // order (period three), so no register is copied.
     auto march_plane = [&](float (&f0)[7], float (&f1)[7], float (&f2)[7], float (&fc)[7], float (&fnx)[7],
-                           float (&fnn)[7], float (&rc)[7], float (&rn)[7], float (&rnn)[7], int z) {
+                           float (&fnn)[7], float (&rc)[7], float (&rn)[7], float (&rnn)[7], float4 (&en)[2],
+                           float4 (&e3)[2], int z) {
         const int sb = (z - za0) & 1;
         const bool doA = z < za1;
         const int zr = zrr;
@@ -291,8 +296,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             bload7(rin, N4, pA && on, col4 + (uint32_t)zq * plane4, fnn);
             bload7(rin, N4, pR && on, ring4 + (uint32_t)zq * plane4, rnn);
         }
-        float4 e3lo, e3hi;
-        erow_r(zr3, e3lo, e3hi);
+        erow_r(zr3, e3[0], e3[1]);
         Sp = sum7(fnx);
         const float Srp = sum7(rn);
         __syncthreads();  // S(t) of plane z, coefficient rows up to z+2, step B's hand-over visible
@@ -406,10 +410,8 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         if (z + 1 < zend) {
             L.S[sb ^ 1][actA ? my_s : sinkS] = Sp;
             L.S[sb ^ 1][ring_s] = Srp;
-            stage_erow(z + 2, e_nlo, e_nhi);
+            stage_erow(z + 2, en[0], en[1]);
         }
-        e_nlo = e3lo;
-        e_nhi = e3hi;
         Sm = Sc;
         Sc = Sp;
         zrr = radv(zr, z + 1);
@@ -419,11 +421,17 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     };
     for (int z = za0;;) {
         if (z >= zend) break;
-        march_plane(fa, fb, fz, fA, fB, fC, rA, rB, rC, z);
+        march_plane(fa, fb, fz, fA, fB, fC, rA, rB, rC, eA, eB, z);
         if (++z >= zend) break;
-        march_plane(fb, fz, fa, fB, fC, fA, rB, rC, rA, z);
+        march_plane(fb, fz, fa, fB, fC, fA, rB, rC, rA, eB, eC, z);
         if (++z >= zend) break;
-        march_plane(fz, fa, fb, fC, fA, fB, rC, rA, rB, z);
+        march_plane(fz, fa, fb, fC, fA, fB, rC, rA, rB, eC, eA, z);
+        if (++z >= zend) break;
+        march_plane(fa, fb, fz, fA, fB, fC, rA, rB, rC, eA, eB, z);
+        if (++z >= zend) break;
+        march_plane(fb, fz, fa, fB, fC, fA, rB, rC, rA, eB, eC, z);
+        if (++z >= zend) break;
+        march_plane(fz, fa, fb, fC, fA, fB, rC, rA, rB, eC, eA, z);
         ++z;
     }
     __syncthreads();  // the last plane's hand-over visible
