@@ -119,12 +119,12 @@ struct Links {
 __device__ __forceinline__ void collide_axis1(float f3, float f4, float S, float cM11, float Syp, float Sym,
                                               const Links& k, float c2, float& fs3, float& fs4) {
 #pragma clang fp contract(off)
-    const float A11p = cM11 * (k.jy_p >= 0 ? Syp : ghost(k.wy_p, S));
-    const float A11m = cM11 * (k.jy_m >= 0 ? Sym : ghost(k.wy_m, S));
-    const float K1 = (f3 - f4) - 0.25f * (A11p - A11m);
-    const float cs = c2 * S;
-    fs3 = cs + K1 - f3;
-    fs4 = cs - K1 - f4;
+    const float sp = k.jy_p >= 0 ? Syp : ghost(k.wy_p, S);
+    const float sm = k.jy_m >= 0 ? Sym : ghost(k.wy_m, S);
+    const float dA = __builtin_fmaf(cM11, sp, -(cM11 * sm));  // A11 above minus below
+    const float K1 = __builtin_fmaf(-0.25f, dA, f3 - f4);
+    fs3 = __builtin_fmaf(c2, S, K1) - f3;
+    fs4 = __builtin_fmaf(c2, S, -K1) - f4;
 }
 
 // Collision at one node (Sec. II evolution equation at tau = 1/2 with the
@@ -143,42 +143,38 @@ __device__ __forceinline__ void collide(const float (&fc)[7], float S, float4 e_
                                         float4 enm, float4 ezp, float2 em, float Sxp, float Sxm, float Syp,
                                         float Sym, float Sp, float Sm, const Links& k, float c2, float two_w0,
                                         float (&fs)[7]) {
-    // every product and sum rounded on its own (no fused multiply-add), so
-    // the result does not depend on how the surrounding kernel is compiled
+    // Every rounding is fixed by the source, not by the compiler: fused
+    // multiply-adds only where written (each difference of A terms is one
+    // product and one fused multiply-add, each K and f* sum takes the
+    // products fused), every other product and sum rounded on its own.  So
+    // every kernel that calls this gets the same bits for a node.
 #pragma clang fp contract(off)
     const float cM00 = e_lo.x, cM02 = e_lo.y, cM22 = e_lo.z, cM11 = e_lo.w;
     const float hG0 = e_hi.x, hG2 = e_hi.y;
-    const float gxp = ghost(k.wx_p, S), gxm = ghost(k.wx_m, S);
-    const float A00p = k.jx_p >= 0 ? enp.x * Sxp : cM00 * gxp;
-    const float A20p = k.jx_p >= 0 ? enp.y * Sxp : cM02 * gxp;
-    const float A00m = k.jx_m >= 0 ? enm.x * Sxm : cM00 * gxm;
-    const float A20m = k.jx_m >= 0 ? enm.y * Sxm : cM02 * gxm;
-    float A22p, A22m, A02p, A02m;
-    if (k.jz_p >= 0) {
-        A02p = ezp.y * Sp;
-        A22p = ezp.z * Sp;
-    } else {
-        const float sg = ghost(k.wz_p, S);
-        A22p = cM22 * sg;
-        A02p = cM02 * sg;
-    }
-    if (k.jz_m >= 0) {
-        A02m = em.x * Sm;
-        A22m = em.y * Sm;
-    } else {
-        const float sg = ghost(k.wz_m, S);
-        A22m = cM22 * sg;
-        A02m = cM02 * sg;
-    }
-    const float K0 = (fc[1] - fc[2]) - hG0 * S - 0.25f * (A00p - A00m) - 0.25f * (A02p - A02m);
-    const float K2 = (fc[5] - fc[6]) - hG2 * S - 0.25f * ((A22p - A22m) + (A20p - A20m));
-    const float cs = c2 * S;
-    fs[0] = two_w0 * S - fc[0];
-    fs[1] = cs + K0 - fc[1];
-    fs[2] = cs - K0 - fc[2];
+    // the neighbour's coefficient and S where the link exists, the node's
+    // own coefficient and its mirrored S beyond a wall
+    const bool xp = k.jx_p >= 0, xm = k.jx_m >= 0;
+    const float sxp = xp ? Sxp : ghost(k.wx_p, S), sxm = xm ? Sxm : ghost(k.wx_m, S);
+    const float c00p = xp ? enp.x : cM00, c20p = xp ? enp.y : cM02;
+    const float c00m = xm ? enm.x : cM00, c20m = xm ? enm.y : cM02;
+    const bool zp = k.jz_p >= 0, zm = k.jz_m >= 0;
+    const float szp = zp ? Sp : ghost(k.wz_p, S), szm = zm ? Sm : ghost(k.wz_m, S);
+    const float c02p = zp ? ezp.y : cM02, c22p = zp ? ezp.z : cM22;
+    const float c02m = zm ? em.x : cM02, c22m = zm ? em.y : cM22;
+    const float d00 = __builtin_fmaf(c00p, sxp, -(c00m * sxm));
+    const float d20 = __builtin_fmaf(c20p, sxp, -(c20m * sxm));
+    const float d02 = __builtin_fmaf(c02p, szp, -(c02m * szm));
+    const float d22 = __builtin_fmaf(c22p, szp, -(c22m * szm));
+    float K0 = __builtin_fmaf(-hG0, S, fc[1] - fc[2]);
+    K0 = __builtin_fmaf(-0.25f, d00, K0);
+    K0 = __builtin_fmaf(-0.25f, d02, K0);
+    const float K2 = __builtin_fmaf(-0.25f, d22 + d20, __builtin_fmaf(-hG2, S, fc[5] - fc[6]));
+    fs[0] = __builtin_fmaf(two_w0, S, -fc[0]);
+    fs[1] = __builtin_fmaf(c2, S, K0) - fc[1];
+    fs[2] = __builtin_fmaf(c2, S, -K0) - fc[2];
     collide_axis1(fc[3], fc[4], S, cM11, Syp, Sym, k, c2, fs[3], fs[4]);
-    fs[5] = cs + K2 - fc[5];
-    fs[6] = cs - K2 - fc[6];
+    fs[5] = __builtin_fmaf(c2, S, K2) - fc[5];
+    fs[6] = __builtin_fmaf(c2, S, -K2) - fc[6];
 }
 
 }  // namespace march
