@@ -111,6 +111,10 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     const int ya = pery ? wrap(yr, n1) : yr;
     const bool actA = lx < n0 && ypres;
     const bool actB = actA && ly >= 1 && ly <= hgt;
+    // waves with no lane on the tile's own rows (all in the halo rows) skip
+    // step B altogether (it has no barrier; its hand-over slots are read
+    // only by lanes of the same row, which are on the tile's rows)
+    const bool waveB = __builtin_amdgcn_ballot_w64(actB) != 0;
     Links kl{};
     kl.jx_p = link_coord(lx, +1, n0, g.bc_lo[0], g.bc_hi[0], &kl.wx_p);
     kl.jx_m = link_coord(lx, -1, n0, g.bc_lo[0], g.bc_hi[0], &kl.wx_m);
@@ -353,7 +357,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
 
         // step B on plane zb = z - 2
         const int zb = z - 2;
-        if (zb >= z0 && zb < z1) {
+        if (zb >= z0 && zb < z1 && waveB) {
             const int zbr = zrb;
             Links k = kp;
             zlinks(zbr, k);
