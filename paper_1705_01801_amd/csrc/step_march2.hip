@@ -75,6 +75,9 @@ __device__ __forceinline__ void opaque_xy(Links& k) {
     asm volatile("" : "+v"(k.jx_p), "+v"(k.jx_m), "+v"(k.jy_p), "+v"(k.jy_m), "+v"(k.wx_p), "+v"(k.wx_m),
                  "+v"(k.wy_p), "+v"(k.wy_m));
 }
+__device__ __forceinline__ void opaque_x(Links& k) {
+    asm volatile("" : "+v"(k.jx_p), "+v"(k.jx_m), "+v"(k.wx_p), "+v"(k.wx_m));
+}
 __device__ __forceinline__ void opaque_y(Links& k) {
     asm volatile("" : "+v"(k.jy_p), "+v"(k.jy_m), "+v"(k.wy_p), "+v"(k.wy_m));
 }
@@ -84,7 +87,9 @@ __device__ __forceinline__ bool opaque_bool(bool b) {
     return v != 0;
 }
 
-template <int TX, int TY>
+// PERY: axis 1 is periodic (every axis-1 link present; the wall rules of
+// that axis are compiled out).
+template <int TX, int TY, bool PERY>
 __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& pr, int64_t t, const MarchPlan& plan,
                                             int tile, const float* __restrict__ fin, float* __restrict__ fout,
                                             M2Lds<TX, TY>& L) {
@@ -100,7 +105,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     if (z0 >= n2) return;  // uniform per block
     const int z1 = min(z0 + plan.lz, n2);
     const int hgt = min(TY, n1 - y0);
-    const bool perz = g.bc_lo[2] == LBW_BC_PERIODIC, pery = g.bc_lo[1] == LBW_BC_PERIODIC;
+    const bool perz = g.bc_lo[2] == LBW_BC_PERIODIC, pery = PERY;
     // step A runs on march planes [za0, za1); the march runs on [za0, z1 + 2)
     const int za0 = perz ? z0 - 2 : max(z0 - 2, 0);
     const int za1 = perz ? z1 + 2 : min(z1 + 2, n2);
@@ -121,6 +126,8 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     kl.jy_p = ypres ? link_coord(ya, +1, n1, g.bc_lo[1], g.bc_hi[1], &kl.wy_p) : -1;
     kl.jy_m = ypres ? link_coord(ya, -1, n1, g.bc_lo[1], g.bc_hi[1], &kl.wy_m) : -1;
     const uint32_t col4 = actA ? ((uint32_t)lx + (uint32_t)n0 * (uint32_t)ya) * 4u : 0u;
+    // byte offsets to the axis-1 neighbours' columns (used where the link exists)
+    const uint32_t dyp4 = (uint32_t)((kl.jy_p - ya) * n0) * 4u, dym4 = (uint32_t)((kl.jy_m - ya) * n0) * 4u;
 
     // ring loader: rows -1 and TY+2 (loaded and collided: they send +e1 / -e1
     // into the halo rows), rows -2 and TY+3 (loaded for S only)
@@ -289,8 +296,14 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         const bool doA = z < za1;
         const int zr = zrr;
         Links kp = kl, krp = kr;
-        opaque_xy(kp);
-        opaque_y(krp);
+        if constexpr (PERY) {
+            kp.jy_p = kp.jy_m = kp.wy_p = kp.wy_m = 0;
+            krp.jy_p = krp.jy_m = krp.wy_p = krp.wy_m = 0;
+            opaque_x(kp);
+        } else {
+            opaque_xy(kp);
+            opaque_y(krp);
+        }
         const bool pA = opaque_bool(actA), pB = opaque_bool(actB), pR = opaque_bool(ring_on);
         // loads consumed later: own column and ring of plane z+2 (S(t) of
         // plane z+1 comes from fnx), coefficient row z+3
@@ -392,8 +405,8 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             pend_nb = nb;
             pend_v1w = bounce(k.wx_p, damp, fs[1], fs[2]);  // +e0 at the far wall, returned as -e0
             pend_v2w = bounce(k.wx_m, damp, fs[2], fs[1]);  // -e0 at the near wall, returned as +e0
-            const uint32_t o3 = k.jy_p >= 0 ? 3u * N4 + nb + (uint32_t)((k.jy_p - ya) * n0) * 4u : 4u * N4 + nb;
-            const uint32_t o4 = k.jy_m >= 0 ? 4u * N4 + nb + (uint32_t)((k.jy_m - ya) * n0) * 4u : 3u * N4 + nb;
+            const uint32_t o3 = k.jy_p >= 0 ? 3u * N4 + nb + dyp4 : 4u * N4 + nb;
+            const uint32_t o4 = k.jy_m >= 0 ? 4u * N4 + nb + dym4 : 3u * N4 + nb;
             const uint32_t o5 = k.jz_p >= 0 ? 5u * N4 + col4 + (uint32_t)k.jz_p * plane4 : 6u * N4 + nb;
             const uint32_t o6 = k.jz_m >= 0 ? 6u * N4 + col4 + (uint32_t)k.jz_m * plane4 : 5u * N4 + nb;
             const float v3 = k.jy_p >= 0 ? fs[3] : bounce(k.wy_p, damp, fs[3], fs[4]);
@@ -443,7 +456,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     __syncthreads();  // LDS reuse by the next tile
 }
 
-template <int TX, int TY>
+template <int TX, int TY, bool PERY>
 __global__ __launch_bounds__(TX * (TY + 2)) void step_march2_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
                                                                     const float* __restrict__ fin,
                                                                     float* __restrict__ fout) {
@@ -463,7 +476,7 @@ __global__ __launch_bounds__(TX * (TY + 2)) void step_march2_kernel(GeomDev g, P
     const int t_begin = (int)(plan.tiles * xcd / kXcds);
     const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
     for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
-        march2_tile<TX, TY>(g, pr, t, plan, tile, fin, fout, L);
+        march2_tile<TX, TY, PERY>(g, pr, t, plan, tile, fin, fout, L);
     // the last workgroup to finish advances the step counter by two (every
     // workgroup read it before counting itself done)
     __syncthreads();
@@ -481,7 +494,7 @@ __global__ __launch_bounds__(TX * (TY + 2)) void step_march2_kernel(GeomDev g, P
 template <int TX, int TY>
 int blocks_per_cu2() {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march2_kernel<TX, TY>, TX * (TY + 2), 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march2_kernel<TX, TY, false>, TX * (TY + 2), 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
@@ -525,10 +538,15 @@ hipError_t launch_step_march2(const GeomDev& g, const ProbeArgs& pr, const March
                               float* fout, hipStream_t st) {
     if (!march2_shape_ok(plan.tx, plan.ty) || !march2_fits(g, plan.tx) || !pr.tdone) return hipErrorInvalidValue;
     const dim3 grid(plan.blocks), block(plan.tx * (plan.ty + 2));
-    if (plan.tx == 96)
-        hipLaunchKernelGGL((step_march2_kernel<96, 6>), grid, block, 0, st, g, pr, plan, fin, fout);
+    const bool pery = g.bc_lo[1] == LBW_BC_PERIODIC;
+    if (plan.tx == 96 && pery)
+        hipLaunchKernelGGL((step_march2_kernel<96, 6, true>), grid, block, 0, st, g, pr, plan, fin, fout);
+    else if (plan.tx == 96)
+        hipLaunchKernelGGL((step_march2_kernel<96, 6, false>), grid, block, 0, st, g, pr, plan, fin, fout);
+    else if (pery)
+        hipLaunchKernelGGL((step_march2_kernel<128, 4, true>), grid, block, 0, st, g, pr, plan, fin, fout);
     else
-        hipLaunchKernelGGL((step_march2_kernel<128, 4>), grid, block, 0, st, g, pr, plan, fin, fout);
+        hipLaunchKernelGGL((step_march2_kernel<128, 4, false>), grid, block, 0, st, g, pr, plan, fin, fout);
     return hipGetLastError();
 }
 
