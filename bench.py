@@ -6,9 +6,13 @@ working set fits the 256 MB Infinity Cache) and the horn (128 x 128 x 512)
 are timed as extra legs.
 
 Prints one JSON line.  value = whole-job MLUPS (node updates per second / 1e6)
-with the state resident in device memory; roofline = algorithmic bytes per
-launch (56 B per node: 7 float populations read and written) over the
-measured average launch duration, against 8 TB/s; surrogate = shape-spectra
+with the state resident in device memory, after the library's autotuner has
+chosen the launch (one step per launch, or two with the temporally blocked
+kernel where that is faster); roofline = algorithmic bytes per launch (56 B
+per node update: 7 float populations read and written, times the updates a
+launch makes) over the measured average launch duration, against 8 TB/s,
+beside the HBM bytes per launch the committed counters measured for that
+kernel (about half the algorithmic ones for two steps per launch); surrogate = shape-spectra
 per second of the plain per-shape LBM, the batched LBM and the trained
 surrogate with every fallback candidate simulated; cpu_baseline = the FP64
 oracle on the host for a bounded number of steps of the headline grid.
@@ -25,32 +29,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM peak; shape-spectra/sec batched+surrogate vs plain LBM"
 HBM_PEAK_GBS = 8000.0
-# committed counter summaries per configuration, and the kernel sources they cover
+# committed counter summaries per configuration and steps per launch (one
+# step, or two with the two-step kernel), and the kernel sources they cover
 _MARCH = ("step_march.hip", "march_common.h", "step.hip", "lbw_internal.h")
-TRAFFIC = {1: ("traffic_step_cylinder_128x128x256.txt", _MARCH),
-           2: ("traffic_step_horn_128x128x512.txt", _MARCH),
-           3: ("traffic_step_torus_96x256x512.txt", _MARCH),
-           4: ("traffic_step_general_duct_128x128x128.txt", ("step_general.hip", "lbw_internal.h"))}
+_MARCH2 = ("step_march2.hip", "march_common.h", "lbw_internal.h")
+TRAFFIC = {(1, 1): ("traffic_step_cylinder_128x128x256.txt", _MARCH),
+           (2, 1): ("traffic_step_horn_128x128x512.txt", _MARCH),
+           (3, 1): ("traffic_step_torus_96x256x512.txt", _MARCH),
+           (4, 1): ("traffic_step_general_duct_128x128x128.txt", ("step_general.hip", "lbw_internal.h")),
+           (2, 2): ("traffic_step2_horn_128x128x512.txt", _MARCH2),
+           (3, 2): ("traffic_step2_torus_96x256x512.txt", _MARCH2)}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(config: int = 1):
+def kernel_source_hash(config: int = 1, steps_per_launch: int = 1):
     h = hashlib.sha256()
-    for name in TRAFFIC[config][1]:
+    for name in TRAFFIC[(config, steps_per_launch)][1]:
         with open(os.path.join(ROOT, "paper_1705_01801_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(config: int = 1):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this configuration, if it was taken on the current kernel source."""
-    if config not in TRAFFIC:
+def read_traffic(config: int = 1, steps_per_launch: int = 1):
+    """HBM bytes per launch (of one or two steps) from the committed
+    rocprofv3 counter summary of this configuration and kernel, if it was
+    taken on the current kernel source."""
+    key = (config, steps_per_launch)
+    if key not in TRAFFIC:
         return None
-    path = os.path.join(ROOT, "profiles", TRAFFIC[config][0])
+    path = os.path.join(ROOT, "profiles", TRAFFIC[key][0])
     if not os.path.exists(path):
         return None
     vals = {}
@@ -58,7 +68,7 @@ def read_traffic(config: int = 1):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash(config):
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(config, steps_per_launch):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -133,8 +143,9 @@ def time_config(config, steps, warmup, launch="auto", two_step=None):
     out = {"workload": w["name"], "nodes": N, "ms_per_step": round(ms_per_step, 5),
            "mlups": round(N * steps / (ms / 1e3) / 1e6, 1), "achieved_gbs": round(achieved, 1),
            "frac": round(achieved / HBM_PEAK_GBS, 4),
-           # the committed counters are the one-step kernel's
-           "traffic": None if two[0] else read_traffic(config),
+           # HBM bytes per launch of the kernel that ran (two steps per
+           # launch with the two-step kernel; achieved_gbs covers the same)
+           "traffic": read_traffic(config, 2 if two[0] else 1),
            "residency": "infinity-cache" if working_set <= INFINITY_CACHE_BYTES else "hbm",
            "working_set_bytes": working_set, "probes": int(len(w["probes"])), "c": geom["c"],
            "launch": {"tile_x": tile[0], "tile_y": tile[1], "chunk_z": tile[2], "blocks": tile[3],
