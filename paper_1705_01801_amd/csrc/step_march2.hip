@@ -66,30 +66,23 @@ struct M2Lds {
 
 __device__ inline int wrap(int i, int n) { return ((i % n) + n) % n; }
 
-// The lane's link data passed through an empty asm statement once per plane:
-// the compiler then derives the lane masks it selects with where they are
-// used, instead of keeping some thirty of them in scalar registers for the
-// whole march (more than the scalar file holds: the rest would be spilled
-// to vector lanes and read back twice per use).
-__device__ __forceinline__ void opaque_xy(Links& k) {
-    asm volatile("" : "+v"(k.jx_p), "+v"(k.jx_m), "+v"(k.jy_p), "+v"(k.jy_m), "+v"(k.wx_p), "+v"(k.wx_m),
-                 "+v"(k.wy_p), "+v"(k.wy_m));
-}
-__device__ __forceinline__ void opaque_x(Links& k) {
-    asm volatile("" : "+v"(k.jx_p), "+v"(k.jx_m), "+v"(k.wx_p), "+v"(k.wx_m));
-}
-__device__ __forceinline__ void opaque_y(Links& k) {
-    asm volatile("" : "+v"(k.jy_p), "+v"(k.jy_m), "+v"(k.wy_p), "+v"(k.wy_m));
-}
+// The lane's link indices (axis 0, axis 1) and activity flags passed
+// through an empty asm statement once per plane: the compiler then derives
+// the lane masks it selects with where they are used, instead of keeping
+// them all in scalar registers for the whole march (more than the scalar
+// file holds: the rest would be spilled to vector lanes and read back twice
+// per use).
+__device__ __forceinline__ void opaque_jx(Links& k) { asm volatile("" : "+v"(k.jx_p), "+v"(k.jx_m)); }
+__device__ __forceinline__ void opaque_jy(Links& k) { asm volatile("" : "+v"(k.jy_p), "+v"(k.jy_m)); }
 __device__ __forceinline__ bool opaque_bool(bool b) {
     int v = b;
     asm volatile("" : "+v"(v));
     return v != 0;
 }
 
-// PERY: axis 1 is periodic (every axis-1 link present; the wall rules of
-// that axis are compiled out).
-template <int TX, int TY, bool PERY>
+// PERY, PERZ: axis 1, axis 2 is periodic (every link along it present;
+// the wall rules of that axis are compiled out).
+template <int TX, int TY, bool PERY, bool PERZ>
 __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& pr, int64_t t, const MarchPlan& plan,
                                             int tile, const float* __restrict__ fin, float* __restrict__ fout,
                                             M2Lds<TX, TY>& L) {
@@ -126,6 +119,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     kl.jy_p = ypres ? link_coord(ya, +1, n1, g.bc_lo[1], g.bc_hi[1], &kl.wy_p) : -1;
     kl.jy_m = ypres ? link_coord(ya, -1, n1, g.bc_lo[1], g.bc_hi[1], &kl.wy_m) : -1;
     const uint32_t col4 = actA ? ((uint32_t)lx + (uint32_t)n0 * (uint32_t)ya) * 4u : 0u;
+    const int bcx_lo = g.bc_lo[0], bcx_hi = g.bc_hi[0], bcy_lo = g.bc_lo[1], bcy_hi = g.bc_hi[1];
     // byte offsets to the axis-1 neighbours' columns (used where the link exists)
     const uint32_t dyp4 = (uint32_t)((kl.jy_p - ya) * n0) * 4u, dym4 = (uint32_t)((kl.jy_m - ya) * n0) * 4u;
 
@@ -296,13 +290,20 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         const bool doA = z < za1;
         const int zr = zrr;
         Links kp = kl, krp = kr;
+        // a wall code matters only where the link is missing, and there it
+        // is that end's code: every lane takes the end codes, uniform, so
+        // the wall rules are tested on the scalar unit
+        kp.wx_p = bcx_hi;
+        kp.wx_m = bcx_lo;
+        opaque_jx(kp);
         if constexpr (PERY) {
             kp.jy_p = kp.jy_m = kp.wy_p = kp.wy_m = 0;
             krp.jy_p = krp.jy_m = krp.wy_p = krp.wy_m = 0;
-            opaque_x(kp);
         } else {
-            opaque_xy(kp);
-            opaque_y(krp);
+            kp.wy_p = krp.wy_p = bcy_hi;
+            kp.wy_m = krp.wy_m = bcy_lo;
+            opaque_jy(kp);
+            opaque_jy(krp);
         }
         const bool pA = opaque_bool(actA), pB = opaque_bool(actB), pR = opaque_bool(ring_on);
         // loads consumed later: own column and ring of plane z+2 (S(t) of
@@ -324,6 +325,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             // (a step-A plane is always a real one: zr >= 0)
             Links k = kp;
             zlinks(zr, k);
+            if constexpr (PERZ) k.jz_p = k.jz_m = 0;  // (step A uses only their presence)
             const float* Ls = L.S[sb];
             const float4 e_lo = L.Elo[z & 7][lx + 1], e_hi = L.Ehi[z & 7][lx + 1];
             const float4 enp = L.Elo[z & 7][lx + 2], enm = L.Elo[z & 7][lx];
@@ -374,6 +376,8 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             const int zbr = zrb;
             Links k = kp;
             zlinks(zbr, k);
+            const int jzp = k.jz_p, jzm = k.jz_m;  // the stores' planes
+            if constexpr (PERZ) k.jz_p = k.jz_m = 0;
             const float* L1 = L.S1[zb & 1];
             // (threads off the tile's rows read row 1 instead: every index stays in the array)
             const int s1 = (actB ? ly : 1) * W + lx + 1;
@@ -407,8 +411,8 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             pend_v2w = bounce(k.wx_m, damp, fs[2], fs[1]);  // -e0 at the near wall, returned as +e0
             const uint32_t o3 = k.jy_p >= 0 ? 3u * N4 + nb + dyp4 : 4u * N4 + nb;
             const uint32_t o4 = k.jy_m >= 0 ? 4u * N4 + nb + dym4 : 3u * N4 + nb;
-            const uint32_t o5 = k.jz_p >= 0 ? 5u * N4 + col4 + (uint32_t)k.jz_p * plane4 : 6u * N4 + nb;
-            const uint32_t o6 = k.jz_m >= 0 ? 6u * N4 + col4 + (uint32_t)k.jz_m * plane4 : 5u * N4 + nb;
+            const uint32_t o5 = k.jz_p >= 0 ? 5u * N4 + col4 + (uint32_t)jzp * plane4 : 6u * N4 + nb;
+            const uint32_t o6 = k.jz_m >= 0 ? 6u * N4 + col4 + (uint32_t)jzm * plane4 : 5u * N4 + nb;
             const float v3 = k.jy_p >= 0 ? fs[3] : bounce(k.wy_p, damp, fs[3], fs[4]);
             const float v4 = k.jy_m >= 0 ? fs[4] : bounce(k.wy_m, damp, fs[4], fs[3]);
             const float v5 = k.jz_p >= 0 ? fs[5] : bounce(k.wz_p, damp, fs[5], fs[6]);
@@ -456,7 +460,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     __syncthreads();  // LDS reuse by the next tile
 }
 
-template <int TX, int TY, bool PERY>
+template <int TX, int TY, bool PERY, bool PERZ>
 __global__ __launch_bounds__(TX * (TY + 2)) void step_march2_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
                                                                     const float* __restrict__ fin,
                                                                     float* __restrict__ fout) {
@@ -476,7 +480,7 @@ __global__ __launch_bounds__(TX * (TY + 2)) void step_march2_kernel(GeomDev g, P
     const int t_begin = (int)(plan.tiles * xcd / kXcds);
     const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
     for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
-        march2_tile<TX, TY, PERY>(g, pr, t, plan, tile, fin, fout, L);
+        march2_tile<TX, TY, PERY, PERZ>(g, pr, t, plan, tile, fin, fout, L);
     // the last workgroup to finish advances the step counter by two (every
     // workgroup read it before counting itself done)
     __syncthreads();
@@ -494,7 +498,7 @@ __global__ __launch_bounds__(TX * (TY + 2)) void step_march2_kernel(GeomDev g, P
 template <int TX, int TY>
 int blocks_per_cu2() {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march2_kernel<TX, TY, false>, TX * (TY + 2), 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march2_kernel<TX, TY, false, false>, TX * (TY + 2), 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
@@ -534,19 +538,30 @@ MarchPlan make_march2_plan(const GeomDev& g, int tx, int ty, int lz, int blocks)
     return p;
 }
 
+namespace {
+template <int TX, int TY>
+void launch2_of(bool pery, bool perz, dim3 grid, dim3 block, hipStream_t st, const GeomDev& g, const ProbeArgs& pr,
+                const MarchPlan& plan, const float* fin, float* fout) {
+    if (pery && perz)
+        hipLaunchKernelGGL((step_march2_kernel<TX, TY, true, true>), grid, block, 0, st, g, pr, plan, fin, fout);
+    else if (pery)
+        hipLaunchKernelGGL((step_march2_kernel<TX, TY, true, false>), grid, block, 0, st, g, pr, plan, fin, fout);
+    else if (perz)
+        hipLaunchKernelGGL((step_march2_kernel<TX, TY, false, true>), grid, block, 0, st, g, pr, plan, fin, fout);
+    else
+        hipLaunchKernelGGL((step_march2_kernel<TX, TY, false, false>), grid, block, 0, st, g, pr, plan, fin, fout);
+}
+}  // namespace
+
 hipError_t launch_step_march2(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin,
                               float* fout, hipStream_t st) {
     if (!march2_shape_ok(plan.tx, plan.ty) || !march2_fits(g, plan.tx) || !pr.tdone) return hipErrorInvalidValue;
     const dim3 grid(plan.blocks), block(plan.tx * (plan.ty + 2));
-    const bool pery = g.bc_lo[1] == LBW_BC_PERIODIC;
-    if (plan.tx == 96 && pery)
-        hipLaunchKernelGGL((step_march2_kernel<96, 6, true>), grid, block, 0, st, g, pr, plan, fin, fout);
-    else if (plan.tx == 96)
-        hipLaunchKernelGGL((step_march2_kernel<96, 6, false>), grid, block, 0, st, g, pr, plan, fin, fout);
-    else if (pery)
-        hipLaunchKernelGGL((step_march2_kernel<128, 4, true>), grid, block, 0, st, g, pr, plan, fin, fout);
+    const bool pery = g.bc_lo[1] == LBW_BC_PERIODIC, perz = g.bc_lo[2] == LBW_BC_PERIODIC;
+    if (plan.tx == 96)
+        launch2_of<96, 6>(pery, perz, grid, block, st, g, pr, plan, fin, fout);
     else
-        hipLaunchKernelGGL((step_march2_kernel<128, 4, false>), grid, block, 0, st, g, pr, plan, fin, fout);
+        launch2_of<128, 4>(pery, perz, grid, block, st, g, pr, plan, fin, fout);
     return hipGetLastError();
 }
 
