@@ -643,7 +643,19 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t err = hipEventCreate(&e0);
     if (err == hipSuccess) err = hipEventCreate(&e1);
-    lbw::ProbeArgs pr{nullptr, 0, nullptr, 0, s->d_scratch_count};
+    // Candidates are timed with the state's own probes recorded into a
+    // scratch trace (the two-step kernel records its probes inside the tiles
+    // that hold them, which is part of its cost); the timing step counter
+    // restarts at 0 for each candidate, so every timed launch records.
+    const int64_t trows = 2 * (int64_t)reps + 8;  // rows of a candidate's reps + 3 launches, two steps each
+    double* ptrace = nullptr;
+    if (err == hipSuccess && s->n_probes > 0)
+        err = hipMalloc((void**)&ptrace, sizeof(double) * (size_t)trows * (size_t)s->n_probes);
+    const int np = ptrace ? s->n_probes : 0;
+    lbw::ProbeArgs pr{np ? s->d_probes : nullptr, np, ptrace, np ? trows : 0, s->d_scratch_count};
+    auto restart = [&]() {
+        if (err == hipSuccess) err = hipMemsetAsync(s->d_scratch_count, 0, sizeof(int64_t), s->stream);
+    };
     const lbw::MarchPlan keep = g->plan;
     lbw::MarchPlan best = keep;
     float best_ms = 1e30f;
@@ -664,6 +676,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
                     for (int r = 0; r < count && err == hipSuccess; ++r, w ^= 1)
                         err = lbw::launch_step_march(g->dev, pr, p, bufs[w], bufs[w ^ 1], s->stream);
                 };
+                restart();
                 if (err == hipSuccess) err = lbw::launch_step_march(g->dev, pr, p, s->f[s->cur], other, s->stream);
                 run(2);
                 if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
@@ -685,7 +698,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     // and its own completion counter
     lbw::MarchPlan best2{};
     float best2_ms = 1e30f;  // per 2 reps steps
-    const lbw::ProbeArgs pr2{nullptr, 0, nullptr, 0, s->d_scratch_count, s->d_done + 1};
+    const lbw::ProbeArgs pr2{pr.nodes, pr.n, pr.trace, pr.t_max, s->d_scratch_count, s->d_done + 1};
     for (int tx : {96, 128}) {
         const int ty = tx == 96 ? 6 : 4;
         if (err != hipSuccess || !lbw::march2_fits(g->dev, tx)) continue;
@@ -711,6 +724,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
                     for (int r = 0; r < count && err == hipSuccess; ++r, w ^= 1)
                         err = lbw::launch_step_march2(g->dev, pr2, p, bufs[w], bufs[w ^ 1], s->stream);
                 };
+                restart();
                 if (err == hipSuccess) err = lbw::launch_step_march2(g->dev, pr2, p, s->f[s->cur], other, s->stream);
                 run(2);
                 if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
@@ -738,6 +752,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
             for (int r = 0; r < count && err == hipSuccess; ++r, w ^= 1)
                 err = lbw::launch_step_march(g->dev, pr, p, bufs[w], bufs[w ^ 1], s->stream);
         };
+        restart();
         if (err == hipSuccess) err = lbw::launch_step_march(g->dev, pr, p, s->f[s->cur], other, s->stream);
         run(2);
         if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
@@ -755,6 +770,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s->stream);
     (void)hipFree(tmp);
+    if (ptrace) (void)hipFree(ptrace);
     g->plan = err == hipSuccess ? best : keep;
     const bool two = err == hipSuccess && best2_ms < 2.f * best_ms;
     g->use2 = two;

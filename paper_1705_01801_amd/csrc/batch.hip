@@ -24,6 +24,7 @@ struct lbw_batch {
     int tx = 32, lz = 16, blocks = 8;
     int section_nt = 0;  // > 0: whole-row tiles of this many threads (tx unused)
     bool nts = false;    // non-temporal population stores (default: the buffers exceed the Infinity Cache)
+    bool pery = false;   // every geometry periodic along axis 1 (the step variant without its wall rules)
     int64_t tiles = 0;
     int plan_version = 0;
     float* f[2] = {nullptr, nullptr};
@@ -174,7 +175,7 @@ hipError_t launch_batch(lbw_batch* b, lbw::BatchProbeArgs bp, const float* fin, 
         if (e != hipSuccess) return e;
     }
     return lbw::launch_step_batch(b->d_items, b->d_tile_item, b->n, b->tiles, b->tx, b->section_nt, b->blocks, b->nts,
-                                  bp, fin, fout, st);
+                                  b->pery, bp, fin, fout, st);
 }
 
 hipError_t build_graph(lbw_batch* b, int from) {
@@ -382,6 +383,9 @@ int lbw_batch_make(const lbw_geometry_desc* descs, int n, const double* p0, floa
     b->f[0] = f_a;
     b->f[1] = f_b;
     b->nts = 2.0 * 28.0 * (double)b->node_off[n] > 256.0 * 1024.0 * 1024.0;
+    b->pery = true;
+    for (int h = 0; h < n; ++h)
+        if (b->d[h].bc_lo[1] != LBW_BC_PERIODIC || b->d[h].bc_hi[1] != LBW_BC_PERIODIC) b->pery = false;
     b->t_max = b->P > 0 ? t_max : 0;
     b->trace = trace;
     b->items.resize(n);

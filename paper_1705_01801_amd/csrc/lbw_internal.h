@@ -171,10 +171,11 @@ int batch_section_blocks_per_cu(int nt);
 // section_nt > 0 selects whole-row tiles of section_nt threads (the tile
 // list must then hold ntx = 1 and nty = ceil(n1 / rty) tiles per chunk).
 // tile_item: the geometry of each of the tiles_total tiles (device); nts:
-// non-temporal population stores.
+// non-temporal population stores; pery: every geometry of the batch is
+// periodic along axis 1 (the variant without that axis's wall rules).
 hipError_t launch_step_batch(const BatchItem* items, const int32_t* tile_item, int n_items, int64_t tiles_total,
-                             int tx, int section_nt, int blocks, bool nts, const BatchProbeArgs& bp, const float* fin,
-                             float* fout, hipStream_t st);
+                             int tx, int section_nt, int blocks, bool nts, bool pery, const BatchProbeArgs& bp,
+                             const float* fin, float* fout, hipStream_t st);
 
 // One driven node (Sec. IV.A/IV.C sources): its populations sit at
 // f[f_off + l N], l < q; the time is counters[counter].  kind 0 imposes a

@@ -109,7 +109,9 @@ __device__ void probe_block(const GeomDev& g, const ProbeArgs& pr, const float* 
 // ring), before any use, as if imposed in memory before the step.  NTS:
 // population stores non-temporal; NTL: the own column's loads too (its
 // planes are read once per pass; the ring's are read again by neighbours).
-template <int TX, int NT, bool ROW, bool RT = false, bool NTS = false, bool SRC = false, bool NTL = false>
+// PERY: axis 1 is periodic (its wall rules compiled out).
+template <int TX, int NT, bool ROW, bool RT = false, bool NTS = false, bool SRC = false, bool NTL = false,
+          bool PERY = false>
 __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const float* __restrict__ fin,
                                            float* __restrict__ fout, float (&sS)[2][lds_s<TX, NT, RT>()],
                                            float4 (&sElo)[3][TX + 3], float4 (&sEhi)[3][TX + 3]) {
@@ -148,6 +150,16 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
         const int jx_m = link_coord(x, -1, n0, g.bc_lo[0], g.bc_hi[0], &wx_m);
         const int jy_p = link_coord(y, +1, n1, g.bc_lo[1], g.bc_hi[1], &wy_p);
         const int jy_m = link_coord(y, -1, n1, g.bc_lo[1], g.bc_hi[1], &wy_m);
+        // byte offsets to the axis-1 neighbours' columns (used where the link exists)
+        const uint32_t dyp4 = (uint32_t)((jy_p - y) * n0) * 4u, dym4 = (uint32_t)((jy_m - y) * n0) * 4u;
+        // a wall code matters only where the link is missing, and there it
+        // is that end's code: the wall rules take the ends' codes (uniform,
+        // tested on the scalar unit)
+        const int bcx_lo = g.bc_lo[0], bcx_hi = g.bc_hi[0], bcy_lo = g.bc_lo[1], bcy_hi = g.bc_hi[1];
+        (void)wx_p;
+        (void)wx_m;
+        (void)wy_p;
+        (void)wy_m;
 
         // ring node of this thread: LDS position and wrapped column, or -1
         int ring_lds = -1;
@@ -294,14 +306,14 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
             Links k;
             k.jx_p = jx_p;
             k.jx_m = jx_m;
-            k.jy_p = jy_p;
-            k.jy_m = jy_m;
+            k.jy_p = PERY ? 0 : jy_p;  // (collide() uses only their presence)
+            k.jy_m = PERY ? 0 : jy_m;
             k.jz_p = jz_p;
             k.jz_m = jz_m;
-            k.wx_p = wx_p;
-            k.wx_m = wx_m;
-            k.wy_p = wy_p;
-            k.wy_m = wy_m;
+            k.wx_p = bcx_hi;
+            k.wx_m = bcx_lo;
+            k.wy_p = bcy_hi;
+            k.wy_m = bcy_lo;
             k.wz_p = wz_p;
             k.wz_m = wz_m;
             float fs[7];
@@ -316,12 +328,12 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
                                 : jx_p >= 0 ? 1u * N4 + nb + (uint32_t)(jx_p - x) * 4u : 2u * N4 + nb;
             const uint32_t o2 = row_tile ? 2u * N4 + nb
                                 : jx_m >= 0 ? 2u * N4 + nb + (uint32_t)(jx_m - x) * 4u : 1u * N4 + nb;
-            const uint32_t o3 = jy_p >= 0 ? 3u * N4 + nb + (uint32_t)((jy_p - y) * n0) * 4u : 4u * N4 + nb;
-            const uint32_t o4 = jy_m >= 0 ? 4u * N4 + nb + (uint32_t)((jy_m - y) * n0) * 4u : 3u * N4 + nb;
+            const uint32_t o3 = k.jy_p >= 0 ? 3u * N4 + nb + dyp4 : 4u * N4 + nb;
+            const uint32_t o4 = k.jy_m >= 0 ? 4u * N4 + nb + dym4 : 3u * N4 + nb;
             const uint32_t o5 = jz_p >= 0 ? 5u * N4 + col4 + (uint32_t)jz_p * plane4 : 6u * N4 + nb;
             const uint32_t o6 = jz_m >= 0 ? 6u * N4 + col4 + (uint32_t)jz_m * plane4 : 5u * N4 + nb;
-            float v1 = jx_p >= 0 ? fs[1] : bounce(wx_p, damp, fs[1], fs[2]);
-            float v2 = jx_m >= 0 ? fs[2] : bounce(wx_m, damp, fs[2], fs[1]);
+            float v1 = jx_p >= 0 ? fs[1] : bounce(bcx_hi, damp, fs[1], fs[2]);
+            float v2 = jx_m >= 0 ? fs[2] : bounce(bcx_lo, damp, fs[2], fs[1]);
             if constexpr (ROW) {
                 // whole-row tile: population 1 of this node comes from the
                 // lane on the left (or the wall at x = 0), population 2 from
@@ -351,8 +363,8 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
                 v1 = row_tile ? in1 : v1;
                 v2 = row_tile ? in2 : v2;
             }
-            const float v3 = jy_p >= 0 ? fs[3] : bounce(wy_p, damp, fs[3], fs[4]);
-            const float v4 = jy_m >= 0 ? fs[4] : bounce(wy_m, damp, fs[4], fs[3]);
+            const float v3 = k.jy_p >= 0 ? fs[3] : bounce(bcy_hi, damp, fs[3], fs[4]);
+            const float v4 = k.jy_m >= 0 ? fs[4] : bounce(bcy_lo, damp, fs[4], fs[3]);
             const float v5 = jz_p >= 0 ? fs[5] : bounce(wz_p, damp, fs[5], fs[6]);
             const float v6 = jz_m >= 0 ? fs[6] : bounce(wz_m, damp, fs[6], fs[5]);
             bstp<NTS>(rout, active ? o0 : kOff, fs[0]);
@@ -389,7 +401,7 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
     }
 }
 
-template <int TX, int NT, bool ROW, bool NTS>
+template <int TX, int NT, bool ROW, bool NTS, bool PERY>
 __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr, MarchPlan plan,
                                                               const float* __restrict__ fin,
                                                               float* __restrict__ fout) {
@@ -422,7 +434,7 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
     const int t_begin = (int)(plan.tiles * xcd / kXcds);
     const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
     for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
-        march_tile<TX, NT, ROW, false, NTS, false, NTS>(tg, tile, fin, fout, sS, sElo, sEhi);
+        march_tile<TX, NT, ROW, false, NTS, false, NTS, PERY>(tg, tile, fin, fout, sS, sElo, sEhi);
 }
 
 // Batch of geometries advanced by one launch: tiles of all geometries form
@@ -433,7 +445,7 @@ __global__ __launch_bounds__(NT) void step_march_kernel(GeomDev g, ProbeArgs pr,
 // tile n0 x rty, rty rows chosen per geometry by the host; the whole
 // cross-section when it fits), for geometries whose rows a TX-wide tile
 // would split or leave mostly idle; TX = NT then only sizes the LDS arrays.
-template <int TX, int NT, bool SECTION, bool NTS>
+template <int TX, int NT, bool SECTION, bool NTS, bool PERY>
 __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restrict__ items,
                                                          const int32_t* __restrict__ tile_item, int n_items,
                                                          int64_t tiles_total, BatchProbeArgs bp,
@@ -509,7 +521,7 @@ __global__ __launch_bounds__(NT) void step_batch_kernel(const BatchItem* __restr
         tg.src_zlo = it.src_zlo;
         tg.src_zhi = it.src_zhi;
         tg.src_t = t_now[h];
-        march_tile<TX, NT, true, SECTION, NTS, true>(tg, (int)(tile - it.tile_begin), fin + it.f_off,
+        march_tile<TX, NT, true, SECTION, NTS, true, false, PERY>(tg, (int)(tile - it.tile_begin), fin + it.f_off,
                                                      fout + it.f_off, sS, sElo, sEhi);
     }
 }
@@ -534,8 +546,16 @@ namespace {
 template <int TX, int NT>
 int blocks_per_cu_of() {
     int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<TX, NT, false, false>, NT, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_march_kernel<TX, NT, false, false, false>, NT, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
+}
+template <int TX, int NT, bool ROW, bool NTS>
+void launch_pery(bool pery, dim3 grid, dim3 block, hipStream_t st, const GeomDev& g, const ProbeArgs& pr,
+                 const MarchPlan& plan, const float* fin, float* fout) {
+    if (pery)
+        hipLaunchKernelGGL((step_march_kernel<TX, NT, ROW, NTS, true>), grid, block, 0, st, g, pr, plan, fin, fout);
+    else
+        hipLaunchKernelGGL((step_march_kernel<TX, NT, ROW, NTS, false>), grid, block, 0, st, g, pr, plan, fin, fout);
 }
 template <int TX, int NT>
 void launch_of(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, const float* fin, float* fout,
@@ -543,15 +563,16 @@ void launch_of(const GeomDev& g, const ProbeArgs& pr, const MarchPlan& plan, con
     // whole walled rows fit one tile: the variant with the axis-0 lane shift;
     // non-temporal stores as the plan says
     const bool row = g.n0 <= TX && g.bc_lo[0] != LBW_BC_PERIODIC;
+    const bool pery = g.bc_lo[1] == LBW_BC_PERIODIC;
     const dim3 grid(plan.blocks), block(NT);
     if (row && plan.nts)
-        hipLaunchKernelGGL((step_march_kernel<TX, NT, true, true>), grid, block, 0, st, g, pr, plan, fin, fout);
+        launch_pery<TX, NT, true, true>(pery, grid, block, st, g, pr, plan, fin, fout);
     else if (row)
-        hipLaunchKernelGGL((step_march_kernel<TX, NT, true, false>), grid, block, 0, st, g, pr, plan, fin, fout);
+        launch_pery<TX, NT, true, false>(pery, grid, block, st, g, pr, plan, fin, fout);
     else if (plan.nts)
-        hipLaunchKernelGGL((step_march_kernel<TX, NT, false, true>), grid, block, 0, st, g, pr, plan, fin, fout);
+        launch_pery<TX, NT, false, true>(pery, grid, block, st, g, pr, plan, fin, fout);
     else
-        hipLaunchKernelGGL((step_march_kernel<TX, NT, false, false>), grid, block, 0, st, g, pr, plan, fin, fout);
+        launch_pery<TX, NT, false, false>(pery, grid, block, st, g, pr, plan, fin, fout);
 }
 }  // namespace
 
@@ -591,11 +612,11 @@ hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchP
 int batch_blocks_per_cu(int tx) {
     int nb = 0;
     hipError_t e =
-        tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<16, kBatchThreads, false, false>,
+        tx == 16   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<16, kBatchThreads, false, false, false>,
                                                                   kBatchThreads, 0)
-        : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32, kBatchThreads, false, false>,
+        : tx == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<32, kBatchThreads, false, false, false>,
                                                                   kBatchThreads, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64, kBatchThreads, false, false>,
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<64, kBatchThreads, false, false, false>,
                                                                   kBatchThreads, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
@@ -609,46 +630,50 @@ int batch_row_tile(int n0, int n1, int nt) {
 int batch_section_blocks_per_cu(int nt) {
     int nb = 0;
     hipError_t e =
-        nt == 128   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<128, 128, true, false>, 128, 0)
-        : nt == 256 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<256, 256, true, false>, 256, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<512, 512, true, false>, 512, 0);
+        nt == 128   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<128, 128, true, false, false>, 128, 0)
+        : nt == 256 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<256, 256, true, false, false>, 256, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_batch_kernel<512, 512, true, false, false>, 512, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 namespace {
-template <bool NTS>
+template <bool NTS, bool PERY>
 void launch_batch_of(const BatchItem* items, const int32_t* tile_item, int n_items, int64_t tiles_total, int tx,
                      int section_nt, int blocks, const BatchProbeArgs& bp, const float* fin, float* fout,
                      hipStream_t st) {
     const dim3 grid(blocks);
     if (section_nt == 128)
-        hipLaunchKernelGGL((step_batch_kernel<128, 128, true, NTS>), grid, dim3(128), 0, st, items, tile_item, n_items,
+        hipLaunchKernelGGL((step_batch_kernel<128, 128, true, NTS, PERY>), grid, dim3(128), 0, st, items, tile_item, n_items,
                            tiles_total, bp, fin, fout);
     else if (section_nt == 256)
-        hipLaunchKernelGGL((step_batch_kernel<256, 256, true, NTS>), grid, dim3(256), 0, st, items, tile_item, n_items,
+        hipLaunchKernelGGL((step_batch_kernel<256, 256, true, NTS, PERY>), grid, dim3(256), 0, st, items, tile_item, n_items,
                            tiles_total, bp, fin, fout);
     else if (section_nt == 512)
-        hipLaunchKernelGGL((step_batch_kernel<512, 512, true, NTS>), grid, dim3(512), 0, st, items, tile_item, n_items,
+        hipLaunchKernelGGL((step_batch_kernel<512, 512, true, NTS, PERY>), grid, dim3(512), 0, st, items, tile_item, n_items,
                            tiles_total, bp, fin, fout);
     else if (tx == 16)
-        hipLaunchKernelGGL((step_batch_kernel<16, kBatchThreads, false, NTS>), grid, dim3(kBatchThreads), 0, st, items,
+        hipLaunchKernelGGL((step_batch_kernel<16, kBatchThreads, false, NTS, PERY>), grid, dim3(kBatchThreads), 0, st, items,
                            tile_item, n_items, tiles_total, bp, fin, fout);
     else if (tx == 32)
-        hipLaunchKernelGGL((step_batch_kernel<32, kBatchThreads, false, NTS>), grid, dim3(kBatchThreads), 0, st, items,
+        hipLaunchKernelGGL((step_batch_kernel<32, kBatchThreads, false, NTS, PERY>), grid, dim3(kBatchThreads), 0, st, items,
                            tile_item, n_items, tiles_total, bp, fin, fout);
     else
-        hipLaunchKernelGGL((step_batch_kernel<64, kBatchThreads, false, NTS>), grid, dim3(kBatchThreads), 0, st, items,
+        hipLaunchKernelGGL((step_batch_kernel<64, kBatchThreads, false, NTS, PERY>), grid, dim3(kBatchThreads), 0, st, items,
                            tile_item, n_items, tiles_total, bp, fin, fout);
 }
 }  // namespace
 
 hipError_t launch_step_batch(const BatchItem* items, const int32_t* tile_item, int n_items, int64_t tiles_total,
-                             int tx, int section_nt, int blocks, bool nts, const BatchProbeArgs& bp, const float* fin,
-                             float* fout, hipStream_t st) {
-    if (nts)
-        launch_batch_of<true>(items, tile_item, n_items, tiles_total, tx, section_nt, blocks, bp, fin, fout, st);
+                             int tx, int section_nt, int blocks, bool nts, bool pery, const BatchProbeArgs& bp,
+                             const float* fin, float* fout, hipStream_t st) {
+    if (nts && pery)
+        launch_batch_of<true, true>(items, tile_item, n_items, tiles_total, tx, section_nt, blocks, bp, fin, fout, st);
+    else if (nts)
+        launch_batch_of<true, false>(items, tile_item, n_items, tiles_total, tx, section_nt, blocks, bp, fin, fout, st);
+    else if (pery)
+        launch_batch_of<false, true>(items, tile_item, n_items, tiles_total, tx, section_nt, blocks, bp, fin, fout, st);
     else
-        launch_batch_of<false>(items, tile_item, n_items, tiles_total, tx, section_nt, blocks, bp, fin, fout, st);
+        launch_batch_of<false, false>(items, tile_item, n_items, tiles_total, tx, section_nt, blocks, bp, fin, fout, st);
     return hipGetLastError();
 }
 

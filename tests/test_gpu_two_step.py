@@ -55,6 +55,10 @@ CASES = {
                       bc_hi=("bounceback", "periodic", "periodic"), qmax=(1.0, 2 * math.pi, 0.1)),
     # one plane along axis 2, walled
     "cyl_flat": dict(W.closed_cylinder(scale=1), n=(20, 9, 1), qmax=(1.0, 2 * math.pi, 0.05)),
+    # axis 1 walled, axis 2 periodic (the kernel variant with only the axis-2 wall rules compiled out)
+    "box_walls_zper": dict(kind="box", dim=3, n=(41, 11, 23), qmin=(0, 0, 0), qmax=(41.0, 9.9, 27.6),
+                           bc_lo=("free", "fixed", "periodic"), bc_hi=("bounceback", "free", "periodic"),
+                           h_ref=1.0, c=0.33, damp=0.85, params=()),
 }
 
 
