@@ -177,14 +177,16 @@ int lbw_get_step_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z
  * arithmetic is the one-step kernel's, so results are identical bit for bit.
  * A workgroup owns tile_y whole axis-0 rows plus a halo row either side
  * (tile_x = 96 with tile_y = 6, or 128 with 4; 768 threads), chunk_z planes
- * along axis 2; blocks as in lbw_set_step_config (0 = one wave).  Needs a
+ * along axis 2, or with chunk_z = 0 an equal share of all (row tile, plane)
+ * pairs per workgroup (no workgroup marches two whole chunks while another
+ * idles); blocks as in lbw_set_step_config (0 = one wave).  Needs a
  * 3-D built-in geometry with n0 <= tile_x and a walled axis 0.
  * lbw_step_n then runs pairs of steps this way (an odd last step, and
  * states with driven sources or with more than 16 probes in one tile of
  * the pass, use one-step launches).  tile_x = 0 turns it off;
  * lbw_set_step_config also turns it off; lbw_autotune turns it on when
  * its best shape is faster per step.  Errors: LBW_EINVAL (other shapes, a
- * geometry it does not fit, chunk_z < 1, blocks < 0). */
+ * geometry it does not fit, chunk_z < 0, blocks < 0). */
 int lbw_set_step2_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, int blocks);
 /* The two-step shape in use (tile_x = 0 and the rest 0 when off). */
 int lbw_get_step2_config(lbw_geometry_t g, int* tile_x, int* tile_y, int* chunk_z, int* blocks);
@@ -226,7 +228,8 @@ int lbw_step_n(lbw_state_t s, int64_t n);
  * (non-temporal population stores, the default where the two population
  * buffers exceed the 256 MiB Infinity Cache, or cached ones).  Two-step
  * launches (lbw_set_step2_config: tiles 96 x 6 and
- * 128 x 4 where the geometry fits them, chunk_z 8 to 64, one and two waves)
+ * 128 x 4 where the geometry fits them, chunk_z 0 (balanced) and 8 to 64,
+ * one and two waves)
  * are timed per step as well, and used when faster.  The choice is stored in
  * the geometry and in a per-process
  * cache keyed by the grid shape, which later geometries of that shape start

@@ -433,7 +433,7 @@ int lbw_set_step2_config(lbw_geometry_t g, int tile_x, int tile_y, int chunk_z, 
     if (!lbw::march2_fits(g->dev, tile_x))
         return fail(LBW_EINVAL, "two-step tile of %d lanes: needs n0 <= %d (n0 = %d) and a walled axis 0", tile_x,
                     tile_x, g->dev.n0);
-    if (chunk_z < 1 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 1 and blocks >= 0");
+    if (chunk_z < 0 || blocks < 0) return fail(LBW_EINVAL, "chunk_z must be >= 0 (0: balanced) and blocks >= 0");
     if (blocks == 0) {
         int cus = 0;
         if (lbw::device_cus(&cus) != LBW_OK) return LBW_EDEVICE;
@@ -531,9 +531,24 @@ bool two_step_ok(const lbw_state* s) {
     if (s->n_probes == 0 || s->t >= s->t_max) return true;
     std::map<int64_t, int> per_tile;
     const int64_t n0 = g->dev.n0, n1 = g->dev.n1;
+    const lbw::MarchPlan& p = g->plan2;
     for (int64_t node : s->probes_host) {
         const int64_t i1 = (node / n0) % n1, i2 = node / (n0 * n1);
-        const int64_t tile = i1 / g->plan2.ty + (int64_t)g->plan2.nty * (i2 / g->plan2.lz);
+        int64_t tile;
+        if (p.lz > 0) {
+            tile = i1 / p.ty + (int64_t)p.nty * (i2 / p.lz);
+        } else {
+            // balanced plan: one segment per (workgroup, row tile); the
+            // workgroup is the one whose share holds the probe's pair
+            const int64_t pair = (i1 / p.ty) * (int64_t)g->dev.n2 + i2;
+            int64_t owner = -1;
+            for (int b = 0; b < p.blocks && owner < 0; ++b) {
+                int64_t a = 0, e = 0;
+                lbw::march2_share(p.tiles, p.blocks, b, &a, &e);
+                if (pair >= a && pair < e) owner = b;
+            }
+            tile = owner * (int64_t)p.nty + i1 / p.ty;
+        }
         if (++per_tile[tile] > lbw::march2_tile_probes()) return false;
     }
     return true;
@@ -705,7 +720,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
         const int bpc = lbw::march2_blocks_per_cu(tx, ty);
         // chunk lengths: besides the plain ones, those whose tile count
         // fills whole waves of resident workgroups (tiles of equal work)
-        std::vector<int> lzs{8, 12, 16, 20, 24, 32, 40, 48, 64};
+        std::vector<int> lzs{0, 8, 12, 16, 20, 24, 32, 40, 48, 64};  // 0: balanced shares
         for (int waves = 1; waves <= 8; ++waves) {
             const int nty = (g->dev.n1 + ty - 1) / ty;
             const int64_t want = (int64_t)waves * cus * bpc;  // tiles

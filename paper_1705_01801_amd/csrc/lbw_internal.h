@@ -104,10 +104,21 @@ hipError_t launch_step_march(const GeomDev& g, const ProbeArgs& pr, const MarchP
 
 // Two time steps per launch (step_march2.hip): workgroups of tx x (ty + 2)
 // threads own ty whole axis-0 rows (n0 <= tx, axis 0 walled) over chunks of
-// lz planes; plan.ntx is 1.  Shapes: 96 x 6 and 128 x 4 (768 threads).
+// lz planes, or (lz 0) over balanced shares of all (row tile, plane) pairs;
+// plan.ntx is 1.  Shapes: 96 x 6 and 128 x 4 (768 threads).
 // The step counter advances by two per launch (needs pr.tdone); the probes
 // of both times are recorded, at most march2_tile_probes() per tile.
 bool march2_shape_ok(int tx, int ty);
+// Balanced two-step plans (lz 0): workgroup b of `blocks` (a multiple of 8)
+// takes the pairs [a, e) of the `total` (row tile, plane) pairs, row tile
+// major; the workgroups of one XCD (b mod 8) take consecutive shares of one
+// eighth of them.  Used by the kernel and by the host's probe check alike.
+__host__ __device__ inline void march2_share(int64_t total, int blocks, int b, int64_t* a, int64_t* e) {
+    const int xcd = b % 8, per = blocks / 8, k = b / 8;
+    const int64_t xs = total * xcd / 8, xe = total * (xcd + 1) / 8;
+    *a = xs + (xe - xs) * k / per;
+    *e = xs + (xe - xs) * (k + 1) / per;
+}
 bool march2_fits(const GeomDev& g, int tx);
 int march2_tile_probes();
 int march2_blocks_per_cu(int tx, int ty);

@@ -83,8 +83,8 @@ __device__ __forceinline__ bool opaque_bool(bool b) {
 // PERY, PERZ: axis 1, axis 2 is periodic (every link along it present;
 // the wall rules of that axis are compiled out).
 template <int TX, int TY, bool PERY, bool PERZ>
-__device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& pr, int64_t t, const MarchPlan& plan,
-                                            int tile, const float* __restrict__ fin, float* __restrict__ fout,
+__device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& pr, int64_t t, int ty, int z0, int z1,
+                                            const float* __restrict__ fin, float* __restrict__ fout,
                                             M2Lds<TX, TY>& L) {
     using C = M2<TX, TY>;
     constexpr int W = C::W;
@@ -93,10 +93,8 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     const uint32_t plane = (uint32_t)n0 * (uint32_t)n1;
     const float c2 = g.c2, two_w0 = g.two_w0, damp = g.damp;
     const int lx = (int)(threadIdx.x % (unsigned)TX), ly = (int)(threadIdx.x / (unsigned)TX);
-    const int ty = tile % plan.nty, chunk = tile / plan.nty;
-    const int y0 = ty * TY, z0 = chunk * plan.lz;
-    if (z0 >= n2) return;  // uniform per block
-    const int z1 = min(z0 + plan.lz, n2);
+    // row tile ty (rows ty TY ..), planes [z0, z1) with 0 <= z0 < z1 <= n2
+    const int y0 = ty * TY;
     const int hgt = min(TY, n1 - y0);
     const bool perz = g.bc_lo[2] == LBW_BC_PERIODIC, pery = PERY;
     // step A runs on march planes [za0, za1); the march runs on [za0, z1 + 2)
@@ -475,12 +473,28 @@ __global__ __launch_bounds__(TX * (TY + 2)) void step_march2_kernel(GeomDev g, P
             pr.trace[t * pr.n + p] = s / g.sqrtg[sg_index(g, node)];
         }
     }
-    const int xcd = blockIdx.x % kXcds;
-    const int per_xcd_blocks = gridDim.x / kXcds;
-    const int t_begin = (int)(plan.tiles * xcd / kXcds);
-    const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
-    for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks)
-        march2_tile<TX, TY, PERY, PERZ>(g, pr, t, plan, tile, fin, fout, L);
+    if (plan.lz > 0) {
+        // tiles of chunk_z planes, XCD-contiguous ranges of the tile list
+        const int xcd = blockIdx.x % kXcds;
+        const int per_xcd_blocks = gridDim.x / kXcds;
+        const int t_begin = (int)(plan.tiles * xcd / kXcds);
+        const int t_end = (int)(plan.tiles * (xcd + 1) / kXcds);
+        for (int tile = t_begin + (int)blockIdx.x / kXcds; tile < t_end; tile += per_xcd_blocks) {
+            const int ty = tile % plan.nty, z0 = (tile / plan.nty) * plan.lz;
+            if (z0 < g.n2) march2_tile<TX, TY, PERY, PERZ>(g, pr, t, ty, z0, min(z0 + plan.lz, g.n2), fin, fout, L);
+        }
+    } else {
+        // balanced: this workgroup's share of the (row tile, plane) pairs,
+        // marched as one segment per row tile it touches
+        int64_t a = 0, e = 0;
+        march2_share(plan.tiles, (int)gridDim.x, (int)blockIdx.x, &a, &e);
+        while (a < e) {
+            const int ty = (int)(a / g.n2), z0 = (int)(a % g.n2);
+            const int z1 = (int)min((int64_t)g.n2, (int64_t)z0 + (e - a));
+            march2_tile<TX, TY, PERY, PERZ>(g, pr, t, ty, z0, z1, fin, fout, L);
+            a += z1 - z0;
+        }
+    }
     // the last workgroup to finish advances the step counter by two (every
     // workgroup read it before counting itself done)
     __syncthreads();
@@ -524,11 +538,12 @@ MarchPlan make_march2_plan(const GeomDev& g, int tx, int ty, int lz, int blocks)
     MarchPlan p{};
     p.tx = tx;
     p.ty = ty;
-    p.lz = lz < 1 ? 1 : lz;
+    p.lz = lz < 0 ? 0 : lz;
     p.ntx = 1;
     p.nty = (g.n1 + ty - 1) / ty;
-    p.nchunks = (g.n2 + p.lz - 1) / p.lz;
-    p.tiles = (int64_t)p.nty * p.nchunks;
+    // balanced (lz 0): tiles counts the (row tile, plane) pairs shared out
+    p.nchunks = p.lz > 0 ? (g.n2 + p.lz - 1) / p.lz : 0;
+    p.tiles = p.lz > 0 ? (int64_t)p.nty * p.nchunks : (int64_t)p.nty * g.n2;
     int b = blocks < kXcds ? kXcds : blocks;
     b = (b / kXcds) * kXcds;
     const int64_t cap = ((p.tiles + kXcds - 1) / kXcds) * kXcds;

@@ -73,8 +73,10 @@ def test_two_step_bit_identical_to_one_step(name):
     say("two-step", name, geom["n"])
     ref, tr_ref, _ = run(geom, P0, probes, steps)
     n0 = geom["n"][0]
-    shapes = [(96, 6, lz, b) for lz, b in ((16, 0), (5, 8), (64, 16))] if n0 <= 96 else []
-    shapes += [(128, 4, lz, b) for lz, b in ((16, 0), (3, 8), (32, 0))]
+    # (chunk_z 0: balanced shares of the (row tile, plane) pairs, with
+    # shares that split row tiles and, at 24 workgroups, many segments)
+    shapes = [(96, 6, lz, b) for lz, b in ((16, 0), (5, 8), (64, 16), (0, 0), (0, 24))] if n0 <= 96 else []
+    shapes += [(128, 4, lz, b) for lz, b in ((16, 0), (3, 8), (32, 0), (0, 0), (0, 8))]
     for shape in shapes:
         for graph in (0, 32, 7):
             f, tr, g = run(geom, P0, probes, steps, two=shape, graph=graph)
@@ -100,7 +102,7 @@ def test_two_step_refuses_what_it_does_not_fit():
     with pytest.raises(lbw.LbwError):
         g.set_step2_config(128, 4, 16, 0)                   # rows longer than the tile
     g2 = lbw.Geometry(CASES["box_walls"])
-    for bad in [(96, 8, 16, 0), (64, 4, 16, 0), (96, 6, 0, 0), (128, 6, 16, 0)]:
+    for bad in [(96, 8, 16, 0), (64, 4, 16, 0), (96, 6, -1, 0), (128, 6, 16, 0)]:
         with pytest.raises(lbw.LbwError):
             g2.set_step2_config(*bad)
     g2.set_step2_config(96, 6, 16, 0)
