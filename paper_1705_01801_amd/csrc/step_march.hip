@@ -145,21 +145,17 @@ __device__ __forceinline__ void march_tile(const TileGeom& g, int tile, const fl
         // ROW = false compiles the shift out (grids wider than a tile)
         const bool row_tile = ROW && x0 == 0 && wdt == n0 && g.bc_lo[0] != LBW_BC_PERIODIC;
 
-        int wx_p = 0, wx_m = 0, wy_p = 0, wy_m = 0;
-        const int jx_p = link_coord(x, +1, n0, g.bc_lo[0], g.bc_hi[0], &wx_p);
-        const int jx_m = link_coord(x, -1, n0, g.bc_lo[0], g.bc_hi[0], &wx_m);
-        const int jy_p = link_coord(y, +1, n1, g.bc_lo[1], g.bc_hi[1], &wy_p);
-        const int jy_m = link_coord(y, -1, n1, g.bc_lo[1], g.bc_hi[1], &wy_m);
-        // byte offsets to the axis-1 neighbours' columns (used where the link exists)
-        const uint32_t dyp4 = (uint32_t)((jy_p - y) * n0) * 4u, dym4 = (uint32_t)((jy_m - y) * n0) * 4u;
         // a wall code matters only where the link is missing, and there it
         // is that end's code: the wall rules take the ends' codes (uniform,
-        // tested on the scalar unit)
+        // tested on the scalar unit), so link_coord's code is not kept
+        int wall_unused = 0;
+        const int jx_p = link_coord(x, +1, n0, g.bc_lo[0], g.bc_hi[0], &wall_unused);
+        const int jx_m = link_coord(x, -1, n0, g.bc_lo[0], g.bc_hi[0], &wall_unused);
+        const int jy_p = link_coord(y, +1, n1, g.bc_lo[1], g.bc_hi[1], &wall_unused);
+        const int jy_m = link_coord(y, -1, n1, g.bc_lo[1], g.bc_hi[1], &wall_unused);
         const int bcx_lo = g.bc_lo[0], bcx_hi = g.bc_hi[0], bcy_lo = g.bc_lo[1], bcy_hi = g.bc_hi[1];
-        (void)wx_p;
-        (void)wx_m;
-        (void)wy_p;
-        (void)wy_m;
+        // byte offsets to the axis-1 neighbours' columns (used where the link exists)
+        const uint32_t dyp4 = (uint32_t)((jy_p - y) * n0) * 4u, dym4 = (uint32_t)((jy_m - y) * n0) * 4u;
 
         // ring node of this thread: LDS position and wrapped column, or -1
         int ring_lds = -1;
