@@ -57,8 +57,8 @@ struct M2Lds {
     float S[2][M2<TX, TY>::SROWS * M2<TX, TY>::W + 1];     // + a sink slot
     float X[4][M2<TX, TY>::XROWS * M2<TX, TY>::W + 1];
     float S1[2][M2<TX, TY>::S1ROWS * M2<TX, TY>::W + 1];
-    float4 Elo[8][M2<TX, TY>::W + 1];                      // coefficient rows, slot = plane & 7
-    float4 Ehi[8][M2<TX, TY>::W + 1];
+    float4 Elo[6][M2<TX, TY>::W + 1];                      // coefficient rows, slot = (plane - za0) mod 6
+    float4 Ehi[6][M2<TX, TY>::W + 1];
     float B[2][2][TY * TX + 1];                            // step B: +-e0 populations along the row (2 planes)
     int pnode[kTileProbes], px[kTileProbes], py[kTileProbes], pz[kTileProbes];
     int pcount;
@@ -178,10 +178,10 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         lo = bld4(rtab, off);
         hi = bld4(rtab, on ? off + 16u : kOff);
     };
-    auto stage_erow = [&](int z, const float4& lo, const float4& hi) {
+    auto stage_erow = [&](int slot, const float4& lo, const float4& hi) {
         if (erow_on) {
-            L.Elo[z & 7][threadIdx.x + 1] = lo;
-            L.Ehi[z & 7][threadIdx.x + 1] = hi;
+            L.Elo[slot][threadIdx.x + 1] = lo;
+            L.Ehi[slot][threadIdx.x + 1] = hi;
         }
     };
 
@@ -226,9 +226,9 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         erow_r(rplane(za0 + 1), a2, b2);
         Sm = sum7(tmp);
         Sc = sum7(fA);
-        stage_erow(za0 - 1, a0, b0);
-        stage_erow(za0, a1, b1);
-        stage_erow(za0 + 1, a2, b2);
+        stage_erow(5, a0, b0);  // plane za0 - 1
+        stage_erow(0, a1, b1);
+        stage_erow(1, a2, b2);
         L.S[0][actA ? my_s : sinkS] = Sc;
         L.S[0][ring_s] = sum7(rA);
     }
@@ -283,8 +283,9 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     // order (period three), so no register is copied.
     auto march_plane = [&](float (&f0)[7], float (&f1)[7], float (&f2)[7], float (&fc)[7], float (&fnx)[7],
                            float (&fnn)[7], float (&rc)[7], float (&rn)[7], float (&rnn)[7], float4 (&en)[2],
-                           float4 (&e3)[2], int z) {
-        const int sb = (z - za0) & 1;
+                           float4 (&e3)[2], int z, auto kc) {
+        constexpr int K = decltype(kc)::value;  // z - za0 modulo 6 (the loop runs six planes per turn)
+        const int sb = K & 1;
         const bool doA = z < za1;
         const int zr = zrr;
         Links kp = kl, krp = kr;
@@ -325,10 +326,10 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             zlinks(zr, k);
             if constexpr (PERZ) k.jz_p = k.jz_m = 0;  // (step A uses only their presence)
             const float* Ls = L.S[sb];
-            const float4 e_lo = L.Elo[z & 7][lx + 1], e_hi = L.Ehi[z & 7][lx + 1];
-            const float4 enp = L.Elo[z & 7][lx + 2], enm = L.Elo[z & 7][lx];
-            const float4 ezp = L.Elo[(z + 1) & 7][lx + 1];
-            const float4 ezm = L.Elo[(z - 1) & 7][lx + 1];
+            const float4 e_lo = L.Elo[K % 6][lx + 1], e_hi = L.Ehi[K % 6][lx + 1];
+            const float4 enp = L.Elo[K % 6][lx + 2], enm = L.Elo[K % 6][lx];
+            const float4 ezp = L.Elo[(K + 1) % 6][lx + 1];
+            const float4 ezm = L.Elo[(K + 5) % 6][lx + 1];
             float fs[7];
             collide(fc, Sc, e_lo, e_hi, enp, enm, ezp, make_float2(ezm.y, ezm.z), Ls[my_s + 1], Ls[my_s - 1],
                     Ls[my_s + W], Ls[my_s - W], Sp, Sm, k, c2, two_w0, fs);
@@ -365,7 +366,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         // plane z-1 is complete: its S(t+1) for step B's neighbours
         if (z - 1 >= za0 && z - 1 < za1) {
             S1c = sum7(f1);
-            L.S1[(z - 1) & 1][actA ? ly * W + lx + 1 : C::S1ROWS * W] = S1c;
+            L.S1[(K + 1) & 1][actA ? ly * W + lx + 1 : C::S1ROWS * W] = S1c;  // plane z - 1
         }
 
         // step B on plane zb = z - 2
@@ -376,13 +377,13 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             zlinks(zbr, k);
             const int jzp = k.jz_p, jzm = k.jz_m;  // the stores' planes
             if constexpr (PERZ) k.jz_p = k.jz_m = 0;
-            const float* L1 = L.S1[zb & 1];
+            const float* L1 = L.S1[K & 1];  // plane z - 2
             // (threads off the tile's rows read row 1 instead: every index stays in the array)
             const int s1 = (actB ? ly : 1) * W + lx + 1;
-            const float4 e_lo = L.Elo[zb & 7][lx + 1], e_hi = L.Ehi[zb & 7][lx + 1];
-            const float4 enp = L.Elo[zb & 7][lx + 2], enm = L.Elo[zb & 7][lx];
-            const float4 ezp = L.Elo[(zb + 1) & 7][lx + 1];
-            const float4 ezm = L.Elo[(zb - 1) & 7][lx + 1];
+            const float4 e_lo = L.Elo[(K + 4) % 6][lx + 1], e_hi = L.Ehi[(K + 4) % 6][lx + 1];
+            const float4 enp = L.Elo[(K + 4) % 6][lx + 2], enm = L.Elo[(K + 4) % 6][lx];
+            const float4 ezp = L.Elo[(K + 5) % 6][lx + 1];
+            const float4 ezm = L.Elo[(K + 3) % 6][lx + 1];
             float fs[7];
             collide(f0, S1b, e_lo, e_hi, enp, enm, ezp, make_float2(ezm.y, ezm.z), L1[s1 + 1], L1[s1 - 1],
                     L1[s1 + W], L1[s1 - W], S1c, S1a, k, c2, two_w0, fs);
@@ -399,7 +400,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
             // push: +-e0 along the row through LDS, stored after the next
             // barrier (aligned stores); the rest to their destinations (or the
             // wall rules) now
-            pend_slot = zb & 1;
+            pend_slot = K & 1;
             L.B[pend_slot][0][actB ? bo : TY * TX] = fs[1];
             L.B[pend_slot][1][actB ? bo : TY * TX] = fs[2];
             const uint32_t nb = col4 + (uint32_t)zbr * plane4;
@@ -429,7 +430,7 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
         if (z + 1 < zend) {
             L.S[sb ^ 1][actA ? my_s : sinkS] = Sp;
             L.S[sb ^ 1][ring_s] = Srp;
-            stage_erow(z + 2, en[0], en[1]);
+            stage_erow((K + 2) % 6, en[0], en[1]);
         }
         Sm = Sc;
         Sc = Sp;
@@ -440,17 +441,17 @@ __device__ __forceinline__ void march2_tile(const GeomDev& g, const ProbeArgs& p
     };
     for (int z = za0;;) {
         if (z >= zend) break;
-        march_plane(fa, fb, fz, fA, fB, fC, rA, rB, rC, eA, eB, z);
+        march_plane(fa, fb, fz, fA, fB, fC, rA, rB, rC, eA, eB, z, std::integral_constant<int, 0>{});
         if (++z >= zend) break;
-        march_plane(fb, fz, fa, fB, fC, fA, rB, rC, rA, eB, eC, z);
+        march_plane(fb, fz, fa, fB, fC, fA, rB, rC, rA, eB, eC, z, std::integral_constant<int, 1>{});
         if (++z >= zend) break;
-        march_plane(fz, fa, fb, fC, fA, fB, rC, rA, rB, eC, eA, z);
+        march_plane(fz, fa, fb, fC, fA, fB, rC, rA, rB, eC, eA, z, std::integral_constant<int, 2>{});
         if (++z >= zend) break;
-        march_plane(fa, fb, fz, fA, fB, fC, rA, rB, rC, eA, eB, z);
+        march_plane(fa, fb, fz, fA, fB, fC, rA, rB, rC, eA, eB, z, std::integral_constant<int, 3>{});
         if (++z >= zend) break;
-        march_plane(fb, fz, fa, fB, fC, fA, rB, rC, rA, eB, eC, z);
+        march_plane(fb, fz, fa, fB, fC, fA, rB, rC, rA, eB, eC, z, std::integral_constant<int, 4>{});
         if (++z >= zend) break;
-        march_plane(fz, fa, fb, fC, fA, fB, rC, rA, rB, eC, eA, z);
+        march_plane(fz, fa, fb, fC, fA, fB, rC, rA, rB, eC, eA, z, std::integral_constant<int, 5>{});
         ++z;
     }
     __syncthreads();  // the last plane's hand-over visible
