@@ -230,7 +230,10 @@ int lbw_step_n(lbw_state_t s, int64_t n);
  * launches (lbw_set_step2_config: tiles 96 x 6 and
  * 128 x 4 where the geometry fits them, chunk_z 0 (balanced) and 8 to 64,
  * one and two waves)
- * are timed per step as well, and used when faster.  The choice is stored in
+ * are timed per step as well, and used when faster.  The three fastest
+ * candidates of each kind are timed again over three times the launches
+ * before one is kept; every candidate runs with the state's probes
+ * recorded into scratch memory.  The choice is stored in
  * the geometry and in a per-process
  * cache keyed by the grid shape, which later geometries of that shape start
  * from.  Synchronises.  best_us (may be NULL) receives the best time per

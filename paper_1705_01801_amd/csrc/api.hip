@@ -662,7 +662,7 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     // scratch trace (the two-step kernel records its probes inside the tiles
     // that hold them, which is part of its cost); the timing step counter
     // restarts at 0 for each candidate, so every timed launch records.
-    const int64_t trows = 2 * (int64_t)reps + 8;  // rows of a candidate's reps + 3 launches, two steps each
+    const int64_t trows = 6 * (int64_t)reps + 8;  // rows of a candidate's 3 reps + 3 launches, two steps each
     double* ptrace = nullptr;
     if (err == hipSuccess && s->n_probes > 0)
         err = hipMalloc((void**)&ptrace, sizeof(double) * (size_t)trows * (size_t)s->n_probes);
@@ -675,6 +675,49 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
     lbw::MarchPlan best = keep;
     float best_ms = 1e30f;
     float* other = s->f[1 - s->cur];
+    // One candidate timed: a launch from the current buffer, two more, then
+    // `count` timed launches on the ping-pong pair; milliseconds for them.
+    auto time1 = [&](const lbw::MarchPlan& p, int count) -> float {
+        float* bufs[2] = {other, tmp};
+        int w = 0;
+        auto run = [&](int n) {
+            for (int r = 0; r < n && err == hipSuccess; ++r, w ^= 1)
+                err = lbw::launch_step_march(g->dev, pr, p, bufs[w], bufs[w ^ 1], s->stream);
+        };
+        restart();
+        if (err == hipSuccess) err = lbw::launch_step_march(g->dev, pr, p, s->f[s->cur], other, s->stream);
+        run(2);
+        if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
+        run(count);
+        if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    // two time steps per launch: timed per step (reps launches = 2 reps
+    // steps), on the same ping-pong buffers with the timing step counter
+    // and its own completion counter
+    const lbw::ProbeArgs pr2{pr.nodes, pr.n, pr.trace, pr.t_max, s->d_scratch_count, s->d_done + 1};
+    auto time2 = [&](const lbw::MarchPlan& p, int count) -> float {
+        float* bufs[2] = {other, tmp};
+        int w = 0;
+        auto run = [&](int n) {
+            for (int r = 0; r < n && err == hipSuccess; ++r, w ^= 1)
+                err = lbw::launch_step_march2(g->dev, pr2, p, bufs[w], bufs[w ^ 1], s->stream);
+        };
+        restart();
+        if (err == hipSuccess) err = lbw::launch_step_march2(g->dev, pr2, p, s->f[s->cur], other, s->stream);
+        run(2);
+        if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
+        run(count);
+        if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    std::vector<std::pair<float, lbw::MarchPlan>> cand1, cand2;
     for (int nt : {256, 384, 512, 768, 1024})
     for (int tx : {16, 32, 64, 96, 128}) {
         if (err != hipSuccess) break;
@@ -685,35 +728,12 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
             if (lz > 2 * g->dev.n2 && lz != 4) continue;
             for (int mult : {1, 2}) {
                 const lbw::MarchPlan p = lbw::make_march_plan(g->dev, tx, ty, lz, mult * cus * bpc);
-                float* bufs[2] = {other, tmp};
-                int w = 0;
-                auto run = [&](int count) {
-                    for (int r = 0; r < count && err == hipSuccess; ++r, w ^= 1)
-                        err = lbw::launch_step_march(g->dev, pr, p, bufs[w], bufs[w ^ 1], s->stream);
-                };
-                restart();
-                if (err == hipSuccess) err = lbw::launch_step_march(g->dev, pr, p, s->f[s->cur], other, s->stream);
-                run(2);
-                if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
-                run(reps);
-                if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
-                if (err == hipSuccess) err = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                const float ms = time1(p, reps);
                 if (err != hipSuccess) break;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = p;
-                }
+                cand1.push_back({ms, p});
             }
         }
     }
-    // two time steps per launch: timed per step (reps launches = 2 reps
-    // steps), on the same ping-pong buffers with the timing step counter
-    // and its own completion counter
-    lbw::MarchPlan best2{};
-    float best2_ms = 1e30f;  // per 2 reps steps
-    const lbw::ProbeArgs pr2{pr.nodes, pr.n, pr.trace, pr.t_max, s->d_scratch_count, s->d_done + 1};
     for (int tx : {96, 128}) {
         const int ty = tx == 96 ? 6 : 4;
         if (err != hipSuccess || !lbw::march2_fits(g->dev, tx)) continue;
@@ -733,49 +753,35 @@ int lbw_autotune(lbw_state_t s, int reps, double* best_us) {
             if (lz > 2 * g->dev.n2 && lz != 8) continue;
             for (int mult : {1, 2}) {
                 const lbw::MarchPlan p = lbw::make_march2_plan(g->dev, tx, ty, lz, mult * cus * bpc);
-                float* bufs[2] = {other, tmp};
-                int w = 0;
-                auto run = [&](int count) {
-                    for (int r = 0; r < count && err == hipSuccess; ++r, w ^= 1)
-                        err = lbw::launch_step_march2(g->dev, pr2, p, bufs[w], bufs[w ^ 1], s->stream);
-                };
-                restart();
-                if (err == hipSuccess) err = lbw::launch_step_march2(g->dev, pr2, p, s->f[s->cur], other, s->stream);
-                run(2);
-                if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
-                run(reps);
-                if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
-                if (err == hipSuccess) err = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                const float ms = time2(p, reps);
                 if (err != hipSuccess) break;
-                if (ms < best2_ms) {
-                    best2_ms = ms;
-                    best2 = p;
-                }
+                cand2.push_back({ms, p});
             }
         }
     }
+    // The fastest three of each kind timed again over three times the
+    // launches (close candidates timed once can swap places from run to
+    // run); times per reps launches.
+    auto pick = [&](std::vector<std::pair<float, lbw::MarchPlan>>& c, auto timer, lbw::MarchPlan& bp, float& bms) {
+        std::sort(c.begin(), c.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+        for (size_t i = 0; i < c.size() && i < 3 && err == hipSuccess; ++i) {
+            const float ms = timer(c[i].second, 3 * reps) / 3.f;
+            if (err == hipSuccess && ms < bms) {
+                bms = ms;
+                bp = c[i].second;
+            }
+        }
+    };
+    lbw::MarchPlan best2{};
+    float best2_ms = 1e30f;  // per 2 reps steps
+    pick(cand1, time1, best, best_ms);
+    pick(cand2, time2, best2, best2_ms);
     // the best shape with the other store policy (non-temporal stores pay on
     // grids that do not fit the caches, and cost where they do)
     if (err == hipSuccess) {
         lbw::MarchPlan p = best;
         p.nts = !p.nts;
-        float* bufs[2] = {other, tmp};
-        int w = 0;
-        auto run = [&](int count) {
-            for (int r = 0; r < count && err == hipSuccess; ++r, w ^= 1)
-                err = lbw::launch_step_march(g->dev, pr, p, bufs[w], bufs[w ^ 1], s->stream);
-        };
-        restart();
-        if (err == hipSuccess) err = lbw::launch_step_march(g->dev, pr, p, s->f[s->cur], other, s->stream);
-        run(2);
-        if (err == hipSuccess) err = hipEventRecord(e0, s->stream);
-        run(reps);
-        if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        const float ms = time1(p, 3 * reps) / 3.f;
         if (err == hipSuccess && ms < best_ms) {
             best_ms = ms;
             best = p;
